@@ -1,0 +1,231 @@
+/*
+ * gcr.h - C ABI of the GCR / GCRV re-ranking library for AMD MI355X (gfx950).
+ *
+ * Graph Convolution based Re-ranking updates retrieval features by parameter-
+ * free graph convolution over a k-nearest-neighbour graph of the query and
+ * gallery features, then ranks by distance between the updated features
+ * (Sec. III-A, Eq. (2)-(3)).  This library runs every step on the GPU:
+ *   gcr_normalize_rows  row L2 normalisation (input preparation)
+ *   gcr_knn             all-pairs similarity + per-row k nearest neighbours
+ *                       (Eq. (4) neighbour sets; Eq. (8) cross-camera sets)
+ *   gcr_build_graph     kNN + exp affinities + symmetrisation + degrees
+ *                       (Eq. (4)-(8))
+ *   gcr_propagate       one synchronous propagation round (Eq. (2) / (9))
+ *                       followed by row re-normalisation
+ *   gcr_final_distances squared distances between query and gallery rows of
+ *                       the updated features, dense or top-K per query
+ *   gcr_rerank          the whole pipeline: T rounds (Eq. (3)), the graph
+ *                       rebuilt from the current features before each round
+ *                       (Sec. III-C) or fixed, then final distances
+ *   gcr_profile_vectors tracklet profile vectors for video (Eq. (10), (16);
+ *                       Alg. 2 step 1)
+ *
+ * Conventions
+ *   Memory: every array argument is a DEVICE pointer owned by the caller,
+ *     contiguous and row-major, unless stated otherwise.  The library owns
+ *     only the workspace inside a gcr_ctx, which grows on demand (a call that
+ *     needs a larger workspace than any earlier call allocates it, so the
+ *     first call at a new size is not capture-safe).
+ *   Streams: `stream` is a hipStream_t passed as void*; NULL means the
+ *     default stream.  Calls enqueue work on that stream and return without
+ *     synchronising, except where a function says it synchronises.
+ *   Errors: functions return gcr_status; a negative value is an error and
+ *     gcr_last_error(ctx) returns its message.  Nothing throws across the ABI.
+ *     Argument checks happen on the host before anything is enqueued.
+ *   Threads: a gcr_ctx must be used by one host thread at a time.
+ *   Neighbour lists: row i lists its k nearest other rows j != i, ordered by
+ *     (squared distance, j) ascending; rows with fewer than k eligible
+ *     neighbours are padded with index -1 and distance +inf.
+ */
+#ifndef GCR_H
+#define GCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GCR_OK = 0,
+  GCR_ERR_INVALID = -1,     /* bad argument (shape, NULL, range)            */
+  GCR_ERR_NOMEM = -2,       /* device allocation failed                     */
+  GCR_ERR_HIP = -3,         /* a HIP runtime call failed                    */
+  GCR_ERR_UNSUPPORTED = -4  /* valid but not supported by this build        */
+} gcr_status;
+
+/* Precision of the similarity screening.  Every mode re-scores the screened
+ * candidates exactly (compensated float32 arithmetic), so the neighbour lists
+ * and distances are the same in all modes; only speed differs. */
+typedef enum {
+  GCR_FP32 = 0,  /* float32 MFMA screening                                   */
+  GCR_BF16 = 1,  /* bfloat16 (RNE) MFMA screening, float32 accumulation      */
+  GCR_FP8 = 2    /* OCP E4M3 with per-row scale, float32 accumulation        */
+} gcr_precision;
+
+typedef struct {
+  int32_t k;                  /* neighbours per node, Eq. (4); 0 <= k <= 120  */
+  int32_t cross_k;            /* cross-camera neighbours, Eq. (8); <0: = k    */
+  int32_t rounds;             /* T, Eq. (3)                                    */
+  int32_t rebuild_each_round; /* 1: rebuild the graph from X_{t-1} each round  */
+  int32_t normalize_input;    /* 1: L2-normalise input rows first              */
+  int32_t precision;          /* gcr_precision of the similarity screening     */
+  int32_t topk_out;           /* K of gcr_rerank's per-query output list       */
+  int32_t symmetric;          /* 1: Eq. (7)+(2) (only mode supported)          */
+  float gamma;                /* temperature of Eq. (4), > 0                   */
+  float alpha;                /* blend of Eq. (9) in [0, 1]; 1: global only    */
+  float beta_same;            /* factor on global-graph edges, same camera     */
+  float beta_cross;           /* factor on global-graph edges, other camera    */
+  float lambda;               /* regulariser of Eq. (16), > 0                  */
+} gcr_params;
+
+/* Paper defaults: gamma 0.2, k 15, T 3, lambda 10 (Sec. IV-B), alpha 1,
+ * graph rebuilt each round, inputs normalised, FP32 screening, K 100. */
+void gcr_params_default(gcr_params* p);
+
+typedef struct gcr_ctx gcr_ctx;
+
+/* Create a context on HIP device `device` (made current for the calls that
+ * use this context).  *out receives the handle.  Errors: INVALID (bad
+ * device / NULL out), HIP. */
+gcr_status gcr_create(gcr_ctx** out, int device);
+/* Free the context and its workspace (synchronises the device). */
+gcr_status gcr_destroy(gcr_ctx* ctx);
+/* Message of the last error on ctx (never NULL; "" if none). */
+const char* gcr_last_error(const gcr_ctx* ctx);
+
+/* Run statistics.  Synchronises the device to read counters. */
+typedef struct {
+  int64_t knn_rows;           /* rows whose neighbour lists were built         */
+  int64_t knn_candidates;     /* screened candidates re-scored exactly         */
+  int64_t knn_fallback_rows;  /* rows recomputed exhaustively (buffer full)    */
+  int64_t splits;             /* column splits of the last similarity sweep    */
+} gcr_stats;
+gcr_status gcr_get_stats(gcr_ctx* ctx, gcr_stats* out);
+gcr_status gcr_reset_stats(gcr_ctx* ctx);
+
+/* Per-kernel-class timing with HIP events recorded on the launch stream
+ * around every launch of that class while timing is on (off by default).
+ * Classes: 0 similarity + top-k screening, 1 exact refine (with the
+ * exhaustive fallback), 2 graph build (weights, reverse lists, degrees,
+ * normalised values), 3 propagation, 4 dense final distances, 5 input
+ * preparation (normalisation and screening operands).
+ * gcr_get_timing synchronises the device, returns the totals since the last
+ * reset (milliseconds and launch counts) and resets them. */
+#define GCR_NUM_TIMERS 6
+typedef struct {
+  double ms[GCR_NUM_TIMERS];
+  int64_t launches[GCR_NUM_TIMERS];
+} gcr_timing;
+gcr_status gcr_set_timing(gcr_ctx* ctx, int32_t on);
+gcr_status gcr_get_timing(gcr_ctx* ctx, gcr_timing* out);
+
+/* Row L2 normalisation: Y[i] = X[i] / max(||X[i]||, 1e-12).
+ * X, Y: float32 [n, d] (may alias).  Errors: INVALID. */
+gcr_status gcr_normalize_rows(gcr_ctx* ctx, const float* X, float* Y,
+                              int64_t n, int32_t d, void* stream);
+
+/* k nearest neighbours of every row of X among the other rows (Eq. (4)),
+ * and, when cam != NULL and cr_idx != NULL, the cross_k nearest rows with a
+ * different camera label (Eq. (8)).
+ *   X: float32 [n, d]; used as given (no normalisation).
+ *   cam: int32 [n] camera labels or NULL.
+ *   idx: int32 [n, k] out; dist: float32 [n, k] out, squared distances.
+ *   cr_idx / cr_dist: int32 / float32 [n, cross_k] out, or NULL.
+ * Uses p->k, p->cross_k, p->precision.  Errors: INVALID, UNSUPPORTED
+ * (k > 120), NOMEM, HIP. */
+gcr_status gcr_knn(gcr_ctx* ctx, const float* X, int64_t n, int32_t d,
+                   const int32_t* cam, const gcr_params* p,
+                   int32_t* idx, float* dist, int32_t* cr_idx, float* cr_dist,
+                   void* stream);
+
+/* Sparse symmetric propagation graph (Eq. (4)-(9)), in caller memory.
+ * For each of the global graph and (if has_cross) the cross-camera graph:
+ *   idx [n,k] int32, dist [n,k] float32   forward kNN lists
+ *   w   [n,k] float32   beta * exp(-dist / gamma)   (0 for padding)
+ *   rev_ptr [n+1], rev_src [n*k] int32, rev_w [n*k] float32: the transposed
+ *       edges j -> i stored at row i, sorted by source index
+ *   deg [n] float32: D_i of A = (A~ + A~^T)/2, i.e. 1 + sum(w)/2 over the
+ *       forward and reverse edges of row i
+ *   pf [n,k], pr [n*k] float32: normalised values c * w / (2 sqrt(D_i D_j))
+ *       of the forward and reverse entries, with c = alpha for the global
+ *       graph and 1 - alpha for the cross graph
+ * and self[n] float32 = alpha / D_i + (1 - alpha) / D^cr_i (diagonal of the
+ * blended operator).  gcr_graph_bytes gives the size of one device buffer
+ * holding all of it; gcr_graph_bind carves that buffer into the fields. */
+typedef struct {
+  int64_t n;
+  int32_t k, cross_k, has_cross, reserved;
+  int32_t *idx, *rev_ptr, *rev_src;
+  float *dist, *w, *rev_w, *deg, *pf, *pr;
+  int32_t *cr_idx, *cr_rev_ptr, *cr_rev_src;
+  float *cr_dist, *cr_w, *cr_rev_w, *cr_deg, *cr_pf, *cr_pr;
+  float* self;
+} gcr_graph;
+
+size_t gcr_graph_bytes(int64_t n, int32_t k, int32_t cross_k, int32_t has_cross);
+gcr_status gcr_graph_bind(gcr_graph* g, void* dev_buf, int64_t n, int32_t k,
+                          int32_t cross_k, int32_t has_cross);
+
+/* Build the propagation graph of X (float32 [n, d], used as given).  cam may
+ * be NULL; the cross graph is built when g->has_cross (requires cam).
+ * Edge factor beta_same / beta_cross applies to the global graph when cam is
+ * given.  Errors: INVALID, UNSUPPORTED, NOMEM, HIP. */
+gcr_status gcr_build_graph(gcr_ctx* ctx, const float* X, int64_t n, int32_t d,
+                           const int32_t* cam, const gcr_params* p,
+                           gcr_graph* g, void* stream);
+
+/* One propagation round over graph g:
+ *   y_i = self_i x_i + sum_fwd pf x_j + sum_rev pr x_j (+ cross graph terms)
+ *   X_out[i] = y_i / max(||y_i||, 1e-12)
+ * X_in, X_out: float32 [n, d], distinct buffers (in-place is INVALID). */
+gcr_status gcr_propagate(gcr_ctx* ctx, const gcr_graph* g, const float* X_in,
+                         float* X_out, int64_t n, int32_t d, void* stream);
+
+/* Distances between the first nq rows (queries) and the next ng rows
+ * (gallery) of X (float32 [nq+ng, d]):
+ *   dist_out: float32 [nq, ng] dense squared distances, or NULL;
+ *   topk_idx / topk_dist: int32 / float32 [nq, K] with K = p->topk_out: the
+ *     K nearest gallery items (gallery index 0..ng-1) by (distance, index),
+ *     or NULL.
+ * Errors: INVALID, UNSUPPORTED, NOMEM, HIP. */
+gcr_status gcr_final_distances(gcr_ctx* ctx, const float* X, int64_t nq,
+                               int64_t ng, int32_t d, const gcr_params* p,
+                               float* dist_out, int32_t* topk_idx,
+                               float* topk_dist, void* stream);
+
+/* Whole re-ranking of X = [queries; gallery] (float32 [nq+ng, d]):
+ * normalise (if asked), T = p->rounds propagation rounds with the graph
+ * rebuilt each round (or built once), then final distances as in
+ * gcr_final_distances.  X_final (float32 [nq+ng, d]) receives X_T if not
+ * NULL.  cam (int32 [nq+ng]) may be NULL; with cam and alpha < 1 the
+ * cross-camera graph and the blend of Eq. (9) are used.
+ * Errors: INVALID, UNSUPPORTED, NOMEM, HIP. */
+gcr_status gcr_rerank(gcr_ctx* ctx, const float* X, int64_t nq, int64_t ng,
+                      int32_t d, const int32_t* cam, const gcr_params* p,
+                      float* dist_out, int32_t* topk_idx, float* topk_dist,
+                      float* X_final, void* stream);
+
+/* Tracklet profile vectors (video re-ID, Alg. 2 step 1).
+ *   frames: float32 [nf, d]; offsets: int32 [nt+1] (frames of tracklet c are
+ *   rows offsets[c] .. offsets[c+1]-1, nonempty, contiguous, increasing);
+ *   group: int32 [nt] camera group per tracklet or NULL (one group);
+ *   mode 0: PVG, Eq. (16) per group: w_c = (F^T F + lambda n I)^-1 (mu_c - mu)
+ *           where F holds the group's n frames and mu their mean;
+ *   mode 1: mean profile, Eq. (10);
+ *   W_out: float32 [nt, d], each row L2-normalised.
+ * Host-side reads of offsets/group: offsets_host and group_host are HOST
+ * copies of the same arrays (the solver plans per-group work on the host).
+ * Errors: INVALID, NOMEM, HIP. */
+gcr_status gcr_profile_vectors(gcr_ctx* ctx, const float* frames,
+                               const int32_t* offsets, const int32_t* group,
+                               const int32_t* offsets_host,
+                               const int32_t* group_host, int32_t nt, int32_t d,
+                               int32_t mode, float lambda, float* W_out,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCR_H */

@@ -1,0 +1,103 @@
+"""ctypes view of libgcr.so (the C ABI declared in include/gcr.h).
+
+Only marshalling lives here: structs, argument types and the loader.  The
+library must have been built in-tree (``python -m paper_2306_08792_amd.build``);
+loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgcr.so")
+
+GCR_OK = 0
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "UNSUPPORTED"}
+
+# every exported entry point of include/gcr.h
+EXPORTS = [
+    "gcr_params_default", "gcr_create", "gcr_destroy", "gcr_last_error", "gcr_get_stats",
+    "gcr_reset_stats", "gcr_normalize_rows", "gcr_knn", "gcr_graph_bytes", "gcr_graph_bind",
+    "gcr_build_graph", "gcr_propagate", "gcr_final_distances", "gcr_rerank",
+    "gcr_profile_vectors", "gcr_set_timing", "gcr_get_timing",
+]
+NUM_TIMERS = 6
+TIMER_NAMES = ["sim_topk", "refine", "graph", "propagate", "final_dense", "prep"]
+
+
+class GcrParams(C.Structure):
+    _fields_ = [
+        ("k", C.c_int32), ("cross_k", C.c_int32), ("rounds", C.c_int32),
+        ("rebuild_each_round", C.c_int32), ("normalize_input", C.c_int32),
+        ("precision", C.c_int32), ("topk_out", C.c_int32), ("symmetric", C.c_int32),
+        ("gamma", C.c_float), ("alpha", C.c_float), ("beta_same", C.c_float),
+        ("beta_cross", C.c_float), ("lambda_", C.c_float),
+    ]
+
+
+class GcrStats(C.Structure):
+    _fields_ = [("knn_rows", C.c_int64), ("knn_candidates", C.c_int64),
+                ("knn_fallback_rows", C.c_int64), ("splits", C.c_int64)]
+
+
+_P = C.c_void_p
+
+
+class GcrTiming(C.Structure):
+    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6)]
+
+
+class GcrGraph(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("k", C.c_int32), ("cross_k", C.c_int32), ("has_cross", C.c_int32),
+        ("reserved", C.c_int32),
+        ("idx", _P), ("rev_ptr", _P), ("rev_src", _P),
+        ("dist", _P), ("w", _P), ("rev_w", _P), ("deg", _P), ("pf", _P), ("pr", _P),
+        ("cr_idx", _P), ("cr_rev_ptr", _P), ("cr_rev_src", _P),
+        ("cr_dist", _P), ("cr_w", _P), ("cr_rev_w", _P), ("cr_deg", _P), ("cr_pf", _P), ("cr_pr", _P),
+        ("self_", _P),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgcr.so once and declare the signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2306_08792_amd.build` "
+            "(there is no CPU fallback)")
+    L = C.CDLL(path)
+    i32, i64, f32, vp = C.c_int32, C.c_int64, C.c_float, C.c_void_p
+    pP = C.POINTER(GcrParams)
+    L.gcr_params_default.argtypes = [pP]
+    L.gcr_params_default.restype = None
+    L.gcr_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.gcr_destroy.argtypes = [vp]
+    L.gcr_last_error.argtypes = [vp]
+    L.gcr_last_error.restype = C.c_char_p
+    L.gcr_get_stats.argtypes = [vp, C.POINTER(GcrStats)]
+    L.gcr_reset_stats.argtypes = [vp]
+    L.gcr_normalize_rows.argtypes = [vp, vp, vp, i64, i32, vp]
+    L.gcr_knn.argtypes = [vp, vp, i64, i32, vp, pP, vp, vp, vp, vp, vp]
+    L.gcr_graph_bytes.argtypes = [i64, i32, i32, i32]
+    L.gcr_graph_bytes.restype = C.c_size_t
+    L.gcr_graph_bind.argtypes = [C.POINTER(GcrGraph), vp, i64, i32, i32, i32]
+    L.gcr_build_graph.argtypes = [vp, vp, i64, i32, vp, pP, C.POINTER(GcrGraph), vp]
+    L.gcr_propagate.argtypes = [vp, C.POINTER(GcrGraph), vp, vp, i64, i32, vp]
+    L.gcr_final_distances.argtypes = [vp, vp, i64, i64, i32, pP, vp, vp, vp, vp]
+    L.gcr_rerank.argtypes = [vp, vp, i64, i64, i32, vp, pP, vp, vp, vp, vp, vp]
+    L.gcr_set_timing.argtypes = [vp, i32]
+    L.gcr_get_timing.argtypes = [vp, C.POINTER(GcrTiming)]
+    L.gcr_profile_vectors.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, f32, vp, vp]
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if fn.restype is C.c_int:  # default restype: gcr_status
+            fn.restype = C.c_int
+    _lib = L
+    return L

@@ -1,0 +1,762 @@
+// C ABI of the GCR library: argument checks, workspace planning and the
+// launch sequence of each entry point.  All device work is enqueued on the
+// caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/gcr.h"
+#include "kernels.h"
+
+struct gcr_timer_rec {
+  hipEvent_t a, b;
+  int cls;
+};
+struct gcr_ctx {
+  int device = 0;
+  int timing = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<gcr_timer_rec> recs;
+  std::string err;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned long long* stats = nullptr;  // device: [0] candidates, [1] fallback rows
+  int64_t knn_rows = 0;
+  int64_t splits = 0;
+};
+
+namespace {
+
+using namespace gcr;
+
+hipEvent_t pool_event(gcr_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// RAII scope recording a start/stop event pair around launches of one class.
+struct TimedScope {
+  gcr_ctx* c;
+  hipStream_t st;
+  gcr_timer_rec r;
+  bool on;
+  TimedScope(gcr_ctx* c_, int cls, hipStream_t st_) : c(c_), st(st_), on(c_ && c_->timing) {
+    if (on) {
+      r.a = pool_event(c);
+      r.b = pool_event(c);
+      r.cls = cls;
+      (void)hipEventRecord(r.a, st);
+    }
+  }
+  ~TimedScope() {
+    if (on) {
+      (void)hipEventRecord(r.b, st);
+      c->recs.push_back(r);
+    }
+  }
+};
+
+gcr_status fail(gcr_ctx* c, gcr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIP_TRY(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(ctx, GCR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t roundup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Two-pass bump planner over the context workspace.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+gcr_status ensure_ws(gcr_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return GCR_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (c->ws) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t want = align_up(bytes + (bytes >> 3), 1 << 20);
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(c, GCR_ERR_NOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  c->ws_bytes = want;
+  return GCR_OK;
+}
+
+__global__ void fill_u32_kernel(unsigned* p, unsigned v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+void fill_u32(void* p, unsigned v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (unsigned*)p, v, n);
+}
+__global__ void add_count_kernel(unsigned long long* dst, const int* src) { *dst += (unsigned long long)*src; }
+
+int esize_of(int prec) { return prec == GCR_PREC_FP32 ? 4 : (prec == GCR_PREC_BF16 ? 2 : 1); }
+
+// Bound on |s~ - s| / (||x_r|| ||x_c||) for the screening precision.
+float eps_similarity(int prec, int d) {
+  const double u23 = ldexp(1.0, -23);
+  double uq = 0.0, m = d;
+  if (prec == GCR_PREC_FP32) m = d + 1;            // rounded products
+  if (prec == GCR_PREC_BF16) uq = ldexp(1.0, -8);
+  if (prec == GCR_PREC_FP8) uq = ldexp(1.0, -4);
+  const double g = m * u23 / (1.0 - m * u23);
+  double e = (2.0 * uq + uq * uq) + g * (1.0 + uq) * (1.0 + uq);
+  if (prec == GCR_PREC_FP8) {
+    // subnormal grid of E4M3 (absolute 2^-10 in scaled units, scale <= ||x|| / 448)
+    e += 2.0 * (1.0 + uq) * sqrt((double)d) * ldexp(1.0, -10) / 448.0 + d * ldexp(1.0, -20) / (448.0 * 448.0);
+    e += 4.0 * u23 * (1.0 + 2.0 * uq);               // scale products in the epilogue
+  }
+  return (float)(e * 1.01);
+}
+float eps_norm(int d) {
+  const double u23 = ldexp(1.0, -23), m = d + 8;
+  return (float)(m * u23 / (1.0 - m * u23) * 1.01);
+}
+
+int capacity_for(int prec, int kmax) {
+  if (prec == GCR_PREC_FP32) return kmax + 8 <= 32 ? 32 : (kmax + 8 <= 64 ? 64 : 128);
+  if (prec == GCR_PREC_BF16) return kmax + 8 <= 64 ? 64 : 128;
+  return kmax + 8 <= 128 ? 128 : 256;
+}
+
+struct KnnPlan {
+  int prec, nl, C, S, RB, kch, fb_grid;
+  int64_t n, npad, ld, W, rows, ncols;
+  uint8_t* Xs; float* n2; float* scale; unsigned* maxn2;
+  uint64_t* cand; int* cnt; int* fb_list; int* fb_count; uint64_t* fb_scr;
+};
+
+void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
+              int64_t c1, int k0, int k1) {
+  kp.prec = prec;
+  kp.nl = k1 > 0 ? 2 : 1;
+  kp.n = n;
+  kp.npad = roundup(n, 128) + 128;
+  kp.ld = roundup((int64_t)d * esize_of(prec), 128);
+  kp.kch = (int)(kp.ld / 128);
+  kp.rows = r1 - r0;
+  kp.ncols = c1 - c0;
+  kp.C = capacity_for(prec, std::max(k0, k1));
+  kp.RB = (int)((kp.rows + 127) / 128);
+  int S = 8;
+  while ((int64_t)kp.RB * S < 1024 && S * 2 * 128 <= kp.ncols && S * 2 * kp.C <= 2048) S *= 2;
+  kp.S = S;
+  kp.W = roundup((kp.ncols + S - 1) / S, 128);
+  kp.fb_grid = 32;
+  kp.Xs = ar.take<uint8_t>((size_t)(kp.npad * kp.ld));
+  kp.n2 = ar.take<float>(kp.npad);
+  kp.scale = ar.take<float>(kp.npad);
+  kp.maxn2 = ar.take<unsigned>(64);
+  kp.cand = ar.take<uint64_t>((size_t)kp.rows * kp.nl * S * kp.C);
+  kp.cnt = ar.take<int>((size_t)kp.rows * kp.nl * S);
+  kp.fb_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
+  kp.fb_count = ar.take<int>(64);
+  kp.fb_scr = ar.take<uint64_t>((size_t)kp.fb_grid * std::max<int64_t>(kp.ncols, 1));
+}
+
+// Screening + refine for rows [r0, r1) against columns [c0, c1) of X.
+void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* cam, int64_t r0, int64_t r1,
+             int64_t c0, int64_t c1, int exclude_self, int k0, int k1, int32_t* idx0, float* dist0,
+             int32_t* idx1, float* dist1, hipStream_t st) {
+  fill_u32(kp.maxn2, 0u, 1, st);
+  fill_u32(kp.fb_count, 0u, 1, st);
+  {
+    TimedScope ts(c, 5, st);
+    launch_screen_prep(kp.prec, X, kp.n, d, kp.npad, kp.Xs, kp.ld, kp.n2, kp.scale, kp.maxn2, st);
+  }
+  SimArgs sa;
+  sa.Xs = kp.Xs; sa.ld_bytes = kp.ld; sa.kchunks = kp.kch; sa.n2 = kp.n2;
+  sa.scale = kp.prec == GCR_PREC_FP8 ? kp.scale : nullptr;
+  sa.cam = cam; sa.maxn2 = (const float*)kp.maxn2;
+  sa.r0 = r0; sa.r1 = r1; sa.c0 = c0; sa.c1 = c1; sa.W = kp.W; sa.S = kp.S; sa.RB = kp.RB;
+  sa.exclude_self = exclude_self; sa.k0 = k0; sa.k1 = k1; sa.C = kp.C;
+  sa.eps_s = eps_similarity(kp.prec, d); sa.eps_n = eps_norm(d);
+  sa.cand = kp.cand; sa.cnt = kp.cnt;
+  {
+    TimedScope ts(c, 0, st);
+    launch_sim_topk(kp.prec, kp.nl, sa, st);
+  }
+  RefineArgs ra;
+  ra.cand = kp.cand; ra.cnt = kp.cnt; ra.S = kp.S; ra.C = kp.C; ra.NL = kp.nl; ra.k0 = k0; ra.k1 = k1;
+  ra.r0 = r0; ra.r1 = r1; ra.c0 = c0; ra.c1 = c1; ra.exclude_self = exclude_self;
+  ra.X = X; ra.d = d; ra.cam = cam; ra.n2 = kp.n2; ra.maxn2 = (const float*)kp.maxn2;
+  ra.eps_s = sa.eps_s; ra.eps_n = sa.eps_n;
+  ra.idx0 = idx0; ra.dist0 = dist0; ra.idx1 = idx1; ra.dist1 = dist1;
+  ra.fb_list = kp.fb_list; ra.fb_count = kp.fb_count; ra.stat_cands = c->stats;
+  ra.fb_scratch = kp.fb_scr; ra.fb_grid = kp.fb_grid;
+  {
+    TimedScope ts(c, 1, st);
+    launch_refine(ra, st);
+  }
+  hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(1), 0, st, c->stats + 1, kp.fb_count);
+  c->knn_rows += kp.rows;
+  c->splits = kp.S;
+}
+
+gcr_status check_params(gcr_ctx* c, const gcr_params* p) {
+  if (!p) return fail(c, GCR_ERR_INVALID, "params is NULL");
+  if (p->k < 0) return fail(c, GCR_ERR_INVALID, "k must be >= 0 (got %d)", p->k);
+  if (p->k > 120 || p->cross_k > 120)
+    return fail(c, GCR_ERR_UNSUPPORTED, "k and cross_k above 120 are not supported");
+  if (!(p->gamma > 0.f)) return fail(c, GCR_ERR_INVALID, "gamma must be > 0");
+  if (!(p->alpha >= 0.f && p->alpha <= 1.f)) return fail(c, GCR_ERR_INVALID, "alpha must be in [0, 1]");
+  if (!(p->beta_same > 0.f && p->beta_cross > 0.f)) return fail(c, GCR_ERR_INVALID, "beta factors must be > 0");
+  if (p->precision < 0 || p->precision > 2) return fail(c, GCR_ERR_INVALID, "unknown precision %d", p->precision);
+  if (p->rounds < 0) return fail(c, GCR_ERR_INVALID, "rounds must be >= 0");
+  if (p->symmetric != 1) return fail(c, GCR_ERR_UNSUPPORTED, "only the symmetric normalisation is built");
+  return GCR_OK;
+}
+
+int cross_k_of(const gcr_params* p) { return p->cross_k < 0 ? p->k : p->cross_k; }
+
+// ---- graph layout
+struct GraphLayout {
+  size_t bytes;
+};
+size_t graph_part(Arena& ar, gcr_graph* g, int64_t n, int k, bool cross) {
+  (void)cross;
+  int32_t* idx = ar.take<int32_t>((size_t)n * k);
+  float* dist = ar.take<float>((size_t)n * k);
+  float* w = ar.take<float>((size_t)n * k);
+  int32_t* rp = ar.take<int32_t>((size_t)n + 1);
+  int32_t* rs = ar.take<int32_t>((size_t)n * k);
+  float* rw = ar.take<float>((size_t)n * k);
+  float* deg = ar.take<float>((size_t)n);
+  float* pf = ar.take<float>((size_t)n * k);
+  float* pr = ar.take<float>((size_t)n * k);
+  if (g) {
+    if (!cross) {
+      g->idx = idx; g->dist = dist; g->w = w; g->rev_ptr = rp; g->rev_src = rs; g->rev_w = rw;
+      g->deg = deg; g->pf = pf; g->pr = pr;
+    } else {
+      g->cr_idx = idx; g->cr_dist = dist; g->cr_w = w; g->cr_rev_ptr = rp; g->cr_rev_src = rs;
+      g->cr_rev_w = rw; g->cr_deg = deg; g->cr_pf = pf; g->cr_pr = pr;
+    }
+  }
+  return ar.off;
+}
+size_t layout_graph(Arena& ar, gcr_graph* g, int64_t n, int k, int ck, int has_cross) {
+  if (g) {
+    memset(g, 0, sizeof(*g));
+    g->n = n; g->k = k; g->cross_k = ck; g->has_cross = has_cross;
+  }
+  graph_part(ar, g, n, k, false);
+  if (has_cross) graph_part(ar, g, n, ck, true);
+  float* self = ar.take<float>((size_t)n);
+  if (g) g->self = self;
+  return ar.off;
+}
+
+struct GraphTmp {
+  int32_t* cnt; float* fsum; int32_t* blk;
+};
+void plan_graph_tmp(Arena& ar, GraphTmp& t, int64_t n) {
+  t.cnt = ar.take<int32_t>((size_t)n + 1);
+  t.fsum = ar.take<float>((size_t)n + 1);
+  t.blk = ar.take<int32_t>((size_t)(n / 1024 + 2));
+}
+
+void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const gcr_params* p, float coef,
+               const GraphTmp& t, hipStream_t st, bool finish) {
+  GraphBuildArgs a;
+  a.n = n;
+  a.k = cross ? g->cross_k : g->k;
+  a.idx = cross ? g->cr_idx : g->idx;
+  a.dist = cross ? g->cr_dist : g->dist;
+  a.cam = cam;
+  a.use_beta = (!cross && cam && (p->beta_same != 1.f || p->beta_cross != 1.f)) ? 1 : 0;
+  a.beta_same = p->beta_same; a.beta_cross = p->beta_cross;
+  a.gamma = p->gamma;
+  a.w = cross ? g->cr_w : g->w;
+  a.rev_ptr = cross ? g->cr_rev_ptr : g->rev_ptr;
+  a.rev_src = cross ? g->cr_rev_src : g->rev_src;
+  a.rev_w = cross ? g->cr_rev_w : g->rev_w;
+  a.deg = cross ? g->cr_deg : g->deg;
+  a.pf = cross ? g->cr_pf : g->pf;
+  a.pr = cross ? g->cr_pr : g->pr;
+  a.coef = coef;
+  a.tmp_cnt = t.cnt; a.tmp_fsum = t.fsum; a.tmp_blk = t.blk;
+  if (!finish) launch_graph_build(a, st);
+  else launch_finish_values(a, st);
+}
+
+// kNN + affinity + CSR + degrees + normalised values into g.
+void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, const float* X, int64_t n, int d,
+                         const int* cam, const gcr_params* p, const gcr_graph* g, hipStream_t st) {
+  const bool cross = g->has_cross != 0;
+  if (g->k > 0 || (cross && g->cross_k > 0))
+    run_knn(c, kp, X, d, cam, 0, n, 0, n, 1, g->k, cross ? g->cross_k : 0, g->idx, g->dist,
+            cross ? g->cr_idx : nullptr, cross ? g->cr_dist : nullptr, st);
+  const float alpha = cross ? p->alpha : 1.0f;
+  TimedScope ts(c, 2, st);
+  build_one(g, false, n, cam, p, alpha, gt, st, false);
+  if (cross) build_one(g, true, n, cam, p, 1.0f - alpha, gt, st, false);
+  build_one(g, false, n, cam, p, alpha, gt, st, true);
+  if (cross) build_one(g, true, n, cam, p, 1.0f - alpha, gt, st, true);
+  launch_self_coef(n, g->deg, cross ? g->cr_deg : nullptr, alpha, g->self, st);
+}
+
+void enqueue_propagate(gcr_ctx* c, const gcr_graph* g, const float* Xin, float* Xout, int64_t n, int d,
+                       hipStream_t st) {
+  TimedScope ts(c, 3, st);
+  PropArgs a;
+  a.X = Xin; a.Y = Xout; a.n = n; a.d = d; a.self = g->self;
+  a.idx = g->idx; a.pf = g->pf; a.k = g->k; a.rev_ptr = g->rev_ptr; a.rev_src = g->rev_src; a.pr = g->pr;
+  if (g->has_cross) {
+    a.cr_idx = g->cr_idx; a.cr_pf = g->cr_pf; a.ck = g->cross_k; a.cr_rev_ptr = g->cr_rev_ptr;
+    a.cr_rev_src = g->cr_rev_src; a.cr_pr = g->cr_pr;
+  } else {
+    a.cr_idx = nullptr; a.cr_pf = nullptr; a.ck = 0; a.cr_rev_ptr = nullptr; a.cr_rev_src = nullptr;
+    a.cr_pr = nullptr;
+  }
+  launch_propagate(a, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+void gcr_params_default(gcr_params* p) {
+  if (!p) return;
+  p->k = 15;
+  p->cross_k = -1;
+  p->rounds = 3;
+  p->rebuild_each_round = 1;
+  p->normalize_input = 1;
+  p->precision = GCR_FP32;
+  p->topk_out = 100;
+  p->symmetric = 1;
+  p->gamma = 0.2f;
+  p->alpha = 1.0f;
+  p->beta_same = 1.0f;
+  p->beta_cross = 1.0f;
+  p->lambda = 10.0f;
+}
+
+gcr_status gcr_create(gcr_ctx** out, int device) {
+  if (!out) return GCR_ERR_INVALID;
+  *out = nullptr;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) {
+    (void)hipGetLastError();
+    return GCR_ERR_INVALID;
+  }
+  gcr_ctx* c = new gcr_ctx();
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->stats, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+    delete c;
+    return GCR_ERR_HIP;
+  }
+  *out = c;
+  return GCR_OK;
+}
+
+gcr_status gcr_destroy(gcr_ctx* c) {
+  if (!c) return GCR_ERR_INVALID;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (const gcr_timer_rec& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->stats) (void)hipFree(c->stats);
+  delete c;
+  return GCR_OK;
+}
+
+const char* gcr_last_error(const gcr_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+gcr_status gcr_get_stats(gcr_ctx* c, gcr_stats* out) {
+  if (!c || !out) return GCR_ERR_INVALID;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  unsigned long long h[4];
+  HIP_TRY(c, hipMemcpy(h, c->stats, sizeof h, hipMemcpyDeviceToHost));
+  out->knn_rows = c->knn_rows;
+  out->knn_candidates = (int64_t)h[0];
+  out->knn_fallback_rows = (int64_t)h[1];
+  out->splits = c->splits;
+  return GCR_OK;
+}
+
+gcr_status gcr_reset_stats(gcr_ctx* c) {
+  if (!c) return GCR_ERR_INVALID;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  HIP_TRY(c, hipMemset(c->stats, 0, 4 * sizeof(unsigned long long)));
+  c->knn_rows = 0;
+  return GCR_OK;
+}
+
+gcr_status gcr_set_timing(gcr_ctx* c, int32_t on) {
+  if (!c) return GCR_ERR_INVALID;
+  c->timing = on ? 1 : 0;
+  return GCR_OK;
+}
+
+gcr_status gcr_get_timing(gcr_ctx* c, gcr_timing* out) {
+  if (!c || !out) return GCR_ERR_INVALID;
+  memset(out, 0, sizeof(*out));
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  for (const gcr_timer_rec& r : c->recs) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, r.a, r.b));
+    out->ms[r.cls] += ms;
+    out->launches[r.cls] += 1;
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return GCR_OK;
+}
+
+gcr_status gcr_normalize_rows(gcr_ctx* c, const float* X, float* Y, int64_t n, int32_t d, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  if (n < 0 || d <= 0 || (n > 0 && (!X || !Y))) return fail(c, GCR_ERR_INVALID, "bad normalize arguments");
+  HIP_TRY(c, hipSetDevice(c->device));
+  launch_normalize_rows(X, Y, n, d, (hipStream_t)stream);
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+gcr_status gcr_knn(gcr_ctx* c, const float* X, int64_t n, int32_t d, const int32_t* cam, const gcr_params* p,
+                   int32_t* idx, float* dist, int32_t* cr_idx, float* cr_dist, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  gcr_status s = check_params(c, p);
+  if (s != GCR_OK) return s;
+  if (n < 1 || d <= 0 || !X) return fail(c, GCR_ERR_INVALID, "bad X / n / d");
+  if (n > (int64_t)INT32_MAX / 2) return fail(c, GCR_ERR_UNSUPPORTED, "n too large");
+  const bool cross = cr_idx != nullptr;
+  if (cross && (!cam || !cr_dist)) return fail(c, GCR_ERR_INVALID, "cross list needs cam and cr_dist");
+  if (p->k > 0 && (!idx || !dist)) return fail(c, GCR_ERR_INVALID, "idx / dist are NULL");
+  const int ck = cross ? cross_k_of(p) : 0;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Arena dry;
+  KnnPlan kp;
+  plan_knn(dry, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
+  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
+  hipStream_t st = (hipStream_t)stream;
+  // a zero-size list is allowed: give the kernels harmless pointers
+  run_knn(c, kp, X, d, cam, 0, n, 0, n, 1, p->k, ck, idx, dist, cr_idx, cr_dist, st);
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+size_t gcr_graph_bytes(int64_t n, int32_t k, int32_t cross_k, int32_t has_cross) {
+  Arena dry;
+  return layout_graph(dry, nullptr, n, k, has_cross ? (cross_k < 0 ? k : cross_k) : 0, has_cross) + 256;
+}
+
+gcr_status gcr_graph_bind(gcr_graph* g, void* buf, int64_t n, int32_t k, int32_t cross_k, int32_t has_cross) {
+  if (!g || !buf || n < 1 || k < 0) return GCR_ERR_INVALID;
+  if (((uintptr_t)buf) & 255) return GCR_ERR_INVALID;
+  Arena ar{(char*)buf, 0};
+  layout_graph(ar, g, n, k, has_cross ? (cross_k < 0 ? k : cross_k) : 0, has_cross);
+  return GCR_OK;
+}
+
+gcr_status gcr_build_graph(gcr_ctx* c, const float* X, int64_t n, int32_t d, const int32_t* cam,
+                           const gcr_params* p, gcr_graph* g, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  gcr_status s = check_params(c, p);
+  if (s != GCR_OK) return s;
+  if (!g || !X || n < 1 || d <= 0 || g->n != n || g->k != p->k)
+    return fail(c, GCR_ERR_INVALID, "graph / X shape mismatch");
+  if (g->has_cross && !cam) return fail(c, GCR_ERR_INVALID, "cross graph needs camera labels");
+  HIP_TRY(c, hipSetDevice(c->device));
+  Arena dry;
+  KnnPlan kp;
+  GraphTmp gt;
+  plan_knn(dry, kp, p->precision, n, d, 0, n, 0, n, g->k, g->has_cross ? g->cross_k : 0);
+  plan_graph_tmp(dry, gt, n);
+  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, g->k, g->has_cross ? g->cross_k : 0);
+  plan_graph_tmp(ar, gt, n);
+  enqueue_build_graph(c, kp, gt, X, n, d, cam, p, g, (hipStream_t)stream);
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+gcr_status gcr_propagate(gcr_ctx* c, const gcr_graph* g, const float* X_in, float* X_out, int64_t n, int32_t d,
+                         void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  if (!g || !X_in || !X_out || g->n != n || d <= 0) return fail(c, GCR_ERR_INVALID, "bad propagate arguments");
+  if (X_in == X_out) return fail(c, GCR_ERR_INVALID, "in-place propagation is not allowed");
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported by propagation");
+  HIP_TRY(c, hipSetDevice(c->device));
+  enqueue_propagate(c, g, X_in, X_out, n, d, (hipStream_t)stream);
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+struct FinalPlan {
+  KnnPlan kd, kt;
+};
+static void plan_final(Arena& ar, FinalPlan& fp, const gcr_params* p, int64_t nq, int64_t ng, int d,
+                       bool dense, bool topk) {
+  const int64_t n = nq + ng;
+  if (dense) plan_knn(ar, fp.kd, GCR_PREC_FP32, n, d, 0, nq, nq, n, 1, 0);
+  if (topk) plan_knn(ar, fp.kt, p->precision, n, d, 0, nq, nq, n, p->topk_out, 0);
+}
+static void run_final(gcr_ctx* c, const FinalPlan& fp, const float* X, int64_t nq, int64_t ng, int32_t d,
+                      const gcr_params* p, float* dist_out, int32_t* topk_idx, float* topk_dist, hipStream_t st) {
+  const int64_t n = nq + ng;
+  if (dist_out) {
+    const KnnPlan& kd = fp.kd;
+    fill_u32(kd.maxn2, 0u, 1, st);
+    {
+      TimedScope ts(c, 5, st);
+      launch_screen_prep(GCR_PREC_FP32, X, n, d, kd.npad, kd.Xs, kd.ld, kd.n2, kd.scale, kd.maxn2, st);
+    }
+    TimedScope ts(c, 4, st);
+    launch_dense_dist(kd.Xs, kd.ld, kd.kch, kd.n2, 0, nq, nq, ng, dist_out, st);
+  }
+  if (topk_idx)
+    run_knn(c, fp.kt, X, d, nullptr, 0, nq, nq, n, 0, p->topk_out, 0, topk_idx, topk_dist, nullptr, nullptr, st);
+}
+
+gcr_status gcr_final_distances(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_t d, const gcr_params* p,
+                               float* dist_out, int32_t* topk_idx, float* topk_dist, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  if (!p) return fail(c, GCR_ERR_INVALID, "params is NULL");
+  if (!X || nq < 1 || ng < 1 || d <= 0) return fail(c, GCR_ERR_INVALID, "bad X / nq / ng / d");
+  if (topk_idx && (!topk_dist || p->topk_out < 1 || p->topk_out > 120))
+    return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
+  if (p->precision < 0 || p->precision > 2) return fail(c, GCR_ERR_INVALID, "unknown precision");
+  HIP_TRY(c, hipSetDevice(c->device));
+  FinalPlan fp;
+  Arena dry;
+  plan_final(dry, fp, p, nq, ng, d, dist_out != nullptr, topk_idx != nullptr);
+  gcr_status s = ensure_ws(c, dry.off);
+  if (s != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan_final(ar, fp, p, nq, ng, d, dist_out != nullptr, topk_idx != nullptr);
+  run_final(c, fp, X, nq, ng, d, p, dist_out, topk_idx, topk_dist, (hipStream_t)stream);
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+gcr_status gcr_rerank(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_t d, const int32_t* cam,
+                      const gcr_params* p, float* dist_out, int32_t* topk_idx, float* topk_dist, float* X_final,
+                      void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  gcr_status s = check_params(c, p);
+  if (s != GCR_OK) return s;
+  const int64_t n = nq + ng;
+  if (!X || nq < 1 || ng < 1 || d <= 0) return fail(c, GCR_ERR_INVALID, "bad X / nq / ng / d");
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
+  if (topk_idx && (!topk_dist || p->topk_out < 1 || p->topk_out > 120))
+    return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
+  const int has_cross = (cam && p->alpha < 1.0f) ? 1 : 0;
+  const int ck = has_cross ? cross_k_of(p) : 0;
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+
+  auto plan = [&](Arena& ar, float** xa, float** xb, gcr_graph* g, KnnPlan& kp, GraphTmp& gt) {
+    *xa = ar.take<float>((size_t)n * d);
+    *xb = ar.take<float>((size_t)n * d);
+    void* gbuf = ar.take<char>(gcr_graph_bytes(n, p->k, ck, has_cross));
+    if (g && gbuf) gcr_graph_bind(g, gbuf, n, p->k, ck, has_cross);
+    plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
+    plan_graph_tmp(ar, gt, n);
+  };
+  float *xa, *xb;
+  gcr_graph g;
+  KnnPlan kp;
+  GraphTmp gt;
+  FinalPlan fp;
+  const bool dense = dist_out != nullptr, topk = topk_idx != nullptr;
+  Arena dry;
+  plan(dry, &xa, &xb, nullptr, kp, gt);
+  plan_final(dry, fp, p, nq, ng, d, dense, topk);
+  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan(ar, &xa, &xb, &g, kp, gt);
+  plan_final(ar, fp, p, nq, ng, d, dense, topk);
+
+  if (p->normalize_input) {
+    TimedScope ts(c, 5, st);
+    launch_normalize_rows(X, xa, n, d, st);
+  }
+  else HIP_TRY(c, hipMemcpyAsync(xa, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
+  for (int t = 0; t < p->rounds; ++t) {
+    if (t == 0 || p->rebuild_each_round) enqueue_build_graph(c, kp, gt, xa, n, d, cam, p, &g, st);
+    enqueue_propagate(c, &g, xa, xb, n, d, st);
+    std::swap(xa, xb);
+  }
+  run_final(c, fp, xa, nq, ng, d, p, dist_out, topk_idx, topk_dist, st);
+  if (X_final) HIP_TRY(c, hipMemcpyAsync(X_final, xa, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* offsets, const int32_t* group,
+                               const int32_t* offsets_host, const int32_t* group_host, int32_t nt, int32_t d,
+                               int32_t mode, float lambda, float* W_out, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  if (!frames || !offsets || !offsets_host || !W_out || nt < 1 || d <= 0)
+    return fail(c, GCR_ERR_INVALID, "bad profile-vector arguments");
+  if (mode != 0 && mode != 1) return fail(c, GCR_ERR_INVALID, "mode must be 0 (PVG) or 1 (mean)");
+  if (mode == 0 && !(lambda > 0.f)) return fail(c, GCR_ERR_INVALID, "lambda must be > 0");
+  if (group && !group_host) return fail(c, GCR_ERR_INVALID, "group needs group_host");
+  if (d > 8192) return fail(c, GCR_ERR_UNSUPPORTED, "d above 8192 is not supported");
+  for (int t = 0; t < nt; ++t)
+    if (offsets_host[t + 1] <= offsets_host[t]) return fail(c, GCR_ERR_INVALID, "tracklet %d is empty", t);
+  if (offsets_host[0] != 0) return fail(c, GCR_ERR_INVALID, "offsets[0] must be 0");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nf = offsets_host[nt];
+
+  // host plan: members and frame rows per group
+  std::vector<int> gid(nt, 0);
+  if (group_host) for (int t = 0; t < nt; ++t) gid[t] = group_host[t];
+  std::vector<int> ug(gid.begin(), gid.end());
+  std::sort(ug.begin(), ug.end());
+  ug.erase(std::unique(ug.begin(), ug.end()), ug.end());
+  std::vector<int32_t> members, rows;
+  std::vector<int64_t> mstart, rstart;
+  for (int gv : ug) {
+    mstart.push_back((int64_t)members.size());
+    rstart.push_back((int64_t)rows.size());
+    for (int t = 0; t < nt; ++t)
+      if (gid[t] == gv) {
+        members.push_back(t);
+        for (int f = offsets_host[t]; f < offsets_host[t + 1]; ++f) rows.push_back(f);
+      }
+  }
+  mstart.push_back((int64_t)members.size());
+  rstart.push_back((int64_t)rows.size());
+  int maxm = 0;
+  for (size_t q = 0; q + 1 < mstart.size(); ++q) maxm = std::max<int>(maxm, (int)(mstart[q + 1] - mstart[q]));
+  const int ksplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, nf / 2048));
+
+  auto plan = [&](Arena& ar, float** mu_c, float** mu, int32_t** dm, int32_t** dr, float** part, float** G,
+                  float** B, float** Wt, float** P, float** R, float** tr) {
+    *mu_c = ar.take<float>((size_t)nt * d);
+    *mu = ar.take<float>((size_t)d);
+    *dm = ar.take<int32_t>(members.size());
+    *dr = ar.take<int32_t>(rows.size());
+    *part = mode == 0 ? ar.take<float>((size_t)ksplit * d * d) : nullptr;
+    *G = mode == 0 ? ar.take<float>((size_t)d * d) : nullptr;
+    *B = ar.take<float>((size_t)maxm * d);
+    *Wt = ar.take<float>((size_t)maxm * d);
+    *P = ar.take<float>((size_t)maxm * d);
+    *R = ar.take<float>((size_t)maxm * d);
+    *tr = ar.take<float>(64);
+  };
+  float *mu_c, *mu, *part, *G, *B, *Wt, *P, *R, *tr;
+  int32_t *dm, *dr;
+  Arena dry;
+  plan(dry, &mu_c, &mu, &dm, &dr, &part, &G, &B, &Wt, &P, &R, &tr);
+  gcr_status s = ensure_ws(c, dry.off);
+  if (s != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan(ar, &mu_c, &mu, &dm, &dr, &part, &G, &B, &Wt, &P, &R, &tr);
+  HIP_TRY(c, hipMemcpyAsync(dm, members.data(), members.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(dr, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, st));
+  launch_segment_means(frames, offsets, nt, d, mu_c, st);
+  if (mode == 1) {
+    launch_normalize_rows(mu_c, W_out, nt, d, st);
+    HIP_TRY(c, hipStreamSynchronize(st));
+    HIP_TRY(c, hipGetLastError());
+    return GCR_OK;
+  }
+  for (size_t q = 0; q + 1 < mstart.size(); ++q) {
+    const int nm = (int)(mstart[q + 1] - mstart[q]);
+    const int64_t nr = rstart[q + 1] - rstart[q];
+    const int32_t* mem = dm + mstart[q];
+    const int32_t* rw = dr + rstart[q];
+    launch_group_mean(mu_c, offsets, mem, nm, d, mu, st);
+    const float shift = lambda * (float)nr;
+    const int ks = (int)std::min<int64_t>(ksplit, std::max<int64_t>(1, nr / 32));
+    launch_gram(frames, rw, nr, d, part, ks, G, shift, st);
+    // spectrum bounds of M = F^T F + lambda n I: [lambda n, lambda n + tr(F^T F)]
+    std::vector<float> diag(d);
+    HIP_TRY(c, hipMemcpy2DAsync(diag.data(), sizeof(float), G, (size_t)(d + 1) * sizeof(float), sizeof(float), d,
+                                hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    double trace = 0.0;
+    for (int e = 0; e < d; ++e) trace += (double)diag[e] - shift;
+    trace = std::max(trace, 0.0) * 1.0001 + 1e-6 * shift;
+    const double lmin = shift, lmax = shift + trace;
+    const double dd = 0.5 * (lmax + lmin), cc = 0.5 * (lmax - lmin);
+    const double kap = lmax / lmin;
+    const double rate = (sqrt(kap) + 1.0) / std::max(sqrt(kap) - 1.0, 1e-30);
+    int iters = (int)ceil(log(2.0 / 1e-9) / log(std::max(rate, 1.0000001))) + 2;
+    iters = std::max(2, std::min(iters, 400));
+    launch_build_rhs(mu_c, mu, mem, nm, d, B, st);
+    const int64_t tot = (int64_t)nm * d;
+    fill_u32(Wt, 0u, tot, st);
+    fill_u32(P, 0u, tot, st);
+    // Chebyshev iteration on M W^T = B^T (rows of W are profile vectors;
+    // M is symmetric so W M is the row form of M w_c).
+    double alpha_c = 0.0, beta_c = 0.0;
+    for (int it = 0; it < iters; ++it) {
+      // R = B - W M
+      launch_gemm_nn_f32(Wt, d, G, d, R, d, nm, d, d, -1.0f, 1.0f, B, d, st);
+      if (it == 0) {
+        alpha_c = 1.0 / dd;
+        beta_c = 0.0;
+      } else if (it == 1) {
+        beta_c = 0.5 * (cc * alpha_c) * (cc * alpha_c);
+        alpha_c = 1.0 / (dd - beta_c / alpha_c);
+      } else {
+        beta_c = (cc * alpha_c * 0.5) * (cc * alpha_c * 0.5);
+        alpha_c = 1.0 / (dd - beta_c / alpha_c);
+      }
+      launch_cheb_update(Wt, P, R, (float)beta_c, (float)alpha_c, tot, st);
+    }
+    launch_normalize_rows(Wt, Wt, nm, d, st);
+    launch_scatter_profiles(Wt, mem, nm, d, W_out, st);
+  }
+  HIP_TRY(c, hipStreamSynchronize(st));
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Shared device helpers for the GCR kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GCR_WAVE 64
+
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) int i32x4;
+
+// ---------------------------------------------------------------------------
+// Order-preserving map float -> uint32 (total order for non-NaN values).
+__device__ __forceinline__ uint32_t ord_f32(float f) {
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t o) {
+  uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(b);
+}
+// Candidate entry: (screened key, column) packed so that unsigned order is
+// (key, column) lexicographic.
+__device__ __forceinline__ uint64_t pack_cand(float key, uint32_t col) {
+  return ((uint64_t)ord_f32(key) << 32) | (uint64_t)col;
+}
+__device__ __forceinline__ float cand_key(uint64_t e) { return unord_f32((uint32_t)(e >> 32)); }
+__device__ __forceinline__ uint32_t cand_col(uint64_t e) { return (uint32_t)e; }
+#define GCR_EMPTY (~0ull)
+
+// ---------------------------------------------------------------------------
+// Error-free float transformations (Knuth two-sum, FMA two-product).  The
+// library is built with -ffp-contract=off so that these stay exact.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  e = b - (s - a);
+}
+// float-float accumulate (hi, lo) += (a_hi, a_lo)
+__device__ __forceinline__ void ff_add(float& hi, float& lo, float ahi, float alo) {
+  float s, e;
+  two_sum(hi, ahi, s, e);
+  e += lo + alo;
+  fast_two_sum(s, e, hi, lo);
+}
+// (hi, lo) += (a - b)^2 with the difference and square kept exact to
+// float-float precision.
+__device__ __forceinline__ void ff_acc_sqdiff(float& hi, float& lo, float a, float b) {
+  float dh, dl;
+  two_sum(a, -b, dh, dl);              // dh + dl = a - b exactly
+  float p = dh * dh;
+  float pe = fmaf(dh, dh, -p);         // p + pe = dh^2 exactly
+  pe = fmaf(2.0f * dh, dl, pe);        // + 2 dh dl (dl^2 is below float-float)
+  float s, e;
+  two_sum(hi, p, s, e);
+  lo += e + pe;
+  hi = s;
+}
+
+// ---------------------------------------------------------------------------
+// wave reductions
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ void wave_ff_sum(float& hi, float& lo) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    float oh = __shfl_xor(hi, o, 64);
+    float ol = __shfl_xor(lo, o, 64);
+    ff_add(hi, lo, oh, ol);
+  }
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl_xor(lo, m, 64);
+  hi = __shfl_xor(hi, m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl(lo, src, 64);
+  hi = __shfl(hi, src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort (ascending) of E*64 uint64 values held by one wave; element
+// e = j * 64 + lane lives in v[j].
+template <int E>
+__device__ __forceinline__ void wave_bitonic_sort(uint64_t (&v)[E]) {
+  const int lane = threadIdx.x & 63;
+  constexpr int N = E * 64;
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= 64) {
+        const int rs = stride >> 6;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          if ((j & rs) == 0) {
+            const int e = j * 64 + lane;
+            const bool asc = (e & size) == 0;
+            uint64_t a = v[j], b = v[j | rs];
+            bool sw = asc ? (a > b) : (a < b);
+            v[j] = sw ? b : a;
+            v[j | rs] = sw ? a : b;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int e = j * 64 + lane;
+          const bool asc = (e & size) == 0;
+          const bool lower = (lane & stride) == 0;
+          uint64_t o = shfl_xor_u64(v[j], stride);
+          uint64_t mn = v[j] < o ? v[j] : o;
+          uint64_t mx = v[j] < o ? o : v[j];
+          v[j] = (lower == asc) ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
+// Margin of the screening: the screened key n2_c - 2 s~ of row r differs
+// from the exact n2_c - 2 s by at most the returned bound.
+//   eps_s : bound on |s~ - s| / (||x_r|| ||x_c||) for the precision mode
+//   eps_n : bound on the relative error of the float32 squared norms
+__device__ __forceinline__ float screen_margin(float n2r, float maxn2, float eps_s, float eps_n) {
+  float nr = sqrtf(n2r), nm = sqrtf(maxn2);
+  float es = eps_s * nr * nm;
+  // final float32 rounding of the key (|key| <= maxn2 + 2 nr nm)
+  float er = 6.0e-8f * (maxn2 + 2.0f * nr * nm);
+  return (2.0f * es + eps_n * maxn2 + er) * 1.0001f;
+}

@@ -1,0 +1,165 @@
+// Sparse symmetric affinity graph from the kNN lists (Eq. (4)-(9)).
+//
+//   w_ij = beta(cam_i, cam_j) exp(-d_ij / gamma)   for j in N_i     (Eq. (4))
+//   A = (A~ + A~^T) / 2 is never formed: row i keeps its forward list
+//   (weight w_ij / 2) and a reverse list of the edges j -> i (weight
+//   w_ji / 2); a mutual pair simply appears in both, which sums to A_ij.
+//   D_i = 1 + sum_fwd w/2 + sum_rev w/2                              (Eq. (5), (7))
+//   P_ij = A_ij / sqrt(D_i D_j), P_ii = 1 / D_i                       (Eq. (2))
+// The reverse lists are a CSR built by a count / exclusive scan / scatter,
+// then each row is sorted by source so that sums run in a fixed order.
+#include "kernels.h"
+
+namespace gcr {
+
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void edge_weight_kernel(GraphBuildArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int ci = (a.use_beta && a.cam) ? a.cam[i] : 0;
+  float fs = 0.f;
+  for (int s = 0; s < a.k; ++s) {
+    const int64_t e = i * a.k + s;
+    const int j = a.idx[e];
+    float wv = 0.f;
+    if (j >= 0) {
+      wv = expf(-a.dist[e] / a.gamma);
+      if (a.use_beta && a.cam) wv *= (a.cam[j] == ci) ? a.beta_same : a.beta_cross;
+      atomicAdd(&a.tmp_cnt[j], 1);
+    }
+    a.w[e] = wv;
+    fs += wv;
+  }
+  a.tmp_fsum[i] = fs;
+}
+
+// exclusive scan of tmp_cnt into rev_ptr (n+1 entries): block-local scans of
+// 1024-entry tiles, a scan of the tile totals, then the add-back.
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(const int32_t* in, int32_t* out,
+                                                          int64_t n, int32_t* tile_sum) {
+  __shared__ int32_t s[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int32_t v = i < n ? in[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int32_t t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) out[i] = s[threadIdx.x] - v;
+  if (threadIdx.x == 1023) tile_sum[blockIdx.x] = s[1023];
+}
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int32_t* tile_sum, int ntiles, int32_t* total) {
+  __shared__ int32_t carry;
+  __shared__ int32_t s[1024];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int32_t v = i < ntiles ? tile_sum[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int32_t t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ntiles) tile_sum[i] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+__global__ void scan_add_kernel(int32_t* out, int64_t n, const int32_t* tile_sum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_sum[i >> 10];
+}
+
+__global__ void rev_scatter_kernel(GraphBuildArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n * a.k) return;
+  const int j = a.idx[e];
+  if (j < 0) return;
+  const int pos = a.rev_ptr[j] + atomicAdd(&a.tmp_cnt[j], 1);
+  a.rev_src[pos] = (int32_t)(e / a.k);
+  a.rev_w[pos] = a.w[e];
+}
+
+// Sort each reverse row by source (one thread per row; rows are short) and
+// compute the degree.
+__global__ void rev_sort_degree_kernel(GraphBuildArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int b = a.rev_ptr[i], e = a.rev_ptr[i + 1];
+  for (int p = b + 1; p < e; ++p) {
+    const int32_t s = a.rev_src[p];
+    const float wv = a.rev_w[p];
+    int q = p - 1;
+    while (q >= b && a.rev_src[q] > s) {
+      a.rev_src[q + 1] = a.rev_src[q];
+      a.rev_w[q + 1] = a.rev_w[q];
+      --q;
+    }
+    a.rev_src[q + 1] = s;
+    a.rev_w[q + 1] = wv;
+  }
+  float rs = 0.f;
+  for (int p = b; p < e; ++p) rs += a.rev_w[p];
+  a.deg[i] = 1.0f + 0.5f * a.tmp_fsum[i] + 0.5f * rs;
+}
+
+__global__ void values_kernel(GraphBuildArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float di = a.deg[i];
+  for (int s = 0; s < a.k; ++s) {
+    const int64_t e = i * a.k + s;
+    const int j = a.idx[e];
+    a.pf[e] = j >= 0 ? a.coef * 0.5f * a.w[e] / sqrtf(di * a.deg[j]) : 0.f;
+  }
+  const int b = a.rev_ptr[i], en = a.rev_ptr[i + 1];
+  for (int p = b; p < en; ++p) a.pr[p] = a.coef * 0.5f * a.rev_w[p] / sqrtf(di * a.deg[a.rev_src[p]]);
+}
+
+__global__ void self_kernel(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = alpha / deg[i];
+  if (cr_deg) s += (1.0f - alpha) / cr_deg[i];
+  self[i] = s;
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_graph_build(const GraphBuildArgs& a, hipStream_t st) {
+  const int64_t n = a.n;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a.tmp_cnt, n);
+  hipLaunchKernelGGL(edge_weight_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a);
+  const int ntiles = (int)((n + 1023) / 1024);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(ntiles), dim3(1024), 0, st, a.tmp_cnt, a.rev_ptr, n, a.tmp_blk);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, a.tmp_blk, ntiles, a.rev_ptr + n);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a.rev_ptr, n, a.tmp_blk);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a.tmp_cnt, n);
+  if (n * a.k > 0)
+    hipLaunchKernelGGL(rev_scatter_kernel, dim3(nblk(n * a.k, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(rev_sort_degree_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a);
+}
+
+void launch_finish_values(const GraphBuildArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(values_kernel, dim3(nblk(a.n, 256)), dim3(256), 0, st, a);
+}
+
+void launch_self_coef(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(self_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, deg, cr_deg, alpha, self);
+}
+
+}  // namespace gcr

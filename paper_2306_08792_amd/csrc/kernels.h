@@ -1,0 +1,120 @@
+// Internal launchers shared between the kernel files and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+#define GCR_PREC_FP32 0
+#define GCR_PREC_BF16 1
+#define GCR_PREC_FP8 2
+
+namespace gcr {
+
+// ---- prep.hip
+void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st);
+void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,
+                        int64_t ld_bytes, float* n2, float* scale, unsigned* maxn2_bits,
+                        hipStream_t st);
+
+// ---- simtopk.hip : fused MFMA similarity tiles + streaming per-row top-k
+struct SimArgs {
+  const uint8_t* Xs;  // screening operand, [npad, ld_bytes]
+  int64_t ld_bytes;   // multiple of 128
+  int kchunks;        // ld_bytes / 128
+  const float* n2;    // [npad]
+  const float* scale; // [npad] FP8 row scales or nullptr
+  const int* cam;     // [n] or nullptr
+  const float* maxn2; // device scalar
+  int64_t r0, r1;     // rows [r0, r1)
+  int64_t c0, c1;     // columns [c0, c1)
+  int64_t W;          // split width (multiple of 128)
+  int S;              // number of column splits (multiple of 8)
+  int RB;             // row blocks of 128
+  int exclude_self;   // skip column == row
+  int k0, k1;         // list sizes (global, cross)
+  int C;              // candidate capacity per (row, list, split)
+  float eps_s, eps_n; // screening error coefficients
+  uint64_t* cand;     // [(r1-r0), NL, S, C]
+  int* cnt;           // [(r1-r0), NL, S]; -1 marks a full buffer
+};
+int sim_topk_grid(int RB, int S);
+void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
+
+// ---- refine.hip : union of split candidates, exact re-score, selection
+struct RefineArgs {
+  const uint64_t* cand;
+  const int* cnt;
+  int S, C, NL;
+  int k0, k1;
+  int64_t r0, r1, c0, c1;
+  int exclude_self;
+  const float* X;     // [n, d] float32 features (exact re-score)
+  int d;
+  const int* cam;
+  const float* n2;
+  const float* maxn2;
+  float eps_s, eps_n;
+  int32_t* idx0; float* dist0;   // [(r1-r0), k0]
+  int32_t* idx1; float* dist1;   // [(r1-r0), k1] (cross list) or nullptr
+  int* fb_list;       // [(r1-r0) * NL] packed (row_rel * 2 + list)
+  int* fb_count;      // device counter
+  unsigned long long* stat_cands;  // device counter
+  uint64_t* fb_scratch;            // [fb_grid, c1 - c0]
+  int fb_grid;
+};
+void launch_refine(const RefineArgs& a, hipStream_t st);
+
+// ---- graph.hip : affinities, reverse CSR, degrees, normalised values
+struct GraphBuildArgs {
+  int64_t n; int k;
+  const int32_t* idx; const float* dist;
+  const int* cam; float beta_same, beta_cross; int use_beta;
+  float gamma;
+  float* w; int32_t* rev_ptr; int32_t* rev_src; float* rev_w; float* deg;
+  float* pf; float* pr;
+  float coef;          // alpha or 1 - alpha
+  int32_t* tmp_cnt;    // [n]
+  float* tmp_fsum;     // [n]
+  int32_t* tmp_blk;    // scan block sums
+};
+void launch_graph_build(const GraphBuildArgs& a, hipStream_t st);
+void launch_self_coef(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self,
+                      hipStream_t st);
+void launch_finish_values(const GraphBuildArgs& a, hipStream_t st);
+
+// ---- propagate.hip
+struct PropArgs {
+  const float* X; float* Y; int64_t n; int d;
+  const float* self;
+  const int32_t* idx; const float* pf; int k;
+  const int32_t* rev_ptr; const int32_t* rev_src; const float* pr;
+  const int32_t* cr_idx; const float* cr_pf; int ck;
+  const int32_t* cr_rev_ptr; const int32_t* cr_rev_src; const float* cr_pr;
+};
+void launch_propagate(const PropArgs& a, hipStream_t st);
+
+// ---- final.hip : dense squared distances between two row ranges
+void launch_dense_dist(const uint8_t* Xs, int64_t ld_bytes, int kchunks, const float* n2,
+                       int64_t q0, int64_t nq, int64_t g0, int64_t ng, float* out,
+                       hipStream_t st);
+
+// ---- pvg.hip : tracklet profile vectors
+void launch_segment_means(const float* frames, const int32_t* offsets, int nt, int d,
+                          float* mu_c, hipStream_t st);
+void launch_group_mean(const float* mu_c, const int32_t* offsets, const int32_t* members,
+                       int nm, int d, float* mu, hipStream_t st);
+void launch_gram(const float* frames, const int32_t* rows, int64_t nrows, int d, float* partial,
+                 int ksplit, float* G, float shift, hipStream_t st);
+void launch_gemm_nn_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,
+                        int64_t ldc, int M, int N, int K, float alpha, float beta,
+                        const float* Cin, int64_t ldcin, hipStream_t st);
+void launch_build_rhs(const float* mu_c, const float* mu, const int32_t* members, int nm, int d,
+                      float* B, hipStream_t st);
+void launch_scatter_profiles(const float* Wt, const int32_t* members, int nm, int d, float* W,
+                             hipStream_t st);
+void launch_axpby(float* y, const float* x, float a, float b, int64_t n, hipStream_t st);
+void launch_cheb_update(float* Wk, float* Wprev, const float* R, float rho, float cR, int64_t n,
+                        hipStream_t st);
+
+}  // namespace gcr

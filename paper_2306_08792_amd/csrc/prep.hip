@@ -1,0 +1,109 @@
+// Input preparation: row normalisation, squared norms and the padded
+// low-precision copies that the similarity screening reads.
+#include "kernels.h"
+
+namespace gcr {
+
+// One wave per row: Y[i] = X[i] / max(||X[i]||, 1e-12).
+__global__ __launch_bounds__(256) void normalize_rows_kernel(const float* __restrict__ X,
+                                                             float* Y, int64_t n, int d) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const float* x = X + row * d;
+  float s = 0.f;
+  for (int e = lane; e < d; e += 64) s = fmaf(x[e], x[e], s);
+  s = wave_sum(s);
+  const float inv = 1.0f / fmaxf(sqrtf(s), 1e-12f);
+  float* y = Y + row * d;
+  for (int e = lane; e < d; e += 64) y[e] = x[e] * inv;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP E4M3 (bias 7, max 448, no infinities), round to nearest even,
+// saturating at +-448.
+__device__ __forceinline__ uint8_t f32_to_e4m3_rne(float x) {
+  uint32_t sign = (__float_as_uint(x) >> 31) << 7;
+  float a = fminf(fabsf(x), 448.0f);
+  if (a < 0.015625f) {  // below 2^-6: subnormal grid 2^-9
+    return (uint8_t)(sign | (uint32_t)rintf(a * 512.0f));
+  }
+  int e;
+  frexpf(a, &e);  // a = f 2^e, f in [0.5, 1)
+  int E = e - 1;
+  float q = rintf(ldexpf(a, 3 - E));  // in [8, 16]
+  if (q >= 16.0f) { E += 1; q = 8.0f; }
+  return (uint8_t)(sign | ((uint32_t)(E + 7) << 3) | ((uint32_t)q - 8u));
+}
+
+// One wave per padded row.  Writes the screening operand (row stride
+// ld_bytes, zero padding past d and past n), n2[i] = ||x_i||^2 (float32),
+// the FP8 per-row scale, and the maximum n2 (atomic max on the bit pattern,
+// valid for non-negative floats).
+template <int PREC>
+__global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restrict__ X, int64_t n,
+                                                          int d, int64_t npad, uint8_t* Xs,
+                                                          int64_t ld_bytes, float* n2,
+                                                          float* scale, unsigned* maxn2_bits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= npad) return;
+  uint8_t* out = Xs + row * ld_bytes;
+  if (row >= n) {
+    for (int64_t b = lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
+    if (lane == 0) { n2[row] = 0.f; if (scale) scale[row] = 0.f; }
+    return;
+  }
+  const float* x = X + row * d;
+  float s = 0.f, amax = 0.f;
+  for (int e = lane; e < d; e += 64) {
+    float v = x[e];
+    s = fmaf(v, v, s);
+    amax = fmaxf(amax, fabsf(v));
+  }
+  s = wave_sum(s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) {
+    n2[row] = s;
+    atomicMax(maxn2_bits, __float_as_uint(s));
+  }
+  if (PREC == GCR_PREC_FP32) {
+    float* o = (float*)out;
+    const int64_t cnt = ld_bytes / 4;
+    for (int64_t e = lane; e < cnt; e += 64) o[e] = e < d ? x[e] : 0.f;
+  } else if (PREC == GCR_PREC_BF16) {
+    uint16_t* o = (uint16_t*)out;
+    const int64_t cnt = ld_bytes / 2;
+    for (int64_t e = lane; e < cnt; e += 64) o[e] = e < d ? f32_to_bf16_rne(x[e]) : (uint16_t)0;
+  } else {
+    const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
+    if (lane == 0) scale[row] = sc;
+    for (int64_t e = lane; e < ld_bytes; e += 64) out[e] = e < d ? f32_to_e4m3_rne(x[e] / sc) : (uint8_t)0;
+  }
+}
+
+void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(normalize_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, Y, n, d);
+}
+
+void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,
+                        int64_t ld_bytes, float* n2, float* scale, unsigned* maxn2_bits,
+                        hipStream_t st) {
+  dim3 g((unsigned)((npad + 3) / 4)), b(256);
+  uint8_t* xs = (uint8_t*)Xs;
+  if (prec == GCR_PREC_FP32)
+    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP32>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, maxn2_bits);
+  else if (prec == GCR_PREC_BF16)
+    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_BF16>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, maxn2_bits);
+  else
+    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP8>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, maxn2_bits);
+}
+
+}  // namespace gcr

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, every
+function include/gcr.h declares is exported, the host-only helpers agree with
+the Python marshalling, and the generators keep their documented shapes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2306_08792_amd import _lib as L
+from paper_2306_08792_amd import datagen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "gcr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(gcr_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libgcr.so is not built (python -m paper_2306_08792_amd.build)")
+    return L.load()
+
+
+def test_header_declares_expected_entry_points():
+    fns = header_functions()
+    for name in ["gcr_knn", "gcr_build_graph", "gcr_propagate", "gcr_rerank", "gcr_final_distances",
+                 "gcr_profile_vectors", "gcr_normalize_rows"]:
+        assert name in fns
+    assert set(fns) == set(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), f"{name} not exported"
+
+
+def test_params_default(lib):
+    p = L.GcrParams()
+    lib.gcr_params_default(C.byref(p))
+    assert (p.k, p.rounds, p.rebuild_each_round, p.normalize_input, p.symmetric) == (15, 3, 1, 1, 1)
+    assert abs(p.gamma - 0.2) < 1e-7 and abs(p.lambda_ - 10.0) < 1e-6 and p.alpha == 1.0
+
+
+def test_struct_sizes_match_header():
+    assert C.sizeof(L.GcrParams) == 13 * 4
+    assert C.sizeof(L.GcrGraph) == 8 + 4 * 4 + 19 * 8
+
+
+def test_graph_bytes_and_bind_layout(lib):
+    n, k = 1000, 20
+    nb = lib.gcr_graph_bytes(n, k, -1, 0)
+    nbx = lib.gcr_graph_bytes(n, k, 7, 1)
+    assert nb > n * k * 4 * 6 and nbx > nb
+    buf = (C.c_char * (nbx + 512))()
+    base = (C.addressof(buf) + 255) // 256 * 256
+    g = L.GcrGraph()
+    assert lib.gcr_graph_bind(C.byref(g), C.c_void_p(base), n, k, 7, 1) == 0
+    assert (g.n, g.k, g.cross_k, g.has_cross) == (n, k, 7, 1)
+    ptrs = [getattr(g, f) for f, _ in L.GcrGraph._fields_[5:]]
+    assert all(p is not None and base <= p < base + nbx for p in ptrs)
+    assert len(set(ptrs)) == len(ptrs)
+    assert all(p % 256 == 0 for p in ptrs)
+    assert lib.gcr_graph_bind(C.byref(g), C.c_void_p(base + 4), n, k, 7, 1) != 0  # misaligned
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.gcr_destroy(None) == -1
+    assert lib.gcr_last_error(None) == b"context is NULL"
+
+
+def test_generators_shapes_and_determinism():
+    w = datagen.plain_gcr_small()
+    assert w.X.shape == (2000, 256) and w.X.dtype == np.float32
+    np.testing.assert_allclose(np.linalg.norm(w.X.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    assert np.array_equal(w.X, datagen.plain_gcr_small().X)
+    assert (w.ids[:w.nq] == np.repeat(np.arange(100), 5)).all()
+    v = datagen.video_tracklets(nq=6, ng=10, d=16, n_ids=5)
+    lens = np.diff(v.offsets)
+    assert len(lens) == 16 and lens.min() >= 4 and lens.max() <= 32
+    assert v.frames.shape == (v.offsets[-1], 16)
+
+
+def test_serving_gallery_bf16_is_round_to_nearest_even():
+    bits, vals, _ = datagen.serving_gallery(ng=300, d=32, n_ids=10)
+    # re-derive from the float32 values: every value must be the bf16 nearest
+    # to some float32 within half a bf16 ulp, and the bit patterns decode back
+    assert np.array_equal((bits.astype(np.uint32) << 16).view(np.float32), vals)
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal(1000).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32) << 16
+    g = r.view(np.float32).astype(np.float64)
+    ulp = np.abs(g) * 2.0 ** -7
+    assert np.all(np.abs(g - f) <= ulp / 2 + 1e-45)

@@ -1,0 +1,286 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Small shapes span several 128-row tiles, ragged tails, tiny and odd feature
+widths, k = 0 / 1 / large, all three screening precisions and camera lists.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gcr_oracle as O
+from paper_2306_08792_amd import datagen
+from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params
+
+from parity import (check_distances, check_features, check_knn_rows,
+                    oracle_round_from_lists)
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [FP32, BF16, FP8]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def case(n, d, seed, clustered=True):
+    if clustered and n >= 8:
+        per = max(2, n // max(1, n // 12))
+        nc = (n + per - 1) // per
+        X, _ = datagen.clustered(nc, per, d, 0.5, seed)
+        return X[:n]
+    return datagen.random_unit(n, d, seed)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,d,k,seed", [
+    (7, 3, 2, 0), (9, 1, 8, 1), (40, 16, 7, 2), (129, 64, 20, 3), (300, 300, 15, 4),
+    (517, 256, 20, 5), (260, 33, 1, 6), (200, 128, 120, 7),
+])
+def test_knn_matches_exhaustive(ctx, prec, n, d, k, seed):
+    print(f"knn prec={prec} n={n} d={d} k={k} seed={seed}", flush=True)
+    X = case(n, d, seed)
+    p = Params(k=k, precision=prec)
+    idx, dist = ctx.knn(dev(X), p)
+    check_knn_rows(host(idx), host(dist), X, np.arange(n), k)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_knn_cross_camera(ctx, prec):
+    print(f"knn cross prec={prec}", flush=True)
+    rng = np.random.default_rng(11)
+    n, d = 390, 96
+    X = case(n, d, 12)
+    cam = rng.integers(0, 4, size=n).astype(np.int32)
+    p = Params(k=10, cross_k=6, precision=prec, alpha=0.5)
+    idx, dist, cidx, cdist = ctx.knn(dev(X), p, dev(cam, torch.int32), cross=True)
+    check_knn_rows(host(idx), host(dist), X, np.arange(n), 10)
+    check_knn_rows(host(cidx), host(cdist), X, np.arange(n), 6, cam=cam, cross=True, what="cross")
+
+
+def test_knn_duplicates_force_fallback(ctx):
+    # 200 identical points: every screened key ties, the candidate buffers
+    # overflow and the exhaustive path must still return (distance, index)
+    # order, i.e. the lowest indices
+    print("knn duplicates", flush=True)
+    X = np.tile(datagen.random_unit(1, 64, 3), (200, 1))
+    ctx.reset_stats()
+    idx, dist = ctx.knn(dev(X), Params(k=20, precision=BF16))
+    st = ctx.stats()
+    I = host(idx)
+    for i in range(200):
+        exp = [j for j in range(200) if j != i][:20]
+        assert I[i].tolist() == exp
+    assert np.all(host(dist) == 0.0)
+    assert st["knn_fallback_rows"] > 0
+
+
+def test_knn_k0_and_empty_cross(ctx):
+    X = case(50, 8, 4)
+    idx, dist = ctx.knn(dev(X), Params(k=0))
+    assert idx.shape == (50, 0)
+    cam = np.zeros(50, dtype=np.int32)
+    i1, d1, ci, cd = ctx.knn(dev(X), Params(k=3, cross_k=3, alpha=0.5), dev(cam, torch.int32), cross=True)
+    assert np.all(host(ci) == -1) and np.all(np.isinf(host(cd)))
+
+
+def _oracle_graph_values(X, p, idx, cam=None, cr_idx=None):
+    n = len(X)
+    X = np.asarray(X, np.float64)
+    def dist_of(ix):
+        d = np.full(ix.shape, np.inf)
+        for i in range(n):
+            for s in range(ix.shape[1]):
+                j = ix[i, s]
+                if j >= 0:
+                    d[i, s] = np.sum((X[i] - X[j]) ** 2)
+        return d
+    At = O.affinity_dense(n, idx, dist_of(idx), p.gamma, O._edge_scale(idx, cam, p))
+    P, A, Dg = O.sym_propagation_matrix(At)
+    return P, Dg
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_build_graph_values(ctx, prec):
+    print(f"graph prec={prec}", flush=True)
+    n, d = 333, 48
+    X = case(n, d, 21)
+    p = Params(k=9, gamma=0.3, precision=prec)
+    g = ctx.build_graph(dev(X), p)
+    idx = host(g.field("idx")).astype(np.int64)
+    check_knn_rows(idx, host(g.field("dist")), X, np.arange(n), 9)
+    P, Dg = _oracle_graph_values(X, O.Params(k=9, gamma=0.3), idx)
+    np.testing.assert_allclose(host(g.field("deg")), Dg, rtol=2e-6)
+    pf = host(g.field("pf"))
+    for i in range(n):
+        for s in range(9):
+            j = idx[i, s]
+            # forward value = half of A_ij's forward part / sqrt(D_i D_j)
+            wij = math.exp(-np.sum((X[i].astype(np.float64) - X[j]) ** 2) / 0.3)
+            assert abs(pf[i, s] - 0.5 * wij / math.sqrt(Dg[i] * Dg[j])) < 2e-6 * max(1.0, pf[i, s])
+    rp, rs, pr = host(g.field("rev_ptr")), host(g.field("rev_src")), host(g.field("pr"))
+    dense = np.zeros((n, n))
+    for i in range(n):
+        dense[i, idx[i]] += pf[i]
+        for q in range(rp[i], rp[i + 1]):
+            dense[i, rs[q]] += pr[q]
+        assert np.all(np.diff(rs[rp[i]:rp[i + 1]]) > 0), "reverse row not sorted by source"
+        dense[i, i] += host(g.field("self"))[i]
+    np.testing.assert_allclose(dense, P, atol=2e-6)
+    assert rp[-1] == n * 9
+
+
+@pytest.mark.parametrize("d", [3, 64, 256, 512, 700])
+def test_propagate_one_round(ctx, d):
+    print(f"propagate d={d}", flush=True)
+    n = 290
+    X = case(n, d, 30 + d)
+    p = Params(k=7, gamma=0.2)
+    Xd = dev(X)
+    g = ctx.build_graph(Xd, p)
+    Y = ctx.propagate(g, Xd)
+    Yo, _, _ = oracle_round_from_lists(X, O.Params(k=7, gamma=0.2), host(g.field("idx")))
+    check_features(host(Y), Yo)
+
+
+def test_propagate_rejects_in_place(ctx):
+    X = dev(case(40, 8, 1))
+    g = ctx.build_graph(X, Params(k=3))
+    with pytest.raises(Exception):
+        ctx.propagate(g, X, out=X)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_final_distances_dense_and_topk(ctx, prec):
+    print(f"final prec={prec}", flush=True)
+    nq, ng, d = 150, 700, 72
+    X = case(nq + ng, d, 40)
+    p = Params(topk_out=25, precision=prec)
+    D, ti, td = ctx.final_distances(dev(X), nq, p, dense=True, topk=True)
+    Do = O.final_distances(X, nq)
+    check_distances(host(D), Do)
+    check_knn_rows(host(ti), host(td), X, np.arange(nq), 25, cols=np.arange(nq, nq + ng),
+                   exclude_self=False, what="final top-K")
+
+
+def _stagewise_rerank(ctx, X, nq, p, op, cam=None, prec=FP32):
+    """Run the rounds one at a time through the C ABI and check each stage
+    against the oracle fed with the GPU's previous features."""
+    Xd = ctx.normalize_rows(dev(X))
+    Xh = host(Xd)
+    np.testing.assert_allclose(Xh, O.row_normalize(X), atol=3e-7)
+    camd = None if cam is None else dev(cam, torch.int32)
+    g = None
+    for t in range(p.rounds):
+        if g is None or p.rebuild_each_round:
+            g = ctx.build_graph(Xd, p, camd)
+            Xgraph = Xh
+            n = Xh.shape[0]
+            check_knn_rows(host(g.field("idx")), host(g.field("dist")), Xh, np.arange(n), p.k)
+            if g.has_cross:
+                check_knn_rows(host(g.field("cr_idx")), host(g.field("cr_dist")), Xh, np.arange(n),
+                               g.cross_k, cam=cam, cross=True, what="cross")
+        Yd = ctx.propagate(g, Xd)
+        Yo, _, _ = oracle_round_from_lists(Xh, op, host(g.field("idx")),
+                                           host(g.field("cr_idx")) if g.has_cross else None, cam,
+                                           X_graph=Xgraph)
+        check_features(host(Yd), Yo, what=f"round {t + 1}")
+        Xd, Xh = Yd, host(Yd)
+    return Xd
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("rebuild", [True, False])
+def test_rerank_small_plain(ctx, prec, rebuild):
+    print(f"rerank small prec={prec} rebuild={rebuild}", flush=True)
+    X, _ = datagen.clustered(40, 9, 64, 0.5, 50)
+    nq = 90
+    p = Params(k=8, gamma=0.2, rounds=3, rebuild_each_round=rebuild, precision=prec)
+    op = O.Params(k=8, gamma=0.2, rounds=3, rebuild_each_round=rebuild)
+    XT = _stagewise_rerank(ctx, X, nq, p, op)
+    out = ctx.rerank(dev(X), nq, p, dense=True, topk=True, keep_features=True)
+    # the fused entry point must equal the step-by-step calls bit for bit
+    np.testing.assert_array_equal(host(out["X"]), host(XT))
+    check_distances(host(out["dist"]), O.final_distances(host(XT), nq))
+    # and the independent FP64 run from X_0
+    ref = O.gcr(X, op)
+    check_features(host(out["X"]), ref["X"][-1], what="end-to-end features")
+    check_distances(host(out["dist"]), O.final_distances(ref["X"][-1], nq), what="end-to-end distances")
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.5, (1.0, 1.0)), (0.7, (1.0, 1.0)), (1.0, (0.5, 1.0))])
+def test_rerank_cross_camera(ctx, alpha, beta):
+    print(f"rerank cross alpha={alpha} beta={beta}", flush=True)
+    w = datagen.cross_camera_reid(seed=3, nq=120, ng=500, d=128, n_ids=60, n_cams=4)
+    p = Params(k=10, gamma=0.2, rounds=3, alpha=alpha, beta_same=beta[0], beta_cross=beta[1])
+    op = O.Params(k=10, gamma=0.2, rounds=3, alpha=alpha, beta_same=beta[0], beta_cross=beta[1])
+    XT = _stagewise_rerank(ctx, w.X, w.nq, p, op, cam=w.cams)
+    out = ctx.rerank(dev(w.X), w.nq, p, dev(w.cams, torch.int32), dense=True, keep_features=True)
+    np.testing.assert_array_equal(host(out["X"]), host(XT))
+    ref = O.gcr(w.X, op, w.cams)
+    check_features(host(out["X"]), ref["X"][-1], what="end-to-end features")
+    check_distances(host(out["dist"]), O.final_distances(ref["X"][-1], w.nq), what="end-to-end distances")
+
+
+def test_rerank_k0_is_normalisation(ctx):
+    X = case(70, 20, 5)
+    out = ctx.rerank(dev(X), 10, Params(k=0, rounds=2), keep_features=True)
+    np.testing.assert_allclose(host(out["X"]), O.row_normalize(X), atol=3e-7)
+
+
+@pytest.mark.parametrize("mode", ["pvg", "mean"])
+@pytest.mark.parametrize("groups", [False, True])
+def test_profile_vectors(ctx, mode, groups):
+    print(f"pvg mode={mode} groups={groups}", flush=True)
+    w = datagen.video_tracklets(seed=2, nq=30, ng=90, d=200, n_ids=25)
+    nt = len(w.offsets) - 1
+    grp = (np.arange(nt) % 3).astype(np.int32) if groups else None
+    W = ctx.profile_vectors(dev(w.frames), torch.from_numpy(w.offsets), None if grp is None else torch.from_numpy(grp),
+                            mode=mode, lam=10.0)
+    Wo = O.profile_vectors(w.frames, w.offsets, grp, lam=10.0, mode=mode)
+    check_features(host(W), Wo, what="profiles")
+
+
+def test_profile_vectors_small_lambda(ctx):
+    w = datagen.video_tracklets(seed=4, nq=10, ng=30, d=64, n_ids=10)
+    W = ctx.profile_vectors(dev(w.frames), torch.from_numpy(w.offsets), None, mode="pvg", lam=0.05)
+    Wo = O.profile_vectors(w.frames, w.offsets, None, lam=0.05)
+    check_features(host(W), Wo, what="profiles")
+
+
+def test_gcrv_small(ctx):
+    w = datagen.video_tracklets(seed=5, nq=40, ng=120, d=128, n_ids=30)
+    p = Params(k=6, gamma=0.2, rounds=2, lam=10.0)
+    out = ctx.gcrv(dev(w.frames), torch.from_numpy(w.offsets), 40, p, dense=True)
+    ref = O.gcrv(w.frames, w.offsets, None, 40, O.Params(k=6, gamma=0.2, rounds=2, lam=10.0))
+    check_features(host(out["W"]), ref["W"], what="profiles")
+    check_features(host(out["X"]), ref["X"][-1], what="gcrv features")
+    check_distances(host(out["dist"]), O.final_distances(ref["X"][-1], 40))
+
+
+def test_plain_gcr_small_workload(ctx):
+    """The 500 + 1,500 x 256 workload end to end (k 20, gamma 0.1, 2 rounds)."""
+    w = datagen.plain_gcr_small()
+    p = Params(k=20, gamma=0.1, rounds=2)
+    op = O.Params(k=20, gamma=0.1, rounds=2)
+    XT = _stagewise_rerank(ctx, w.X, w.nq, p, op)
+    out = ctx.rerank(dev(w.X), w.nq, p, dense=True, topk=True, keep_features=True)
+    np.testing.assert_array_equal(host(out["X"]), host(XT))
+    check_distances(host(out["dist"]), O.final_distances(host(XT), w.nq))
+    from oracle.metrics import mean_average_precision
+    m = mean_average_precision(host(out["dist"]), w.ids[:w.nq], w.ids[w.nq:])
+    assert m >= 0.99
