@@ -33,6 +33,8 @@
  *     gcr_last_error(ctx) returns its message.  Nothing throws across the ABI.
  *     Argument checks happen on the host before anything is enqueued.
  *   Threads: a gcr_ctx must be used by one host thread at a time.
+ *   Feature width: d <= 2048 for every entry point that takes features
+ *     (GCR_ERR_UNSUPPORTED above), d <= 8192 for gcr_profile_vectors.
  *   Neighbour lists: row i lists its k nearest other rows j != i, ordered by
  *     (squared distance, j) ascending; rows with fewer than k eligible
  *     neighbours are padded with index -1 and distance +inf.

@@ -151,9 +151,12 @@ float eps_norm(int d) {
   return (float)(m * u23 / (1.0 - m * u23) * 1.01);
 }
 
-int capacity_for(int prec, int kmax) {
+// Candidate capacity per (row, list, split).  Two-list (cross-camera) runs
+// get room for a wider band: a cross list's k-th neighbour often lies among
+// many unrelated items at nearly equal distance.
+int capacity_for(int prec, int kmax, int nl) {
   if (prec == GCR_PREC_FP32) return kmax + 8 <= 32 ? 32 : (kmax + 8 <= 64 ? 64 : 128);
-  if (prec == GCR_PREC_BF16) return kmax + 8 <= 64 ? 64 : 128;
+  if (prec == GCR_PREC_BF16) return (kmax + 8 <= 64 && nl == 1) ? 64 : (kmax + 8 <= 128 ? 128 : 256);
   return kmax + 8 <= 128 ? 128 : 256;
 }
 
@@ -161,7 +164,7 @@ struct KnnPlan {
   int prec, nl, C, S, RB, kch, fb_grid;
   int64_t n, npad, ld, W, rows, ncols;
   uint8_t* Xs; float* n2; float* scale; unsigned* maxn2;
-  uint64_t* cand; int* cnt; int* fb_list; int* fb_count; uint64_t* fb_scr;
+  uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
 };
 
 void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
@@ -174,19 +177,20 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.kch = (int)(kp.ld / 128);
   kp.rows = r1 - r0;
   kp.ncols = c1 - c0;
-  kp.C = capacity_for(prec, std::max(k0, k1));
+  kp.C = capacity_for(prec, std::max(k0, k1), kp.nl);
   kp.RB = (int)((kp.rows + 127) / 128);
   int S = 8;
   while ((int64_t)kp.RB * S < 1024 && S * 2 * 128 <= kp.ncols && S * 2 * kp.C <= 2048) S *= 2;
   kp.S = S;
   kp.W = roundup((kp.ncols + S - 1) / S, 128);
-  kp.fb_grid = 32;
+  kp.fb_grid = (int)std::min<int64_t>(1024, std::max<int64_t>(64, kp.rows * kp.nl / 16));
   kp.Xs = ar.take<uint8_t>((size_t)(kp.npad * kp.ld));
   kp.n2 = ar.take<float>(kp.npad);
   kp.scale = ar.take<float>(kp.npad);
   kp.maxn2 = ar.take<unsigned>(64);
   kp.cand = ar.take<uint64_t>((size_t)kp.rows * kp.nl * S * kp.C);
   kp.cnt = ar.take<int>((size_t)kp.rows * kp.nl * S);
+  kp.thr = ar.take<float>((size_t)kp.rows * kp.nl * S);
   kp.fb_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
   kp.fb_count = ar.take<int>(64);
   kp.fb_scr = ar.take<uint64_t>((size_t)kp.fb_grid * std::max<int64_t>(kp.ncols, 1));
@@ -209,13 +213,13 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   sa.r0 = r0; sa.r1 = r1; sa.c0 = c0; sa.c1 = c1; sa.W = kp.W; sa.S = kp.S; sa.RB = kp.RB;
   sa.exclude_self = exclude_self; sa.k0 = k0; sa.k1 = k1; sa.C = kp.C;
   sa.eps_s = eps_similarity(kp.prec, d); sa.eps_n = eps_norm(d);
-  sa.cand = kp.cand; sa.cnt = kp.cnt;
+  sa.cand = kp.cand; sa.cnt = kp.cnt; sa.thr = kp.thr;
   {
     TimedScope ts(c, 0, st);
     launch_sim_topk(kp.prec, kp.nl, sa, st);
   }
   RefineArgs ra;
-  ra.cand = kp.cand; ra.cnt = kp.cnt; ra.S = kp.S; ra.C = kp.C; ra.NL = kp.nl; ra.k0 = k0; ra.k1 = k1;
+  ra.cand = kp.cand; ra.cnt = kp.cnt; ra.thr = kp.thr; ra.S = kp.S; ra.C = kp.C; ra.NL = kp.nl; ra.k0 = k0; ra.k1 = k1;
   ra.r0 = r0; ra.r1 = r1; ra.c0 = c0; ra.c1 = c1; ra.exclude_self = exclude_self;
   ra.X = X; ra.d = d; ra.cam = cam; ra.n2 = kp.n2; ra.maxn2 = (const float*)kp.maxn2;
   ra.eps_s = sa.eps_s; ra.eps_n = sa.eps_n;
@@ -467,6 +471,7 @@ gcr_status gcr_knn(gcr_ctx* c, const float* X, int64_t n, int32_t d, const int32
   gcr_status s = check_params(c, p);
   if (s != GCR_OK) return s;
   if (n < 1 || d <= 0 || !X) return fail(c, GCR_ERR_INVALID, "bad X / n / d");
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
   if (n > (int64_t)INT32_MAX / 2) return fail(c, GCR_ERR_UNSUPPORTED, "n too large");
   const bool cross = cr_idx != nullptr;
   if (cross && (!cam || !cr_dist)) return fail(c, GCR_ERR_INVALID, "cross list needs cam and cr_dist");
@@ -506,6 +511,7 @@ gcr_status gcr_build_graph(gcr_ctx* c, const float* X, int64_t n, int32_t d, con
   if (s != GCR_OK) return s;
   if (!g || !X || n < 1 || d <= 0 || g->n != n || g->k != p->k)
     return fail(c, GCR_ERR_INVALID, "graph / X shape mismatch");
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
   if (g->has_cross && !cam) return fail(c, GCR_ERR_INVALID, "cross graph needs camera labels");
   HIP_TRY(c, hipSetDevice(c->device));
   Arena dry;
@@ -565,6 +571,7 @@ gcr_status gcr_final_distances(gcr_ctx* c, const float* X, int64_t nq, int64_t n
   if (!c) return GCR_ERR_INVALID;
   if (!p) return fail(c, GCR_ERR_INVALID, "params is NULL");
   if (!X || nq < 1 || ng < 1 || d <= 0) return fail(c, GCR_ERR_INVALID, "bad X / nq / ng / d");
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
   if (topk_idx && (!topk_dist || p->topk_out < 1 || p->topk_out > 120))
     return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
   if (p->precision < 0 || p->precision > 2) return fail(c, GCR_ERR_INVALID, "unknown precision");

@@ -36,7 +36,9 @@ struct SimArgs {
   int C;              // candidate capacity per (row, list, split)
   float eps_s, eps_n; // screening error coefficients
   uint64_t* cand;     // [(r1-r0), NL, S, C]
-  int* cnt;           // [(r1-r0), NL, S]; -1 marks a full buffer
+  int* cnt;           // [(r1-r0), NL, S] entries kept
+  float* thr;         // [(r1-r0), NL, S] final admission threshold: the buffer
+                      // holds every item of the split with key <= thr
 };
 int sim_topk_grid(int RB, int S);
 void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
@@ -45,6 +47,7 @@ void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
 struct RefineArgs {
   const uint64_t* cand;
   const int* cnt;
+  const float* thr;
   int S, C, NL;
   int k0, k1;
   int64_t r0, r1, c0, c1;

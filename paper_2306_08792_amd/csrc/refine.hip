@@ -3,7 +3,8 @@
 // For one (row, list) the candidate buffers of all column splits are
 // gathered, sorted by screened key, and cut at tau + 2 E (tau = k-th smallest
 // screened key over all splits, E = screening margin): this superset holds
-// the exact top-k.  Its members are re-scored with the squared distance
+// the exact top-k as long as every split kept all of its items up to that
+// cut (each split reports the threshold up to which its buffer is whole).  Its members are re-scored with the squared distance
 // ||x_i - x_j||^2 evaluated in float-float arithmetic (error-free
 // differences and products, compensated sums), then ordered by
 // (distance, index), the order of Eq. (4)'s neighbour sets, and the first k
@@ -72,7 +73,8 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   __shared__ uint64_t ek[UMAX];
   __shared__ uint32_t ec[UMAX];
   __shared__ int offs[65];
-  __shared__ int s_flag, s_M;
+  __shared__ int s_M;
+  __shared__ float s_tmin;
 
   const int NL = a.NL;
   const int64_t rrel = blockIdx.x / NL;
@@ -85,22 +87,18 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   const int tid = threadIdx.x;
 
   if (tid == 0) {
-    int acc = 0, fl = 0;
-    const int* cp = a.cnt + (rrel * NL + L) * (int64_t)a.S;
+    int acc = 0;
+    float tmin = INFINITY;
+    const int64_t o = (rrel * NL + L) * (int64_t)a.S;
     for (int s = 0; s < a.S; ++s) {
       offs[s] = acc;
-      const int c = cp[s];
-      if (c < 0) fl = 1; else acc += c;
+      acc += a.cnt[o + s];
+      tmin = fminf(tmin, a.thr[o + s]);
     }
     offs[a.S] = acc;
-    s_flag = fl;
-    if (fl) {
-      const int slot = atomicAdd(a.fb_count, 1);
-      a.fb_list[slot] = (int)(rrel * 2 + L);
-    }
+    s_tmin = tmin;
   }
   __syncthreads();
-  if (s_flag) return;
   const int T = offs[a.S];
   int P = 64;
   while (P < T) P <<= 1;
@@ -118,6 +116,15 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   const float twoE = 2.0f * screen_margin(a.n2[row], *a.maxn2, a.eps_s, a.eps_n);
   const float tau = (T >= kk && kk > 0) ? cand_key(U[kk - 1]) : INFINITY;
   const float th = tau + twoE;
+  // every split holds all of its items with key <= its threshold; if the
+  // cut reaches past one of them, this row needs the exhaustive path
+  if (kk > 0 && th > s_tmin) {
+    if (tid == 0) {
+      const int slot = atomicAdd(a.fb_count, 1);
+      a.fb_list[slot] = (int)(rrel * 2 + L);
+    }
+    return;
+  }
   if (tid == 0) s_M = 0;
   __syncthreads();
   int mine = 0;
@@ -151,10 +158,32 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   if (tid == 0 && a.stat_cands) atomicAdd(a.stat_cands, (unsigned long long)M);
 }
 
-// Exhaustive exact path for rows whose candidate buffer overflowed.
-__global__ __launch_bounds__(1024) void fallback_kernel(RefineArgs a) {
-  __shared__ uint64_t rk[16];
-  __shared__ uint32_t rc[16];
+// Exhaustive exact path for (row, list) pairs whose cut reached past a
+// split's threshold.  One block per pair (grid-stride); the row's slice of
+// the feature vector stays in registers (d <= 2048), each wave scores one
+// column at a time in float-float arithmetic, then k rounds of "smallest
+// (distance, column) above the previous one" extract the list in order.
+__device__ __forceinline__ uint64_t wave_exact_sqdist_reg(const float (&xr)[32], const float* __restrict__ xb,
+                                                          int d) {
+  const int lane = threadIdx.x & 63;
+  float hi = 0.f, lo = 0.f;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const int e = lane + 64 * t;
+    if (e < d) ff_acc_sqdiff(hi, lo, xr[t], xb[e]);
+  }
+  float h, l;
+  fast_two_sum(hi, lo, h, l);
+  wave_ff_sum(h, l);
+  fast_two_sum(h, l, hi, lo);
+  return ((uint64_t)ord_f32(hi) << 32) | (uint64_t)ord_f32(lo);
+}
+
+constexpr int FBT = 512;
+__global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
+  constexpr int NW = FBT / 64;
+  __shared__ uint64_t rk[NW];
+  __shared__ uint32_t rc[NW];
   __shared__ uint64_t bk;
   __shared__ uint32_t bc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -169,14 +198,20 @@ __global__ __launch_bounds__(1024) void fallback_kernel(RefineArgs a) {
     const int kk = L == 0 ? a.k0 : a.k1;
     int32_t* oidx = (L == 0 ? a.idx0 : a.idx1) + rrel * kk;
     float* odist = (L == 0 ? a.dist0 : a.dist1) + rrel * kk;
-    const float* xr = a.X + row * (int64_t)a.d;
+    const float* xrow = a.X + row * (int64_t)a.d;
+    float xr[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int e = lane + 64 * t;
+      xr[t] = e < a.d ? xrow[e] : 0.f;
+    }
     const int rcam = a.cam ? a.cam[row] : 0;
-    for (int64_t j = wave; j < ncols; j += 16) {
+    for (int64_t j = wave; j < ncols; j += NW) {
       const int64_t col = a.c0 + j;
       bool ok = !(a.exclude_self && col == row);
       if (L == 1) ok = ok && a.cam[col] != rcam;
       uint64_t v = GCR_EMPTY;
-      if (ok) v = wave_exact_sqdist(xr, a.X + col * (int64_t)a.d, a.d);
+      if (ok) v = wave_exact_sqdist_reg(xr, a.X + col * (int64_t)a.d, a.d);
       if (lane == 0) scr[j] = v;
     }
     __syncthreads();
@@ -186,7 +221,7 @@ __global__ __launch_bounds__(1024) void fallback_kernel(RefineArgs a) {
     for (int t = 0; t < kk; ++t) {
       uint64_t best = GCR_EMPTY;
       uint32_t bcol = 0xffffffffu;
-      for (int64_t j = tid; j < ncols; j += 1024) {
+      for (int64_t j = tid; j < ncols; j += FBT) {
         const uint64_t v = scr[j];
         if (v == GCR_EMPTY) continue;
         const bool after = !have_prev || v > pk || (v == pk && (uint32_t)j > pc);
@@ -204,7 +239,7 @@ __global__ __launch_bounds__(1024) void fallback_kernel(RefineArgs a) {
       if (tid == 0) {
         uint64_t b = rk[0];
         uint32_t c = rc[0];
-        for (int q = 1; q < 16; ++q)
+        for (int q = 1; q < NW; ++q)
           if (rk[q] < b || (rk[q] == b && rc[q] < c)) { b = rk[q]; c = rc[q]; }
         bk = b; bc = c;
         if (b == GCR_EMPTY) { oidx[t] = -1; odist[t] = INFINITY; }
@@ -212,8 +247,8 @@ __global__ __launch_bounds__(1024) void fallback_kernel(RefineArgs a) {
       }
       __syncthreads();
       pk = bk; pc = bc; have_prev = true;
-      if (pk == GCR_EMPTY) {  // nothing left: pad the rest
-        for (int u = t + 1 + tid; u < kk; u += 1024) { oidx[u] = -1; odist[u] = INFINITY; }
+      if (pk == GCR_EMPTY) {
+        for (int u = t + 1 + tid; u < kk; u += FBT) { oidx[u] = -1; odist[u] = INFINITY; }
         break;
       }
     }
@@ -225,7 +260,7 @@ void launch_refine(const RefineArgs& a, hipStream_t st) {
   const int64_t rows = a.r1 - a.r0;
   if (rows <= 0) return;
   hipLaunchKernelGGL(refine_kernel, dim3((unsigned)(rows * a.NL)), dim3(RT), 0, st, a);
-  hipLaunchKernelGGL(fallback_kernel, dim3(a.fb_grid), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(fallback_kernel, dim3(a.fb_grid), dim3(FBT), 0, st, a);
 }
 
 }  // namespace gcr

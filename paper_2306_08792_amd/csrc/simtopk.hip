@@ -17,8 +17,12 @@
 // every true neighbour has a screened key <= tau_final + 2 E_i, so the
 // buffer always keeps the exact top-k (ties included).  A full buffer is
 // compacted by one wave: bitonic sort, new tau_i, drop keys above the
-// threshold.  If the margin band alone fills the buffer the row is marked
-// (count -1) and later recomputed exhaustively.
+// threshold.  If the margin band alone fills the buffer (a split's local
+// k-th neighbour can sit in a dense region of unrelated items), the buffer
+// keeps its smallest keys and the admission threshold drops below the first
+// key it gave up; the split's final threshold is written out, and the
+// refine step falls back to an exhaustive row only if the global cut
+// reaches beyond it.
 #include "kernels.h"
 
 namespace gcr {
@@ -125,10 +129,13 @@ __device__ __forceinline__ void tile_lstore(uint8_t* smem, int stage, int tid, c
 }
 #undef GCR_LS
 
-// One wave compacts the candidate buffer of (list L, local row lr).
+// One wave compacts the candidate buffer of (list L, local row lr): sort,
+// tau = k-th smallest key, keep the keys <= tau + 2E.  When that band does
+// not fit, keep only the m = max(C/2, k) smallest keys and lower the
+// admission threshold below the first dropped key, so the buffer still
+// holds every item of the split whose key is <= the threshold.
 template <int E>
-__device__ void compact_row(uint64_t* base, int* cnt, float* thr, int* ovf, int C, int kk,
-                            float twoE) {
+__device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk, float twoE) {
   const int lane = threadIdx.x & 63;
   const int n = min(*cnt, C);
   uint64_t v[E];
@@ -138,34 +145,43 @@ __device__ void compact_row(uint64_t* base, int* cnt, float* thr, int* ovf, int 
     v[j] = e < n ? base[e] : GCR_EMPTY;
   }
   wave_bitonic_sort<E>(v);
-  float tau = INFINITY;
-  if (n >= kk) {
-    const int e = kk - 1;
+  auto elem = [&](int e) {
     uint64_t sel = 0;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      uint64_t t = shfl_u64(v[j], e & 63);
+      const uint64_t t = shfl_u64(v[j], e & 63);
       if (j == (e >> 6)) sel = t;
     }
-    tau = cand_key(sel);
-  }
-  const float th = tau + twoE;
+    return sel;
+  };
+  float th = *thr;
+  if (n >= kk) th = fminf(th, cand_key(elem(kk - 1)) + twoE);
   int newn = 0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const bool ok = v[j] != GCR_EMPTY && cand_key(v[j]) <= th;
     newn += __popcll(__ballot(ok));
   }
-  if (newn >= C) {
-    if (lane == 0) { *ovf = 1; *thr = -INFINITY; }
-  } else {
+  if (newn > C - 16) {
+    const int m = max(C / 2, kk);
+    if (m < newn) {
+      // admit only keys strictly below the first dropped one
+      const float cut = cand_key(elem(m));
+      th = fminf(th, nextafterf(cut, -INFINITY));
+      newn = 0;
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int e = j * 64 + lane;
-      if (e < newn) base[e] = v[j];
+      for (int j = 0; j < E; ++j) {
+        const bool ok = v[j] != GCR_EMPTY && cand_key(v[j]) <= th;
+        newn += __popcll(__ballot(ok));
+      }
     }
-    if (lane == 0) { *cnt = newn; *thr = th; }
   }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = j * 64 + lane;
+    if (e < newn) base[e] = v[j];
+  }
+  if (lane == 0) { *cnt = newn; *thr = th; }
 }
 
 template <int PREC, int NL, int E>
@@ -174,7 +190,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ float col_n2[BN], col_sc[BN];
   __shared__ int col_cam[BN];
   __shared__ float row_thr[NL][BM];
-  __shared__ int row_cnt[NL][BM], row_ovf[NL][BM];
+  __shared__ int row_cnt[NL][BM];
   __shared__ float row_twoE[BM], row_sc[BM];
   __shared__ int row_cam[BM];
   __shared__ int any_flag[2];
@@ -209,7 +225,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     for (int L = 0; L < NL; ++L) {
       row_thr[L][t] = (rv && (L == 0 ? a.k0 : a.k1) > 0) ? INFINITY : -INFINITY;
       row_cnt[L][t] = 0;
-      row_ovf[L][t] = 0;
     }
   }
 
@@ -321,9 +336,9 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       if (!any) break;
       for (int q = wave; q < NL * BM; q += NT / 64) {
         const int L = q / BM, lr = q - L * BM;
-        if (row_cnt[L][lr] >= a.C && !row_ovf[L][lr]) {
+        if (row_cnt[L][lr] >= a.C) {
           uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
-          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], &row_ovf[L][lr], a.C,
+          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C,
                          L == 0 ? a.k0 : a.k1, row_twoE[lr]);
         }
       }
@@ -355,7 +370,11 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   for (int t = tid; t < BM * NL; t += NT) {
     const int L = t / BM, lr = t - L * BM;
     if (row0 + lr < a.r1)
-      a.cnt[((rrel0 + lr) * NL + L) * (int64_t)a.S + cs] = row_ovf[L][lr] ? -1 : min(row_cnt[L][lr], a.C);
+    {
+      const int64_t o = ((rrel0 + lr) * NL + L) * (int64_t)a.S + cs;
+      a.cnt[o] = min(row_cnt[L][lr], a.C);
+      a.thr[o] = row_thr[L][lr];
+    }
   }
 }
 

@@ -284,3 +284,22 @@ def test_plain_gcr_small_workload(ctx):
     from oracle.metrics import mean_average_precision
     m = mean_average_precision(host(out["dist"]), w.ids[:w.nq], w.ids[w.nq:])
     assert m >= 0.99
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_knn_truncated_splits(ctx, prec):
+    """Identities interleaved over 3,000 rows: each column split holds only a
+    few members of a row's cluster, so its local k-th neighbour lies among
+    unrelated items and the split buffers truncate.  The lists must stay
+    exact, and no row should need the exhaustive path."""
+    print(f"knn truncated splits prec={prec}", flush=True)
+    w = datagen.cross_camera_reid(seed=9, nq=600, ng=2400, d=128, n_ids=150, n_cams=5)
+    p = Params(k=15, precision=prec, alpha=0.5)
+    ctx.reset_stats()
+    idx, dist, cidx, cdist = ctx.knn(dev(w.X), p, dev(w.cams, torch.int32), cross=True)
+    st = ctx.stats()
+    rows = np.arange(0, 3000, 7)
+    check_knn_rows(host(idx)[rows], host(dist)[rows], w.X, rows, 15)
+    check_knn_rows(host(cidx)[rows], host(cdist)[rows], w.X, rows, 15, cam=w.cams, cross=True, what="cross")
+    if prec != FP8:
+        assert st["knn_fallback_rows"] == 0, st
