@@ -68,6 +68,11 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+    # first makes this library bind to that same runtime, so tensors that
+    # torch allocated are valid device pointers here.
+    import torch  # noqa: F401
+
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2306_08792_amd.build` "

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gcr.h"
+#include "gcr.h"
 #include "kernels.h"
 
 struct gcr_timer_rec {
@@ -151,13 +151,17 @@ float eps_norm(int d) {
   return (float)(m * u23 / (1.0 - m * u23) * 1.01);
 }
 
-// Candidate capacity per (row, list, split).  Two-list (cross-camera) runs
-// get room for a wider band: a cross list's k-th neighbour often lies among
-// many unrelated items at nearly equal distance.
+// Candidate capacity per (row, list, split).  When a row's k-th neighbour
+// lies among many unrelated items at nearly the same distance (a cross-camera
+// list whose identity has few other-camera samples), the screening band holds
+// hundreds of items; a buffer that keeps 256 of them leaves the split's
+// threshold far enough above the cut that the exact step rarely needs the
+// exhaustive path.  Rows with a tight neighbourhood compact once and stay
+// small, so the large buffer costs little for them.
 int capacity_for(int prec, int kmax, int nl) {
-  if (prec == GCR_PREC_FP32) return kmax + 8 <= 32 ? 32 : (kmax + 8 <= 64 ? 64 : 128);
-  if (prec == GCR_PREC_BF16) return (kmax + 8 <= 64 && nl == 1) ? 64 : (kmax + 8 <= 128 ? 128 : 256);
-  return kmax + 8 <= 128 ? 128 : 256;
+  (void)prec;
+  (void)nl;
+  return kmax + 8 <= 512 ? 512 : 1024;
 }
 
 struct KnnPlan {
@@ -165,6 +169,8 @@ struct KnnPlan {
   int64_t n, npad, ld, W, rows, ncols;
   uint8_t* Xs; float* n2; float* scale; unsigned* maxn2;
   uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
+  uint64_t* fb_pk; uint32_t* fb_pc;
+  float* seed;
 };
 
 void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
@@ -179,27 +185,43 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.ncols = c1 - c0;
   kp.C = capacity_for(prec, std::max(k0, k1), kp.nl);
   kp.RB = (int)((kp.rows + 127) / 128);
-  int S = 8;
-  while ((int64_t)kp.RB * S < 1024 && S * 2 * 128 <= kp.ncols && S * 2 * kp.C <= 2048) S *= 2;
+  const int TC = sim_topk_tile_cols();
+  // Whole-row sweeps keep a row's neighbourhood in one candidate buffer
+  // (its running threshold then tightens to the true k-th key); rows are
+  // split over columns only while there are too few row blocks to occupy
+  // the GPU.
+  int S = 1;
+  while ((int64_t)kp.RB * S < 128 && (int64_t)S * 2 * TC <= kp.ncols && S * 2 * kp.C <= 2048 && S < 64) S *= 2;
   kp.S = S;
-  kp.W = roundup((kp.ncols + S - 1) / S, 128);
-  kp.fb_grid = (int)std::min<int64_t>(1024, std::max<int64_t>(64, kp.rows * kp.nl / 16));
+  kp.W = roundup((kp.ncols + S - 1) / S, TC);
+  kp.fb_grid = 256;
   kp.Xs = ar.take<uint8_t>((size_t)(kp.npad * kp.ld));
   kp.n2 = ar.take<float>(kp.npad);
   kp.scale = ar.take<float>(kp.npad);
   kp.maxn2 = ar.take<unsigned>(64);
   kp.cand = ar.take<uint64_t>((size_t)kp.rows * kp.nl * S * kp.C);
   kp.cnt = ar.take<int>((size_t)kp.rows * kp.nl * S);
+  kp.seed = ar.take<float>((size_t)kp.rows * kp.nl);
   kp.thr = ar.take<float>((size_t)kp.rows * kp.nl * S);
   kp.fb_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
   kp.fb_count = ar.take<int>(64);
   kp.fb_scr = ar.take<uint64_t>((size_t)kp.fb_grid * std::max<int64_t>(kp.ncols, 1));
+  {
+    const int64_t pairs = std::min<int64_t>(FB_MAX, kp.rows * kp.nl);
+    const int64_t nch = (kp.ncols + 2047) / 2048;
+    const int64_t kmx = std::max(k0, k1);
+    kp.fb_pk = ar.take<uint64_t>((size_t)(pairs * nch * kmx + 1));
+    kp.fb_pc = ar.take<uint32_t>((size_t)(pairs * nch * kmx + 1));
+  }
 }
 
 // Screening + refine for rows [r0, r1) against columns [c0, c1) of X.
+// prev0 / prev1: earlier neighbour lists of the same rows (graph rebuilt
+// from updated features) used to seed the admission thresholds, or nullptr.
 void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* cam, int64_t r0, int64_t r1,
              int64_t c0, int64_t c1, int exclude_self, int k0, int k1, int32_t* idx0, float* dist0,
-             int32_t* idx1, float* dist1, hipStream_t st) {
+             int32_t* idx1, float* dist1, hipStream_t st, const int32_t* prev0 = nullptr,
+             const int32_t* prev1 = nullptr) {
   fill_u32(kp.maxn2, 0u, 1, st);
   fill_u32(kp.fb_count, 0u, 1, st);
   {
@@ -207,13 +229,20 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
     launch_screen_prep(kp.prec, X, kp.n, d, kp.npad, kp.Xs, kp.ld, kp.n2, kp.scale, kp.maxn2, st);
   }
   SimArgs sa;
-  sa.Xs = kp.Xs; sa.ld_bytes = kp.ld; sa.kchunks = kp.kch; sa.n2 = kp.n2;
+  sa.Xs = kp.Xs; sa.npad = kp.npad; sa.ld_bytes = kp.ld; sa.kchunks = kp.kch; sa.n2 = kp.n2;
   sa.scale = kp.prec == GCR_PREC_FP8 ? kp.scale : nullptr;
   sa.cam = cam; sa.maxn2 = (const float*)kp.maxn2;
   sa.r0 = r0; sa.r1 = r1; sa.c0 = c0; sa.c1 = c1; sa.W = kp.W; sa.S = kp.S; sa.RB = kp.RB;
   sa.exclude_self = exclude_self; sa.k0 = k0; sa.k1 = k1; sa.C = kp.C;
   sa.eps_s = eps_similarity(kp.prec, d); sa.eps_n = eps_norm(d);
   sa.cand = kp.cand; sa.cnt = kp.cnt; sa.thr = kp.thr;
+  sa.thr_init = nullptr;
+  if (prev0 && r0 == 0 && c0 == 0 && r1 == c1 && (k1 == 0 || prev1)) {
+    TimedScope ts(c, 1, st);
+    launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, (const float*)kp.maxn2,
+                           sa.eps_s, sa.eps_n, kp.seed, st);
+    sa.thr_init = kp.seed;
+  }
   {
     TimedScope ts(c, 0, st);
     launch_sim_topk(kp.prec, kp.nl, sa, st);
@@ -226,6 +255,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   ra.idx0 = idx0; ra.dist0 = dist0; ra.idx1 = idx1; ra.dist1 = dist1;
   ra.fb_list = kp.fb_list; ra.fb_count = kp.fb_count; ra.stat_cands = c->stats;
   ra.fb_scratch = kp.fb_scr; ra.fb_grid = kp.fb_grid;
+  ra.fb_part_key = kp.fb_pk; ra.fb_part_col = kp.fb_pc;
   {
     TimedScope ts(c, 1, st);
     launch_refine(ra, st);
@@ -323,12 +353,16 @@ void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const 
 }
 
 // kNN + affinity + CSR + degrees + normalised values into g.
+// seed_from_previous: g already holds the lists of the same rows from the
+// previous round; they bound this round's k-th distances from above.
 void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, const float* X, int64_t n, int d,
-                         const int* cam, const gcr_params* p, const gcr_graph* g, hipStream_t st) {
+                         const int* cam, const gcr_params* p, const gcr_graph* g, hipStream_t st,
+                         bool seed_from_previous = false) {
   const bool cross = g->has_cross != 0;
   if (g->k > 0 || (cross && g->cross_k > 0))
     run_knn(c, kp, X, d, cam, 0, n, 0, n, 1, g->k, cross ? g->cross_k : 0, g->idx, g->dist,
-            cross ? g->cr_idx : nullptr, cross ? g->cr_dist : nullptr, st);
+            cross ? g->cr_idx : nullptr, cross ? g->cr_dist : nullptr, st,
+            seed_from_previous ? g->idx : nullptr, seed_from_previous && cross ? g->cr_idx : nullptr);
   const float alpha = cross ? p->alpha : 1.0f;
   TimedScope ts(c, 2, st);
   build_one(g, false, n, cam, p, alpha, gt, st, false);
@@ -632,7 +666,7 @@ gcr_status gcr_rerank(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_
   }
   else HIP_TRY(c, hipMemcpyAsync(xa, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
   for (int t = 0; t < p->rounds; ++t) {
-    if (t == 0 || p->rebuild_each_round) enqueue_build_graph(c, kp, gt, xa, n, d, cam, p, &g, st);
+    if (t == 0 || p->rebuild_each_round) enqueue_build_graph(c, kp, gt, xa, n, d, cam, p, &g, st, t > 0);
     enqueue_propagate(c, &g, xa, xb, n, d, st);
     std::swap(xa, xb);
   }

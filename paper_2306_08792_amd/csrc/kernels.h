@@ -20,6 +20,7 @@ void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad
 // ---- simtopk.hip : fused MFMA similarity tiles + streaming per-row top-k
 struct SimArgs {
   const uint8_t* Xs;  // screening operand, [npad, ld_bytes]
+  int64_t npad;       // rows of Xs (reads beyond return zero)
   int64_t ld_bytes;   // multiple of 128
   int kchunks;        // ld_bytes / 128
   const float* n2;    // [npad]
@@ -28,7 +29,7 @@ struct SimArgs {
   const float* maxn2; // device scalar
   int64_t r0, r1;     // rows [r0, r1)
   int64_t c0, c1;     // columns [c0, c1)
-  int64_t W;          // split width (multiple of 128)
+  int64_t W;          // split width (multiple of the 256-column tile)
   int S;              // number of column splits (multiple of 8)
   int RB;             // row blocks of 128
   int exclude_self;   // skip column == row
@@ -36,11 +37,18 @@ struct SimArgs {
   int C;              // candidate capacity per (row, list, split)
   float eps_s, eps_n; // screening error coefficients
   uint64_t* cand;     // [(r1-r0), NL, S, C]
+  const float* thr_init;  // [(r1-r0), NL] initial admission thresholds or nullptr
   int* cnt;           // [(r1-r0), NL, S] entries kept
   float* thr;         // [(r1-r0), NL, S] final admission threshold: the buffer
                       // holds every item of the split with key <= thr
 };
 int sim_topk_grid(int RB, int S);
+// Initial admission thresholds from earlier neighbour lists (any k items give
+// an upper bound on the k-th distance): out[row * nl + L].
+void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
+                            int k1, const float* n2, const float* maxn2, float eps_s, float eps_n, float* out,
+                            hipStream_t st);
+int sim_topk_tile_cols();
 void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
 
 // ---- refine.hip : union of split candidates, exact re-score, selection
@@ -65,7 +73,11 @@ struct RefineArgs {
   unsigned long long* stat_cands;  // device counter
   uint64_t* fb_scratch;            // [fb_grid, c1 - c0]
   int fb_grid;
+  uint64_t* fb_part_key;           // [min(FB_MAX, pairs), chunks, k] chunk winners
+  uint32_t* fb_part_col;
 };
+// queued pairs handled by the column-parallel exhaustive path
+constexpr int FB_MAX = 8192;
 void launch_refine(const RefineArgs& a, hipStream_t st);
 
 // ---- graph.hip : affinities, reverse CSR, degrees, normalised values

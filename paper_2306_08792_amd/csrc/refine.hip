@@ -17,6 +17,7 @@ namespace gcr {
 namespace {
 constexpr int RT = 256;       // threads per refine block
 constexpr int UMAX = 2048;    // max union size (S * C)
+constexpr int FB_CW = 2048;   // columns per exhaustive work item
 }  // namespace
 
 // float-float squared distance of two float32 rows by one wave; the result
@@ -179,6 +180,134 @@ __device__ __forceinline__ uint64_t wave_exact_sqdist_reg(const float (&xr)[32],
   return ((uint64_t)ord_f32(hi) << 32) | (uint64_t)ord_f32(lo);
 }
 
+// Column-parallel exhaustive path for the first FB_MAX queued pairs: each
+// work item scores one 2,048-column chunk of one pair exactly and keeps the
+// chunk's k smallest (distance, column); a merge then takes the k smallest
+// over the chunks.  Pairs past FB_MAX use the one-block-per-pair kernel.
+__device__ __forceinline__ bool lex_less(uint64_t ka, uint32_t ca, uint64_t kb, uint32_t cb) {
+  return ka < kb || (ka == kb && ca < cb);
+}
+// block-wide minimum of (key, col) pairs over 256 threads
+__device__ __forceinline__ void block_min_pair(uint64_t& k, uint32_t& c, uint64_t* rk, uint32_t* rc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t ok = shfl_xor_u64(k, o);
+    const uint32_t oc = __shfl_xor(c, o, 64);
+    if (lex_less(ok, oc, k, c)) { k = ok; c = oc; }
+  }
+  if (lane == 0) { rk[wave] = k; rc[wave] = c; }
+  __syncthreads();
+  k = rk[0]; c = rc[0];
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+    if (lex_less(rk[q], rc[q], k, c)) { k = rk[q]; c = rc[q]; }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void fallback_scan_kernel(RefineArgs a) {
+  __shared__ uint64_t sk[FB_CW];
+  __shared__ uint64_t rk[4];
+  __shared__ uint32_t rc[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ncols = a.c1 - a.c0;
+  const int nch = (int)((ncols + FB_CW - 1) / FB_CW);
+  const int nfb = min(*a.fb_count, FB_MAX);
+  for (int64_t wi = blockIdx.x; wi < (int64_t)nfb * nch; wi += gridDim.x) {
+    const int f = (int)(wi / nch), ch = (int)(wi - (int64_t)f * nch);
+    const int code = a.fb_list[f];
+    const int64_t rrel = code >> 1;
+    const int L = code & 1;
+    const int64_t row = a.r0 + rrel;
+    const int kk = L == 0 ? a.k0 : a.k1;
+    const float* xrow = a.X + row * (int64_t)a.d;
+    float xr[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int e = lane + 64 * t;
+      xr[t] = e < a.d ? xrow[e] : 0.f;
+    }
+    const int rcam = a.cam ? a.cam[row] : 0;
+    const int64_t j0 = (int64_t)ch * FB_CW;
+    const int nj = (int)min<int64_t>(FB_CW, ncols - j0);
+    for (int j = wave; j < nj; j += 4) {
+      const int64_t col = a.c0 + j0 + j;
+      bool ok = !(a.exclude_self && col == row);
+      if (L == 1) ok = ok && a.cam[col] != rcam;
+      uint64_t v = GCR_EMPTY;
+      if (ok) v = wave_exact_sqdist_reg(xr, a.X + col * (int64_t)a.d, a.d);
+      if (lane == 0) sk[j] = v;
+    }
+    __syncthreads();
+    // every pair owns nch * kmax slots, whichever list it belongs to
+    const int kmax = max(a.k0, a.k1);
+    uint64_t* pk = a.fb_part_key + ((int64_t)f * nch + ch) * kmax;
+    uint32_t* pc = a.fb_part_col + ((int64_t)f * nch + ch) * kmax;
+    uint64_t prevk = 0;
+    uint32_t prevc = 0;
+    bool have = false;
+    for (int t = 0; t < kk; ++t) {
+      uint64_t bkey = GCR_EMPTY;
+      uint32_t bcol = 0xffffffffu;
+      for (int j = tid; j < nj; j += 256) {
+        const uint64_t v = sk[j];
+        if (v == GCR_EMPTY) continue;
+        const uint32_t cj = (uint32_t)(j0 + j);
+        if (have && !lex_less(prevk, prevc, v, cj)) continue;
+        if (lex_less(v, cj, bkey, bcol)) { bkey = v; bcol = cj; }
+      }
+      block_min_pair(bkey, bcol, rk, rc);
+      if (tid == 0) { pk[t] = bkey; pc[t] = bcol; }
+      prevk = bkey; prevc = bcol; have = true;
+      if (bkey == GCR_EMPTY) {
+        for (int u = t + 1 + tid; u < kk; u += 256) { pk[u] = GCR_EMPTY; pc[u] = 0xffffffffu; }
+        break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void fallback_merge_kernel(RefineArgs a) {
+  __shared__ uint64_t rk[4];
+  __shared__ uint32_t rc[4];
+  const int tid = threadIdx.x;
+  const int64_t ncols = a.c1 - a.c0;
+  const int nch = (int)((ncols + FB_CW - 1) / FB_CW);
+  const int nfb = min(*a.fb_count, FB_MAX);
+  for (int f = blockIdx.x; f < nfb; f += gridDim.x) {
+    const int code = a.fb_list[f];
+    const int64_t rrel = code >> 1;
+    const int L = code & 1;
+    const int kk = L == 0 ? a.k0 : a.k1;
+    int32_t* oidx = (L == 0 ? a.idx0 : a.idx1) + rrel * kk;
+    float* odist = (L == 0 ? a.dist0 : a.dist1) + rrel * kk;
+    const int kmax = max(a.k0, a.k1);
+    const uint64_t* pk = a.fb_part_key + (int64_t)f * nch * kmax;
+    const uint32_t* pc = a.fb_part_col + (int64_t)f * nch * kmax;
+    uint64_t prevk = 0;
+    uint32_t prevc = 0;
+    bool have = false;
+    for (int t = 0; t < kk; ++t) {
+      uint64_t bkey = GCR_EMPTY;
+      uint32_t bcol = 0xffffffffu;
+      for (int j = tid; j < nch * kk; j += 256) {
+        const int64_t o = (int64_t)(j / kk) * kmax + (j % kk);  // chunk j / kk, rank j % kk
+        const uint64_t v = pk[o];
+        if (v == GCR_EMPTY) continue;
+        const uint32_t cj = pc[o];
+        if (have && !lex_less(prevk, prevc, v, cj)) continue;
+        if (lex_less(v, cj, bkey, bcol)) { bkey = v; bcol = cj; }
+      }
+      block_min_pair(bkey, bcol, rk, rc);
+      if (tid == 0) {
+        if (bkey == GCR_EMPTY) { oidx[t] = -1; odist[t] = INFINITY; }
+        else { oidx[t] = (int32_t)bcol; odist[t] = exact_hi(bkey); }
+      }
+      prevk = bkey; prevc = bcol; have = true;
+    }
+  }
+}
+
 constexpr int FBT = 512;
 __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
   constexpr int NW = FBT / 64;
@@ -190,7 +319,7 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
   const int64_t ncols = a.c1 - a.c0;
   uint64_t* scr = a.fb_scratch + (int64_t)blockIdx.x * ncols;
   const int nfb = *a.fb_count;
-  for (int f = blockIdx.x; f < nfb; f += gridDim.x) {
+  for (int f = FB_MAX + blockIdx.x; f < nfb; f += gridDim.x) {
     const int code = a.fb_list[f];
     const int64_t rrel = code >> 1;
     const int L = code & 1;
@@ -256,10 +385,60 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
   }
 }
 
+// One wave per (row, list).  If the previous list of the row has k valid
+// members j, the k-th smallest exact key of the row is at most
+// U = max_j ||x_i - x_j||^2 - n2_i (up to the float32 error of n2_i), so the
+// final screened k-th key is <= U + E and the screening never needs to keep
+// keys above U + 3E, E being the row's screening margin.
+__global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __restrict__ X, int d, int64_t n,
+                                                              const int32_t* __restrict__ idx0, int k0,
+                                                              const int32_t* __restrict__ idx1, int k1,
+                                                              const float* __restrict__ n2,
+                                                              const float* __restrict__ maxn2, float eps_s,
+                                                              float eps_n, float* __restrict__ out) {
+  const int nl = idx1 ? 2 : 1;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= n * nl) return;
+  const int64_t row = w / nl;
+  const int L = (int)(w - row * nl);
+  const int kk = L == 0 ? k0 : k1;
+  const int32_t* lst = (L == 0 ? idx0 : idx1) + row * kk;
+  const float* xr = X + row * (int64_t)d;
+  float umax = -INFINITY;
+  int valid = 0;
+  for (int t = 0; t < kk; ++t) {
+    const int j = lst[t];
+    if (j < 0) break;
+    const float dj = exact_hi(wave_exact_sqdist(xr, X + (int64_t)j * d, d));
+    umax = fmaxf(umax, dj);
+    ++valid;
+  }
+  if ((threadIdx.x & 63) != 0) return;
+  float res = INFINITY;
+  if (kk > 0 && valid == kk) {
+    const float mx = *maxn2, n2r = n2[row];
+    const float E = screen_margin(n2r, mx, eps_s, eps_n);
+    const float u = umax - n2r + eps_n * mx;
+    res = u + 3.0f * E + 4e-7f * (fabsf(umax) + n2r + 1.0f);
+  }
+  out[w] = res;
+}
+
+void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
+                            int k1, const float* n2, const float* maxn2, float eps_s, float eps_n, float* out,
+                            hipStream_t st) {
+  const int nl = idx1 ? 2 : 1;
+  const int64_t waves = n * nl;
+  hipLaunchKernelGGL(seed_thresholds_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, X, d, n, idx0, k0,
+                     idx1, k1, n2, maxn2, eps_s, eps_n, out);
+}
+
 void launch_refine(const RefineArgs& a, hipStream_t st) {
   const int64_t rows = a.r1 - a.r0;
   if (rows <= 0) return;
   hipLaunchKernelGGL(refine_kernel, dim3((unsigned)(rows * a.NL)), dim3(RT), 0, st, a);
+  hipLaunchKernelGGL(fallback_scan_kernel, dim3(2048), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(fallback_merge_kernel, dim3(1024), dim3(256), 0, st, a);
   hipLaunchKernelGGL(fallback_kernel, dim3(a.fb_grid), dim3(FBT), 0, st, a);
 }
 

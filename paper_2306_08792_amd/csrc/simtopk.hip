@@ -3,12 +3,20 @@
 // The k-nearest-neighbour sets of Eq. (4) (and the cross-camera sets of
 // Eq. (8)) need, for every row i, the k smallest ||x_i - x_j||^2.  For a
 // fixed row this ranks columns by the key n2_j - 2 <x_i, x_j>.  Each work-
-// group owns 128 rows and sweeps one column split in 128-column tiles; a tile
+// group owns 128 rows and sweeps one column split in 256-column tiles; a tile
 // of similarities is an MFMA GEMM over the feature dimension (float32,
 // bfloat16 or FP8-E4M3 operands, float32 accumulation) and never leaves the
 // registers.  Its epilogue screens every score against the row's running
 // admission threshold and appends survivors to the row's candidate buffer
 // (global memory, one region per row/list/split).
+//
+// Data movement: the feature dimension is consumed in 128-byte chunks.  Each
+// chunk of the 128-row tile and of the 256-column tile is copied straight
+// from global memory into LDS by buffer loads with an LDS destination
+// (16 bytes per lane, no register staging), through a 3-stage ring so two
+// chunks are in flight while a third is multiplied.  Rows are XOR-swizzled in
+// 16-byte units inside LDS so that fragment reads are free of bank conflicts.
+// Out-of-range reads return zero through the buffer descriptor's range.
 //
 // Admission rule.  Let E_i bound |screened key - exact key| (screen_margin)
 // and tau_i be the k-th smallest screened key the buffer has seen.  A column
@@ -28,36 +36,82 @@
 namespace gcr {
 
 namespace {
-constexpr int BM = 128, BN = 128, NT = 256;
-constexpr int LSTR = 144;                  // LDS row stride (128 B + 16 B pad)
-constexpr int OPB = BM * LSTR;             // one operand tile in LDS
-constexpr int SMEM = 4 * OPB;              // 2 stages x (rows, cols)
+constexpr int BM = 128, BN = 256, NT = 256;
+constexpr int RBYTES = BM * 128;           // row tile of one chunk in LDS
+constexpr int CBYTES = BN * 128;           // column tile of one chunk
+constexpr int STAGE = RBYTES + CBYTES;     // 48 KB
+constexpr int NSTAGE = 3;
+constexpr int SMEM = NSTAGE * STAGE;       // 144 KB
+constexpr int DMA_PER_WAVE = (BM + BN) / 8 / 4;  // 1 KB wave loads per chunk per wave
+// s_waitcnt immediate (gfx9 layout) that waits for vmcnt <= n only
+constexpr int waitcnt_vm(int n) { return 0xF70 | (n & 0xF) | (((n >> 4) & 3) << 14); }
 }  // namespace
 
-int sim_topk_grid(int RB, int S) {
-  const int RBg = (RB + 7) / 8;
-  const int blocks = RBg * (S / 8);
-  const int blocks8 = (blocks + 7) / 8 * 8;
-  return blocks8 * 64;
+int sim_topk_grid(int RB, int S) { return RB * S; }
+int sim_topk_tile_cols() { return BN; }
+
+typedef uint32_t __attribute__((address_space(3)))* lds_u32_ptr;
+extern "C" __device__ void gcr_buffer_load_lds(i32x4 rsrc, lds_u32_ptr lds, int size, int voffset, int soffset,
+                                               int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+
+struct BufRes {
+  const void* p;
+  uint32_t range;
+  uint32_t cfg;
+};
+// Buffer descriptor over [p, p + range): reads past range return zero.
+__device__ __forceinline__ i32x4 make_res(const void* p, uint64_t range) {
+  BufRes r{p, (uint32_t)(range > 0xffffffffull ? 0xffffffffull : range), 0x00020000u};
+  i32x4 v = __builtin_bit_cast(i32x4, r);
+  v.x = __builtin_amdgcn_readfirstlane(v.x);
+  v.y = __builtin_amdgcn_readfirstlane(v.y);
+  v.z = __builtin_amdgcn_readfirstlane(v.z);
+  v.w = __builtin_amdgcn_readfirstlane(v.w);
+  return v;
 }
 
+// Issue this wave's share of one chunk: 1 KB blocks of 8 rows, lane l
+// bringing logical 16-byte part (l & 7) ^ (row & 7) of row blk*8 + l/8 so the
+// data lands swizzled.  Block blk = wave + 4 i has row & 7 == l / 8, so the
+// per-lane offset is the same for every block and the block step goes into
+// the scalar offset.
+__device__ __forceinline__ void issue_chunk(uint8_t* stage, i32x4 rres, i32x4 cres, int ld, int ch, int wave,
+                                            int lane) {
+  const int rsub = lane >> 3, pp = lane & 7;
+  const int voff = (wave * 8 + rsub) * ld + ((pp ^ rsub) << 4) + ch * 128;
+  const int step = 32 * ld;  // 4 blocks of 8 rows
+#pragma unroll
+  for (int i = 0; i < BM / 32; ++i)
+    gcr_buffer_load_lds(rres, (lds_u32_ptr)(stage + (wave + 4 * i) * 1024), 16, voff,
+                        __builtin_amdgcn_readfirstlane(i * step), 0, 0);
+#pragma unroll
+  for (int i = 0; i < BN / 32; ++i)
+    gcr_buffer_load_lds(cres, (lds_u32_ptr)(stage + RBYTES + (wave + 4 * i) * 1024), 16, voff,
+                        __builtin_amdgcn_readfirstlane(i * step), 0, 0);
+}
+
+__device__ __forceinline__ const uint8_t* frag(const uint8_t* base, int r, int lp) {
+  return base + r * 128 + ((lp ^ (r & 7)) << 4);
+}
+
+// acc[cb][rb]: 4 column blocks x 2 row blocks of 32 x 32 (transposed
+// orientation: lane l holds row l & 31 of its row block and 16 columns).
 template <int PREC>
-__device__ __forceinline__ void mma_chunk(const uint8_t* __restrict__ Rt, const uint8_t* __restrict__ Ct,
-                                          int wr, int wc, int lane, f32x16 (&acc)[2][2]) {
+__device__ __forceinline__ void mma_chunk(const uint8_t* __restrict__ Rt, const uint8_t* __restrict__ Ct, int wr,
+                                          int wc, int lane, f32x16 (&acc)[4][2]) {
   const int l32 = lane & 31, half = lane >> 5;
   if constexpr (PREC == GCR_PREC_FP32) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      f32x4 vr[2], vc[2];
+      f32x4 vr[2], vc[4];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        vr[b] = *(const f32x4*)(Rt + (wr + 32 * b + l32) * LSTR + half * 64 + q * 16);
-        vc[b] = *(const f32x4*)(Ct + (wc + 32 * b + l32) * LSTR + half * 64 + q * 16);
-      }
+      for (int b = 0; b < 2; ++b) vr[b] = *(const f32x4*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) vc[b] = *(const f32x4*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb)
             acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[cb][s], vr[rb][s], acc[cb][rb], 0, 0, 0);
@@ -65,123 +119,109 @@ __device__ __forceinline__ void mma_chunk(const uint8_t* __restrict__ Rt, const 
   } else if constexpr (PREC == GCR_PREC_BF16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      bf16x8 fr[2], fc[2];
+      bf16x8 fr[2], fc[4];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        fr[b] = *(const bf16x8*)(Rt + (wr + 32 * b + l32) * LSTR + half * 64 + q * 16);
-        fc[b] = *(const bf16x8*)(Ct + (wc + 32 * b + l32) * LSTR + half * 64 + q * 16);
-      }
+      for (int b = 0; b < 2; ++b) fr[b] = *(const bf16x8*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int b = 0; b < 4; ++b) fc[b] = *(const bf16x8*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
           acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fc[cb], fr[rb], acc[cb][rb], 0, 0, 0);
     }
   } else {
-    i32x8 fr[2][2], fc[2][2];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const uint8_t* pr = Rt + (wr + 32 * b + l32) * LSTR + half * 64;
-      const uint8_t* pc = Ct + (wc + 32 * b + l32) * LSTR + half * 64;
+    for (int q = 0; q < 2; ++q) {
+      i32x8 fr[2], fc[4];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        fr[b][q] = *(const i32x8*)(pr + q * 32);
-        fc[b][q] = *(const i32x8*)(pc + q * 32);
+      for (int b = 0; b < 2; ++b) {
+        const int r = wr + 32 * b + l32;
+        const i32x4 lo = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q);
+        const i32x4 hi = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q + 1);
+        fr[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
       }
-    }
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+      for (int b = 0; b < 4; ++b) {
+        const int r = wc + 32 * b + l32;
+        const i32x4 lo = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q);
+        const i32x4 hi = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q + 1);
+        fc[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      }
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
-          acc[cb][rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fc[cb][s], fr[rb][s], acc[cb][rb],
-                                                                         0, 0, 0, 127, 0, 127);
+          acc[cb][rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fc[cb], fr[rb], acc[cb][rb], 0, 0, 0, 127,
+                                                                         0, 127);
+    }
   }
 }
 
-// Prefetch registers of one K chunk: 4 x 16 B of the row tile and of the
-// column tile per thread (named members keep them in VGPRs).
-struct Pref {
-  u32x4 r0, r1, r2, r3, c0, c1, c2, c3;
-};
-#define GCR_GL(Q, RV, CV)                                                                   \
-  {                                                                                         \
-    const int seg = tid + NT * (Q), lr = seg >> 3, part = seg & 7;                          \
-    RV = *(const u32x4*)(Xs + (row0 + lr) * ld + ch * 128 + part * 16);                     \
-    CV = *(const u32x4*)(Xs + (ct0 + lr) * ld + ch * 128 + part * 16);                      \
-  }
-__device__ __forceinline__ void tile_gload(const uint8_t* __restrict__ Xs, int64_t ld, int64_t row0, int64_t ct0,
-                                           int ch, int tid, Pref& p) {
-  GCR_GL(0, p.r0, p.c0) GCR_GL(1, p.r1, p.c1) GCR_GL(2, p.r2, p.c2) GCR_GL(3, p.r3, p.c3)
+// Number of buffer entries whose ordered key is <= u (wave-uniform).
+template <int E>
+__device__ __forceinline__ int wave_count_le(const uint32_t (&key)[E], uint32_t u) {
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) c += __popcll(__ballot(key[j] <= u));
+  return c;
 }
-#undef GCR_GL
-#define GCR_LS(Q, RV, CV)                                                                   \
-  {                                                                                         \
-    const int seg = tid + NT * (Q), lr = seg >> 3, part = seg & 7;                          \
-    *(u32x4*)(R + lr * LSTR + part * 16) = RV;                                              \
-    *(u32x4*)(Cc + lr * LSTR + part * 16) = CV;                                             \
+// Smallest ordered key value u with at least r entries <= u (r <= count of
+// non-empty entries): binary search over the 32-bit ordered key space.
+template <int E>
+__device__ __forceinline__ uint32_t wave_select(const uint32_t (&key)[E], int r) {
+  uint32_t lo = 0u, hi = 0xfffffffeu;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (wave_count_le<E>(key, mid) >= r) hi = mid;
+    else lo = mid + 1u;
   }
-__device__ __forceinline__ void tile_lstore(uint8_t* smem, int stage, int tid, const Pref& p) {
-  uint8_t* R = smem + stage * 2 * OPB;
-  uint8_t* Cc = R + OPB;
-  GCR_LS(0, p.r0, p.c0) GCR_LS(1, p.r1, p.c1) GCR_LS(2, p.r2, p.c2) GCR_LS(3, p.r3, p.c3)
+  return lo;
 }
-#undef GCR_LS
 
-// One wave compacts the candidate buffer of (list L, local row lr): sort,
+// One wave compacts the candidate buffer of (list L, local row lr):
 // tau = k-th smallest key, keep the keys <= tau + 2E.  When that band does
-// not fit, keep only the m = max(C/2, k) smallest keys and lower the
-// admission threshold below the first dropped key, so the buffer still
-// holds every item of the split whose key is <= the threshold.
+// not fit, keep only the keys below the (m+1)-th smallest, m = max(C/2, k),
+// and lower the admission threshold below that key, so the buffer still
+// holds every item of the split whose key is <= the threshold.  Order
+// statistics come from a radix select on the ordered keys (ballots and
+// popcounts), not from sorting; the kept entries are written back densely
+// in no particular order.
 template <int E>
 __device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk, float twoE) {
   const int lane = threadIdx.x & 63;
   const int n = min(*cnt, C);
   uint64_t v[E];
+  uint32_t key[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int e = j * 64 + lane;
     v[j] = e < n ? base[e] : GCR_EMPTY;
+    key[j] = (uint32_t)(v[j] >> 32);  // empty slots: 0xffffffff, above any key
   }
-  wave_bitonic_sort<E>(v);
-  auto elem = [&](int e) {
-    uint64_t sel = 0;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const uint64_t t = shfl_u64(v[j], e & 63);
-      if (j == (e >> 6)) sel = t;
-    }
-    return sel;
-  };
   float th = *thr;
-  if (n >= kk) th = fminf(th, cand_key(elem(kk - 1)) + twoE);
-  int newn = 0;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const bool ok = v[j] != GCR_EMPTY && cand_key(v[j]) <= th;
-    newn += __popcll(__ballot(ok));
-  }
+  if (n >= kk && kk > 0) th = fminf(th, unord_f32(wave_select<E>(key, kk)) + twoE);
+  int newn = wave_count_le<E>(key, ord_f32(th));
   if (newn > C - 16) {
     const int m = max(C / 2, kk);
     if (m < newn) {
-      // admit only keys strictly below the first dropped one
-      const float cut = cand_key(elem(m));
+      // admit only keys strictly below the (m+1)-th smallest
+      const float cut = unord_f32(wave_select<E>(key, m + 1));
       th = fminf(th, nextafterf(cut, -INFINITY));
-      newn = 0;
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const bool ok = v[j] != GCR_EMPTY && cand_key(v[j]) <= th;
-        newn += __popcll(__ballot(ok));
-      }
+      newn = wave_count_le<E>(key, ord_f32(th));
     }
   }
+  const uint32_t tho = ord_f32(th);
+  int off = 0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int e = j * 64 + lane;
-    if (e < newn) base[e] = v[j];
+    const bool keep = key[j] <= tho && v[j] != GCR_EMPTY;
+    const uint64_t b = __ballot(keep);
+    const int pos = off + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (keep) base[pos] = v[j];
+    off += __popcll(b);
   }
-  if (lane == 0) { *cnt = newn; *thr = th; }
+  if (lane == 0) { *cnt = off; *thr = th; }
 }
 
 template <int PREC, int NL, int E>
@@ -194,16 +234,15 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ float row_twoE[BM], row_sc[BM];
   __shared__ int row_cam[BM];
   __shared__ int any_flag[2];
+  __shared__ uint32_t cb_vote[2];
 
-  // XCD-aware placement: consecutive ids go round-robin over the 8 XCDs;
-  // the 64 workgroups an XCD holds at a time form an 8 row-block x 8 split
-  // block, so they share 8 row tiles and 8 column streams in its L2.
+  // XCD-aware placement: workgroup ids go round-robin over the 8 XCDs and
+  // the split is id mod S, so every workgroup an XCD runs sweeps the same
+  // column split (S <= 8 divides 8) and the column tiles are shared in that
+  // XCD's L2; consecutive row blocks spread over all XCDs.
   const int id = blockIdx.x;
-  const int xcd = id & 7, j = id >> 3;
-  const int blk = (j >> 6) * 8 + xcd, w = j & 63;
-  const int SG = a.S >> 3;
-  const int rb = (blk / SG) * 8 + (w >> 3);
-  const int cs = (blk % SG) * 8 + (w & 7);
+  const int cs = id % a.S;
+  const int rb = id / a.S;
   if (rb >= a.RB) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -213,7 +252,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   const int ntiles = sc1 > sc0 ? (int)((sc1 - sc0 + BN - 1) / BN) : 0;
   const float maxn2 = *a.maxn2;
 
-  if (tid < 2) any_flag[tid] = 0;
+  if (tid < 2) { any_flag[tid] = 0; cb_vote[tid] = 0u; }
   for (int t = tid; t < BM; t += NT) {
     const int64_t r = row0 + t;
     const bool rv = r < a.r1;
@@ -223,52 +262,69 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     row_sc[t] = (PREC == GCR_PREC_FP8 && rv) ? a.scale[r] : 1.0f;
 #pragma unroll
     for (int L = 0; L < NL; ++L) {
-      row_thr[L][t] = (rv && (L == 0 ? a.k0 : a.k1) > 0) ? INFINITY : -INFINITY;
+      row_thr[L][t] = (rv && (L == 0 ? a.k0 : a.k1) > 0)
+                          ? (a.thr_init ? a.thr_init[(r - a.r0) * NL + L] : INFINITY)
+                          : -INFINITY;
       row_cnt[L][t] = 0;
     }
   }
 
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
   const int kch = a.kchunks;
   const int total = ntiles * kch;
-  const int64_t ld = a.ld_bytes;
-  const uint8_t* __restrict__ Xs = a.Xs;
-  Pref pf;
-
+  const int ld = (int)a.ld_bytes;
   const int l32 = lane & 31, half = lane >> 5;
   const int64_t rrel0 = row0 - a.r0;
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-    for (int rb2 = 0; rb2 < 2; ++rb2)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[cb][rb2][i] = 0.f;
+  const uint64_t tot_bytes = (uint64_t)a.npad * (uint64_t)ld;
+  const i32x4 rres = make_res(a.Xs + row0 * ld, tot_bytes - (uint64_t)row0 * ld);
 
-  if (total > 0) {
-    tile_gload(Xs, ld, row0, sc0, 0, tid, pf);
-    tile_lstore(smem, 0, tid, pf);
+  f32x16 acc[4][2];
+
+  // prologue: chunks 0 and 1 in flight
+  for (int g = 0; g < 2 && g < total; ++g) {
+    const int t = g / kch;
+    const int64_t ct = sc0 + (int64_t)t * BN;
+    issue_chunk(smem + (g % NSTAGE) * STAGE, rres, make_res(a.Xs + ct * ld, tot_bytes - (uint64_t)ct * ld), ld,
+                g - t * kch, wave, lane);
   }
-  __syncthreads();
 
-  for (int g = 0; g < total; ++g) {
-    const int tile = g / kch, ch = g - tile * kch;
-    if (g + 1 < total) {
-      const int tn = (g + 1) / kch;
-      tile_gload(Xs, ld, row0, sc0 + (int64_t)tn * BN, (g + 1) - tn * kch, tid, pf);
+  for (int tile = 0; tile < ntiles; ++tile) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int rb2 = 0; rb2 < 2; ++rb2)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[cb][rb2][i] = 0.f;
+    // descriptors of this tile's and the next tile's columns
+    const int64_t ctc = sc0 + (int64_t)tile * BN;
+    const i32x4 cres_cur = make_res(a.Xs + ctc * ld, tot_bytes - (uint64_t)ctc * ld);
+    const int64_t ctn = ctc + BN;
+    const i32x4 cres_nxt = make_res(a.Xs + ctn * ld, tot_bytes > (uint64_t)ctn * ld ? tot_bytes - (uint64_t)ctn * ld : 0);
+    for (int ch = 0; ch < kch; ++ch) {
+      const int g = tile * kch + ch;
+      // chunk g has landed once at most the next chunk's loads are pending;
+      // right after an epilogue (candidate stores, compaction loads) and at
+      // the end drain everything
+      if (ch == 0 || g + 1 >= total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+      else __builtin_amdgcn_s_waitcnt(waitcnt_vm(DMA_PER_WAVE));
+      __syncthreads();
+      if (g + 2 < total) {
+        const int t2 = (g + 2) / kch, ch2 = (g + 2) - t2 * kch;
+        i32x4 cres = t2 == tile ? cres_cur : cres_nxt;
+        if (t2 > tile + 1) {  // one chunk per tile: the prefetch runs two tiles ahead
+          const int64_t ct2 = sc0 + (int64_t)t2 * BN;
+          cres = make_res(a.Xs + ct2 * ld, tot_bytes - (uint64_t)ct2 * ld);
+        }
+        issue_chunk(smem + ((g + 2) % NSTAGE) * STAGE, rres, cres, ld, ch2, wave, lane);
+      }
+      const uint8_t* S = smem + (g % NSTAGE) * STAGE;
+      mma_chunk<PREC>(S, S + RBYTES, wr, wc, lane, acc);
     }
-    {
-      const uint8_t* R = smem + (g & 1) * 2 * OPB;
-      mma_chunk<PREC>(R, R + OPB, wr, wc, lane, acc);
-    }
-    if (g + 1 < total) tile_lstore(smem, (g + 1) & 1, tid, pf);
-    __syncthreads();
-    if (ch != kch - 1) continue;
 
-    // ---------------- epilogue of one 128 x 128 tile ----------------
+    // ---------------- epilogue of one 128 x 256 tile ----------------
     const int64_t ct0 = sc0 + (int64_t)tile * BN;
-    if (tid < BN) {
-      const int64_t c = ct0 + tid;
+    {
+      const int64_t c = ct0 + tid;  // NT == BN
       const bool cv = c < sc1;
       col_n2[tid] = cv ? a.n2[c] : INFINITY;
       col_cam[tid] = (a.cam && cv) ? a.cam[c] : 0;
@@ -276,101 +332,158 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     }
     __syncthreads();
 
-    uint64_t pend0 = 0, pend1 = 0;
-    int it = 0;
+    // Keys of the whole tile (ineligible entries become +inf), and a vote:
+    // which 32-column blocks hold any key under its row's threshold.  Blocks
+    // nobody votes for skip the admission protocol altogether, which after
+    // the first tiles is almost every block.
+    uint32_t myvote = 0;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int rb2 = 0; rb2 < 2; ++rb2) {
+      const int lr = wr + 32 * rb2 + l32;
+      const int64_t row = row0 + lr;
+      const float tmax = NL > 1 ? fmaxf(row_thr[0][lr], row_thr[NL - 1][lr]) : row_thr[0][lr];
+      const float rs = row_sc[lr];
+      const bool rvalid = row < a.r1;
 #pragma unroll
-      for (int rb2 = 0; rb2 < 2; ++rb2) {
-        const int lr = wr + 32 * rb2 + l32;
-        const int64_t row = row0 + lr;
-        const float t0 = row_thr[0][lr];
-        const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
-        const float rs = row_sc[lr];
-        const int rc = row_cam[lr];
+      for (int cb = 0; cb < 4; ++cb) {
+        float mn = INFINITY;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
           const int64_t col = ct0 + lc;
           float s = acc[cb][rb2][i];
           if (PREC == GCR_PREC_FP8) s = s * (rs * col_sc[lc]);
-          const float key = col_n2[lc] - 2.0f * s;
+          const bool valid = rvalid && col < sc1 && !(a.exclude_self && col == row);
+          const float key = valid ? col_n2[lc] - 2.0f * s : INFINITY;
           acc[cb][rb2][i] = key;
-          const bool valid = col < sc1 && row < a.r1 && !(a.exclude_self && col == row);
-          const int bit = cb * 32 + rb2 * 16 + i;
-          if (valid && key <= t0) pend0 |= 1ull << bit;
-          if (NL > 1 && valid && col_cam[lc] != rc && key <= t1) pend1 |= 1ull << bit;
+          mn = fminf(mn, key);
         }
+        if (mn <= tmax) myvote |= 1u << cb;
       }
+    }
+    {
+      uint32_t wv = 0;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        if (__any((myvote >> cb) & 1u)) wv |= 1u << cb;
+      if (lane == 0 && wv) atomicOr(&cb_vote[tile & 1], wv);
+    }
+    __syncthreads();
+    const uint32_t votes = cb_vote[tile & 1];
+    if (tid == 0) cb_vote[(tile + 1) & 1] = 0u;
+    int it = 0;
 
-    while (true) {
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < 4; ++cb) {
+      if (!((votes >> cb) & 1u)) continue;  // uniform over the workgroup
+      uint32_t pend[NL];
 #pragma unroll
-        for (int rb2 = 0; rb2 < 2; ++rb2)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int bit = cb * 32 + rb2 * 16 + i;
-            const int lr = wr + 32 * rb2 + l32;
-            const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
-            const uint32_t colrel = (uint32_t)(ct0 + lc - a.c0);
-#pragma unroll
-            for (int L = 0; L < NL; ++L) {
-              uint64_t& pend = L == 0 ? pend0 : pend1;
-              if ((pend >> bit) & 1ull) {
-                const int slot = atomicAdd(&row_cnt[L][lr], 1);
-                if (slot < a.C) {
-                  a.cand[(((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C + slot] =
-                      pack_cand(acc[cb][rb2][i], colrel);
-                  pend &= ~(1ull << bit);
-                }
-              }
-            }
-          }
-      const bool mine = (pend0 | pend1) != 0ull;
-      if (__any(mine) && lane == 0) any_flag[it & 1] = 1;
-      __syncthreads();
-      const int any = any_flag[it & 1];
-      if (tid == 0) any_flag[(it + 1) & 1] = 0;
-      ++it;
-      if (!any) break;
-      for (int q = wave; q < NL * BM; q += NT / 64) {
-        const int L = q / BM, lr = q - L * BM;
-        if (row_cnt[L][lr] >= a.C) {
-          uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
-          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C,
-                         L == 0 ? a.k0 : a.k1, row_twoE[lr]);
-        }
-      }
-      __syncthreads();
+      for (int L = 0; L < NL; ++L) pend[L] = 0u;
 #pragma unroll
       for (int rb2 = 0; rb2 < 2; ++rb2) {
         const int lr = wr + 32 * rb2 + l32;
         const float t0 = row_thr[0][lr];
         const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
+        const int rc = row_cam[lr];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int i = 0; i < 16; ++i) {
+          const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
+          const float key = acc[cb][rb2][i];
+          const int bit = rb2 * 16 + i;
+          if (key <= t0) pend[0] |= 1u << bit;
+          if (NL > 1 && col_cam[lc] != rc && key <= t1) pend[NL - 1] |= 1u << bit;
+        }
+      }
+      while (true) {
+        uint32_t anyp = 0;
+#pragma unroll
+        for (int L = 0; L < NL; ++L) anyp |= pend[L];
+        if (__any(anyp != 0u)) {
+          // one atomic per (row, list) reserves all of this lane's slots;
+          // each pending score then goes to base + its rank among them
+          int base[2][NL], room[2][NL];
+#pragma unroll
+          for (int rb2 = 0; rb2 < 2; ++rb2) {
+            const int lr = wr + 32 * rb2 + l32;
+#pragma unroll
+            for (int L = 0; L < NL; ++L) {
+              const int c = __popc((pend[L] >> (rb2 * 16)) & 0xffffu);
+              base[rb2][L] = c ? atomicAdd(&row_cnt[L][lr], c) : 0;
+              room[rb2][L] = max(0, min(c, a.C - base[rb2][L]));
+            }
+          }
+#pragma unroll
+          for (int rb2 = 0; rb2 < 2; ++rb2) {
+            const int lr = wr + 32 * rb2 + l32;
+#pragma unroll
+            for (int L = 0; L < NL; ++L) {
+              const uint32_t m16 = (pend[L] >> (rb2 * 16)) & 0xffffu;
+              if (room[rb2][L] > 0) {
+                uint64_t* rowbuf = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C + base[rb2][L];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                  const uint32_t bit = 1u << i;
+                  const int rank = __popc(m16 & (bit - 1u));
+                  if ((m16 & bit) && rank < room[rb2][L]) {
+                    const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
+                    rowbuf[rank] = pack_cand(acc[cb][rb2][i], (uint32_t)(ct0 + lc - a.c0));
+                    pend[L] &= ~(bit << (rb2 * 16));
+                  }
+                }
+              }
+            }
+          }
+        }
+        anyp = 0;
+#pragma unroll
+        for (int L = 0; L < NL; ++L) anyp |= pend[L];
+        if (__any(anyp != 0u) && lane == 0) any_flag[it & 1] = 1;
+        __syncthreads();
+        const int any = any_flag[it & 1];
+        if (tid == 0) any_flag[(it + 1) & 1] = 0;
+        ++it;
+        if (!any) break;
+        for (int q = wave; q < NL * BM; q += NT / 64) {
+          const int L = q / BM, lr = q - L * BM;
+          if (row_cnt[L][lr] >= a.C) {
+            uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
+            compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rb2 = 0; rb2 < 2; ++rb2) {
+          const int lr = wr + 32 * rb2 + l32;
+          const float t0 = row_thr[0][lr];
+          const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            const int bit = cb * 32 + rb2 * 16 + i;
-            if (!(acc[cb][rb2][i] <= t0)) pend0 &= ~(1ull << bit);
-            if (NL > 1 && !(acc[cb][rb2][i] <= t1)) pend1 &= ~(1ull << bit);
+            const uint32_t m = 1u << (rb2 * 16 + i);
+            if (!(acc[cb][rb2][i] <= t0)) pend[0] &= ~m;
+            if (NL > 1 && !(acc[cb][rb2][i] <= t1)) pend[NL - 1] &= ~m;
           }
+        }
       }
     }
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int rb2 = 0; rb2 < 2; ++rb2)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[cb][rb2][i] = 0.f;
+    if (tile == 0) {
+      // set every row's threshold from its first tile instead of waiting
+      // for its buffer to fill
+      for (int q = wave; q < NL * BM; q += NT / 64) {
+        const int L = q / BM, lr = q - L * BM;
+        const int kk = L == 0 ? a.k0 : a.k1;
+        if (kk > 0 && row_cnt[L][lr] >= kk) {
+          uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
+          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, kk, row_twoE[lr]);
+        }
+      }
+      __syncthreads();
+    }
   }
 
   __syncthreads();
   for (int t = tid; t < BM * NL; t += NT) {
     const int L = t / BM, lr = t - L * BM;
-    if (row0 + lr < a.r1)
-    {
+    if (row0 + lr < a.r1) {
       const int64_t o = ((rrel0 + lr) * NL + L) * (int64_t)a.S + cs;
       a.cnt[o] = min(row_cnt[L][lr], a.C);
       a.thr[o] = row_thr[L][lr];
@@ -383,15 +496,19 @@ static void launch_prec_nl(const SimArgs& a, hipStream_t st) {
   const dim3 grid(sim_topk_grid(a.RB, a.S)), block(NT);
   if (a.C <= 64) {
     auto k = sim_topk_kernel<PREC, NL, 1>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
     hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
   } else if (a.C <= 128) {
     auto k = sim_topk_kernel<PREC, NL, 2>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
+    hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
+  } else if (a.C <= 256) {
+    auto k = sim_topk_kernel<PREC, NL, 4>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
     hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
   } else {
-    auto k = sim_topk_kernel<PREC, NL, 4>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
+    auto k = sim_topk_kernel<PREC, NL, 8>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
     hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
   }
 }

@@ -73,17 +73,18 @@ def test_knn_cross_camera(ctx, prec):
 
 
 def test_knn_duplicates_force_fallback(ctx):
-    # 200 identical points: every screened key ties, the candidate buffers
-    # overflow and the exhaustive path must still return (distance, index)
-    # order, i.e. the lowest indices
+    # 3,000 identical points: every screened key ties, the candidate buffers
+    # (512 entries) overflow and the exhaustive path must still return
+    # (distance, index) order, i.e. the lowest indices
     print("knn duplicates", flush=True)
-    X = np.tile(datagen.random_unit(1, 64, 3), (200, 1))
+    n = 3000  # four column splits of 768 columns: more ties than a buffer holds
+    X = np.tile(datagen.random_unit(1, 64, 3), (n, 1))
     ctx.reset_stats()
     idx, dist = ctx.knn(dev(X), Params(k=20, precision=BF16))
     st = ctx.stats()
     I = host(idx)
-    for i in range(200):
-        exp = [j for j in range(200) if j != i][:20]
+    for i in list(range(0, n, 37)) + [n - 1]:
+        exp = [j for j in range(n) if j != i][:20]
         assert I[i].tolist() == exp
     assert np.all(host(dist) == 0.0)
     assert st["knn_fallback_rows"] > 0
@@ -303,3 +304,26 @@ def test_knn_truncated_splits(ctx, prec):
     check_knn_rows(host(cidx)[rows], host(cdist)[rows], w.X, rows, 15, cam=w.cams, cross=True, what="cross")
     if prec != FP8:
         assert st["knn_fallback_rows"] == 0, st
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_knn_exact_ties_exhaustive_paths(ctx, prec):
+    """9,000 rows that are 5 distinct points repeated: every neighbour is at
+    distance 0, each column split (two of 4,500 columns) holds ~900 ties,
+    more than a candidate buffer keeps, so every row takes the exhaustive
+    path (the chunked path and, past its capacity, the one-block-per-row
+    path) and the lists must be the lowest indices of the same point in
+    (distance, index) order."""
+    print(f"knn exact ties prec={prec}", flush=True)
+    n, d, k = 9000, 16, 20
+    base = datagen.random_unit(5, d, 21)
+    X = base[np.arange(n) % 5]
+    ctx.reset_stats()
+    idx, dist = ctx.knn(dev(X), Params(k=k, precision=prec))
+    st = ctx.stats()
+    I = host(idx)
+    for i in list(range(0, n, 97)) + [n - 1]:
+        exp = [j for j in range(i % 5, n, 5) if j != i][:k]
+        assert I[i].tolist() == exp, i
+    assert np.all(host(dist) == 0.0)
+    assert st["knn_fallback_rows"] == n
