@@ -101,8 +101,11 @@ const char* gcr_last_error(const gcr_ctx* ctx);
 typedef struct {
   int64_t knn_rows;           /* rows whose neighbour lists were built         */
   int64_t knn_candidates;     /* screened candidates re-scored exactly         */
-  int64_t knn_fallback_rows;  /* rows recomputed exhaustively (buffer full)    */
+  int64_t knn_fallback_rows;  /* (row, list) pairs re-swept in float32 because
+                                 a truncated buffer did not reach the cut      */
   int64_t splits;             /* column splits of the last similarity sweep    */
+  int64_t knn_exhaustive_rows;/* (row, list) pairs whose float32 band exceeded
+                                 2,048 items, scored exactly over all columns */
 } gcr_stats;
 gcr_status gcr_get_stats(gcr_ctx* ctx, gcr_stats* out);
 gcr_status gcr_reset_stats(gcr_ctx* ctx);

@@ -25,7 +25,7 @@ struct gcr_ctx {
   std::string err;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  unsigned long long* stats = nullptr;  // device: [0] candidates, [1] fallback rows
+  unsigned long long* stats = nullptr;  // device: [0] candidates, [1] re-swept pairs, [2] exhaustive pairs
   int64_t knn_rows = 0;
   int64_t splits = 0;
 };
@@ -171,6 +171,7 @@ struct KnnPlan {
   uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
   uint64_t* fb_pk; uint32_t* fb_pc;
   float* seed;
+  float* fb_cut; uint64_t* band; int* band_cnt; int band_cap, band_max; int* ovf_list;
 };
 
 void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
@@ -204,6 +205,12 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.seed = ar.take<float>((size_t)kp.rows * kp.nl);
   kp.thr = ar.take<float>((size_t)kp.rows * kp.nl * S);
   kp.fb_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
+  kp.fb_cut = ar.take<float>((size_t)kp.rows * kp.nl + 1);
+  kp.ovf_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
+  kp.band_max = (int)std::min<int64_t>(2048, kp.rows * kp.nl);
+  kp.band_cap = 2048;
+  kp.band = ar.take<uint64_t>((size_t)kp.band_max * kp.band_cap + 1);
+  kp.band_cnt = ar.take<int>((size_t)kp.band_max + 1);
   kp.fb_count = ar.take<int>(64);
   kp.fb_scr = ar.take<uint64_t>((size_t)kp.fb_grid * std::max<int64_t>(kp.ncols, 1));
   {
@@ -223,7 +230,8 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
              int32_t* idx1, float* dist1, hipStream_t st, const int32_t* prev0 = nullptr,
              const int32_t* prev1 = nullptr) {
   fill_u32(kp.maxn2, 0u, 1, st);
-  fill_u32(kp.fb_count, 0u, 1, st);
+  fill_u32(kp.fb_count, 0u, 2, st);
+  fill_u32(kp.band_cnt, 0u, kp.band_max, st);
   {
     TimedScope ts(c, 5, st);
     launch_screen_prep(kp.prec, X, kp.n, d, kp.npad, kp.Xs, kp.ld, kp.n2, kp.scale, kp.maxn2, st);
@@ -256,11 +264,15 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   ra.fb_list = kp.fb_list; ra.fb_count = kp.fb_count; ra.stat_cands = c->stats;
   ra.fb_scratch = kp.fb_scr; ra.fb_grid = kp.fb_grid;
   ra.fb_part_key = kp.fb_pk; ra.fb_part_col = kp.fb_pc;
+  ra.fb_cut = kp.fb_cut; ra.eps32 = eps_similarity(GCR_PREC_FP32, d);
+  ra.band = kp.band; ra.band_cnt = kp.band_cnt; ra.band_cap = kp.band_cap; ra.band_max = kp.band_max;
+  ra.ovf_list = kp.ovf_list; ra.ovf_count = kp.fb_count + 1;
   {
     TimedScope ts(c, 1, st);
     launch_refine(ra, st);
   }
   hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(1), 0, st, c->stats + 1, kp.fb_count);
+  hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(1), 0, st, c->stats + 2, kp.fb_count + 1);
   c->knn_rows += kp.rows;
   c->splits = kp.S;
 }
@@ -454,6 +466,7 @@ gcr_status gcr_get_stats(gcr_ctx* c, gcr_stats* out) {
   out->knn_rows = c->knn_rows;
   out->knn_candidates = (int64_t)h[0];
   out->knn_fallback_rows = (int64_t)h[1];
+  out->knn_exhaustive_rows = (int64_t)h[2];
   out->splits = c->splits;
   return GCR_OK;
 }

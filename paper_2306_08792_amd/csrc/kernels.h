@@ -75,6 +75,13 @@ struct RefineArgs {
   int fb_grid;
   uint64_t* fb_part_key;           // [min(FB_MAX, pairs), chunks, k] chunk winners
   uint32_t* fb_part_col;
+  float* fb_cut;      // [(r1-r0) * NL] upper bound on the exact k-th key of queued pair f
+  float eps32;        // screening coefficient of the float32 band sweep
+  uint64_t* band;     // [band_max, band_cap] (key32, column) of the swept band
+  int* band_cnt;      // [band_max] zero before the launch
+  int band_cap, band_max;
+  int* ovf_list;      // [(r1-r0) * NL] pairs for the exhaustive path
+  int* ovf_count;     // device counter, zero before the launch
 };
 // queued pairs handled by the column-parallel exhaustive path
 constexpr int FB_MAX = 8192;

@@ -123,6 +123,9 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
     if (tid == 0) {
       const int slot = atomicAdd(a.fb_count, 1);
       a.fb_list[slot] = (int)(rrel * 2 + L);
+      // the k items with screened key <= tau have exact keys <= tau + E,
+      // hence so does the exact k-th smallest key of the row
+      a.fb_cut[slot] = tau + 0.5f * twoE;
     }
     return;
   }
@@ -211,10 +214,10 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(RefineArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ncols = a.c1 - a.c0;
   const int nch = (int)((ncols + FB_CW - 1) / FB_CW);
-  const int nfb = min(*a.fb_count, FB_MAX);
+  const int nfb = min(*a.ovf_count, FB_MAX);
   for (int64_t wi = blockIdx.x; wi < (int64_t)nfb * nch; wi += gridDim.x) {
     const int f = (int)(wi / nch), ch = (int)(wi - (int64_t)f * nch);
-    const int code = a.fb_list[f];
+    const int code = a.ovf_list[f];
     const int64_t rrel = code >> 1;
     const int L = code & 1;
     const int64_t row = a.r0 + rrel;
@@ -273,9 +276,9 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(RefineArgs a) {
   const int tid = threadIdx.x;
   const int64_t ncols = a.c1 - a.c0;
   const int nch = (int)((ncols + FB_CW - 1) / FB_CW);
-  const int nfb = min(*a.fb_count, FB_MAX);
+  const int nfb = min(*a.ovf_count, FB_MAX);
   for (int f = blockIdx.x; f < nfb; f += gridDim.x) {
-    const int code = a.fb_list[f];
+    const int code = a.ovf_list[f];
     const int64_t rrel = code >> 1;
     const int L = code & 1;
     const int kk = L == 0 ? a.k0 : a.k1;
@@ -318,9 +321,9 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ncols = a.c1 - a.c0;
   uint64_t* scr = a.fb_scratch + (int64_t)blockIdx.x * ncols;
-  const int nfb = *a.fb_count;
+  const int nfb = *a.ovf_count;
   for (int f = FB_MAX + blockIdx.x; f < nfb; f += gridDim.x) {
-    const int code = a.fb_list[f];
+    const int code = a.ovf_list[f];
     const int64_t rrel = code >> 1;
     const int L = code & 1;
     const int64_t row = a.r0 + rrel;
@@ -385,6 +388,206 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Band re-sweep for queued (row, list) pairs.  Pair f carries an upper bound
+// ub_f on its exact k-th smallest key.  The sweep scores the pair's row
+// against every column in float32 (sequential fused multiply-adds; error at
+// most E32 = screen_margin at the float32 coefficient) and keeps each
+// eligible column with key32 <= ub_f + E32, which holds every exact top-k
+// member; the kept set is the prefix of the key32 order, so its k-th element
+// is the global k-th smallest key32, tau32.  The selection then re-scores
+// only the items with key32 <= tau32 + 2 E32 exactly.  Pairs whose kept set
+// exceeds the band capacity go to the exhaustive path.
+namespace {
+constexpr int BT_R = 32;   // pairs per sweep tile
+constexpr int BT_C = 128;  // columns per sweep tile
+constexpr int BT_K = 32;   // feature chunk
+}  // namespace
+
+__global__ __launch_bounds__(256) void band_sweep_kernel(RefineArgs a) {
+  __shared__ float As[BT_K][BT_R];
+  __shared__ float Bs[BT_K][BT_C + 4];
+  __shared__ int64_t s_row[BT_R];
+  __shared__ int s_list[BT_R];
+  __shared__ int s_cam[BT_R];
+  __shared__ float s_cut[BT_R];
+  const int tid = threadIdx.x;
+  const int64_t ncols = a.c1 - a.c0;
+  const int nf = min(*a.fb_count, a.band_max);
+  const int nrt = (nf + BT_R - 1) / BT_R;
+  const int nct = (int)((ncols + BT_C - 1) / BT_C);
+  const int d = a.d;
+  const bool vec = (d & 3) == 0 && (((uintptr_t)a.X) & 15) == 0;
+  const float mx = *a.maxn2;
+  const int eg = tid >> 5, cg = tid & 31;   // 4 pairs x 4 columns per thread
+  for (int64_t wi = blockIdx.x; wi < (int64_t)nrt * nct; wi += gridDim.x) {
+    const int rt = (int)(wi % nrt);
+    const int ct = (int)(wi / nrt);
+    const int f0 = rt * BT_R;
+    const int64_t j0 = (int64_t)ct * BT_C;
+    __syncthreads();
+    if (tid < BT_R) {
+      const int f = f0 + tid;
+      if (f < nf) {
+        const int code = a.fb_list[f];
+        const int64_t row = a.r0 + (code >> 1);
+        s_row[tid] = row;
+        s_list[tid] = code & 1;
+        s_cam[tid] = a.cam ? a.cam[row] : 0;
+        const float n2r = a.n2[row];
+        s_cut[tid] = a.fb_cut[f] + screen_margin(n2r, mx, a.eps32, a.eps_n);
+      } else {
+        s_row[tid] = -1;
+        s_list[tid] = 0;
+        s_cam[tid] = 0;
+        s_cut[tid] = -INFINITY;
+      }
+    }
+    __syncthreads();
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    // staging: pair tid / 8 takes floats 4 (tid % 8) .. +3 of the chunk;
+    // column tid / 2 takes floats 16 (tid % 2) .. +15
+    const int ar = tid >> 3, ak = (tid & 7) * 4;
+    const int bc = tid >> 1, bk = (tid & 1) * 16;
+    const int64_t arow = s_row[ar];
+    const int64_t bcol = j0 + bc < ncols ? a.c0 + j0 + bc : -1;
+    const float* ap = arow >= 0 ? a.X + arow * (int64_t)d : nullptr;
+    const float* bp = bcol >= 0 ? a.X + bcol * (int64_t)d : nullptr;
+    for (int k0 = 0; k0 < d; k0 += BT_K) {
+      float av[4], bv[16];
+      if (vec && k0 + BT_K <= d) {
+        const f32x4 t = ap ? *(const f32x4*)(ap + k0 + ak) : f32x4{0.f, 0.f, 0.f, 0.f};
+        av[0] = t.x; av[1] = t.y; av[2] = t.z; av[3] = t.w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 u = bp ? *(const f32x4*)(bp + k0 + bk + 4 * q) : f32x4{0.f, 0.f, 0.f, 0.f};
+          bv[4 * q] = u.x; bv[4 * q + 1] = u.y; bv[4 * q + 2] = u.z; bv[4 * q + 3] = u.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) av[q] = (ap && k0 + ak + q < d) ? ap[k0 + ak + q] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) bv[q] = (bp && k0 + bk + q < d) ? bp[k0 + bk + q] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[ak + q][ar] = av[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) Bs[bk + q][bc] = bv[q];
+      __syncthreads();
+#pragma unroll 8
+      for (int k = 0; k < BT_K; ++k) {
+        const f32x4 x = *(const f32x4*)&As[k][eg * 4];
+        const f32x4 y = *(const f32x4*)&Bs[k][cg * 4];
+        const float xa[4] = {x.x, x.y, x.z, x.w}, ya[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(xa[i], ya[j], acc[i][j]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int pr = eg * 4 + i;
+      const int64_t row = s_row[pr];
+      if (row < 0) continue;
+      const int L = s_list[pr];
+      const float cut = s_cut[pr];
+      const int f = f0 + pr;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t jr = j0 + cg * 4 + j;
+        if (jr >= ncols) continue;
+        const int64_t col = a.c0 + jr;
+        if (a.exclude_self && col == row) continue;
+        if (L == 1 && a.cam[col] == s_cam[pr]) continue;
+        const float key = a.n2[col] - 2.0f * acc[i][j];
+        if (key <= cut) {
+          const int slot = atomicAdd(&a.band_cnt[f], 1);
+          if (slot < a.band_cap)
+            a.band[(int64_t)f * a.band_cap + slot] = ((uint64_t)ord_f32(key) << 32) | (uint64_t)(uint32_t)jr;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
+  __shared__ uint64_t U[UMAX];
+  __shared__ uint32_t ux[UMAX];
+  __shared__ uint64_t ek[UMAX];
+  __shared__ uint32_t ec[UMAX];
+  __shared__ int s_M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nfb = *a.fb_count;
+  const int nf = min(nfb, a.band_max);
+  // pairs past the band capacity go straight to the exhaustive path
+  for (int f = a.band_max + blockIdx.x * RT + tid; f < nfb; f += gridDim.x * RT) {
+    const int slot = atomicAdd(a.ovf_count, 1);
+    a.ovf_list[slot] = a.fb_list[f];
+  }
+  for (int f = blockIdx.x; f < nf; f += gridDim.x) {
+    const int code = a.fb_list[f];
+    const int64_t rrel = code >> 1;
+    const int L = code & 1;
+    const int64_t row = a.r0 + rrel;
+    const int kk = L == 0 ? a.k0 : a.k1;
+    const int T = a.band_cnt[f];
+    if (T > a.band_cap) {
+      if (tid == 0) {
+        const int slot = atomicAdd(a.ovf_count, 1);
+        a.ovf_list[slot] = code;
+      }
+      continue;
+    }
+    int32_t* oidx = (L == 0 ? a.idx0 : a.idx1) + rrel * kk;
+    float* odist = (L == 0 ? a.dist0 : a.dist1) + rrel * kk;
+    int P = 64;
+    while (P < T) P <<= 1;
+    const uint64_t* src = a.band + (int64_t)f * a.band_cap;
+    __syncthreads();
+    for (int t = tid; t < P; t += RT) {
+      U[t] = t < T ? src[t] : GCR_EMPTY;
+      ux[t] = 0u;
+    }
+    if (tid == 0) s_M = 0;
+    __syncthreads();
+    block_sort_pairs(U, ux, P);
+    const float e32 = screen_margin(a.n2[row], *a.maxn2, a.eps32, a.eps_n);
+    const float th = (T >= kk && kk > 0) ? cand_key(U[kk - 1]) + 2.0f * e32 : INFINITY;
+    int mine = 0;
+    for (int t = tid; t < T; t += RT) mine += cand_key(U[t]) <= th ? 1 : 0;
+    if (mine) atomicAdd(&s_M, mine);
+    __syncthreads();
+    const int M = s_M;
+    const float* xr = a.X + row * (int64_t)a.d;
+    for (int m = wave; m < M; m += RT / 64) {
+      const uint32_t col = cand_col(U[m]);
+      const uint64_t ex = wave_exact_sqdist(xr, a.X + (a.c0 + (int64_t)col) * a.d, a.d);
+      if (lane == 0) { ek[m] = ex; ec[m] = col; }
+    }
+    int P2 = 64;
+    while (P2 < M) P2 <<= 1;
+    for (int t = M + tid; t < P2; t += RT) { ek[t] = GCR_EMPTY; ec[t] = 0xffffffffu; }
+    __syncthreads();
+    block_sort_pairs(ek, ec, P2);
+    for (int t = tid; t < kk; t += RT) {
+      if (t < M) {
+        oidx[t] = (int32_t)ec[t];
+        odist[t] = exact_hi(ek[t]);
+      } else {
+        oidx[t] = -1;
+        odist[t] = INFINITY;
+      }
+    }
+  }
+}
+
 // One wave per (row, list).  If the previous list of the row has k valid
 // members j, the k-th smallest exact key of the row is at most
 // U = max_j ||x_i - x_j||^2 - n2_i (up to the float32 error of n2_i), so the
@@ -437,6 +640,8 @@ void launch_refine(const RefineArgs& a, hipStream_t st) {
   const int64_t rows = a.r1 - a.r0;
   if (rows <= 0) return;
   hipLaunchKernelGGL(refine_kernel, dim3((unsigned)(rows * a.NL)), dim3(RT), 0, st, a);
+  hipLaunchKernelGGL(band_sweep_kernel, dim3(2048), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(band_select_kernel, dim3(1024), dim3(RT), 0, st, a);
   hipLaunchKernelGGL(fallback_scan_kernel, dim3(2048), dim3(256), 0, st, a);
   hipLaunchKernelGGL(fallback_merge_kernel, dim3(1024), dim3(256), 0, st, a);
   hipLaunchKernelGGL(fallback_kernel, dim3(a.fb_grid), dim3(FBT), 0, st, a);

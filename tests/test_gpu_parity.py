@@ -88,6 +88,46 @@ def test_knn_duplicates_force_fallback(ctx):
         assert I[i].tolist() == exp
     assert np.all(host(dist) == 0.0)
     assert st["knn_fallback_rows"] > 0
+    # 2,999 ties per row exceed the float32 band (2,048 items)
+    assert st["knn_exhaustive_rows"] > 0
+
+
+def shell_workload(hubs=12, shell=1500, d=64, seed=5):
+    """Hubs with a shell of points whose squared distances to the hub are
+    spread over [0.5, 0.51]: a hub's k-th neighbour sits inside a band of
+    1,500 items narrower than the BF16 screening margin, more than one
+    candidate buffer (512) keeps.  Returns (X, hub row indices)."""
+    rng = np.random.default_rng(seed)
+    H = datagen.random_unit(hubs, d, seed + 1).astype(np.float64)
+    pts = []
+    for h in H:
+        U = rng.standard_normal((shell, d))
+        U -= np.outer(U @ h, h)
+        U /= np.linalg.norm(U, axis=1, keepdims=True)
+        rho = np.sqrt(rng.uniform(0.5, 0.51, shell))
+        pts.append(np.vstack([h[None], h[None] + rho[:, None] * U]))
+    X = np.vstack(pts).astype(np.float32)
+    perm = rng.permutation(len(X))
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(X))
+    return X[perm], np.sort(inv[np.arange(hubs) * (shell + 1)])
+
+
+@pytest.mark.parametrize("prec", [BF16, FP8])
+def test_knn_band_resweep(ctx, prec):
+    """Rows whose screening band overflows the candidate buffer are re-swept
+    in float32 against every column; their lists stay exact, and a band
+    within the re-sweep capacity (2,048 items) needs no exhaustive pass."""
+    print(f"knn band re-sweep prec={prec}", flush=True)
+    X, hub_rows = shell_workload()
+    n = len(X)
+    ctx.reset_stats()
+    idx, dist = ctx.knn(dev(X), Params(k=20, precision=prec))
+    st = ctx.stats()
+    rows = np.union1d(hub_rows, np.arange(0, n, 211))
+    check_knn_rows(host(idx)[rows], host(dist)[rows], X, rows, 20)
+    assert st["knn_fallback_rows"] >= len(hub_rows), st
+    assert st["knn_exhaustive_rows"] <= max(0, st["knn_fallback_rows"] - 2048), st
 
 
 def test_knn_k0_and_empty_cross(ctx):
@@ -307,23 +347,26 @@ def test_knn_truncated_splits(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16])
-def test_knn_exact_ties_exhaustive_paths(ctx, prec):
-    """9,000 rows that are 5 distinct points repeated: every neighbour is at
-    distance 0, each column split (two of 4,500 columns) holds ~900 ties,
-    more than a candidate buffer keeps, so every row takes the exhaustive
-    path (the chunked path and, past its capacity, the one-block-per-row
-    path) and the lists must be the lowest indices of the same point in
-    (distance, index) order."""
-    print(f"knn exact ties prec={prec}", flush=True)
+@pytest.mark.parametrize("npts", [5, 1])
+def test_knn_exact_ties_exhaustive_paths(ctx, prec, npts):
+    """9,000 rows that are `npts` distinct points repeated: every neighbour
+    is at distance 0 and a column split holds more ties than a candidate
+    buffer keeps.  A buffer cannot keep part of a tie, so it truncates below
+    the tied key, the row has no bound on its k-th distance and every row
+    takes the exhaustive paths (column-chunked, then one block per row past
+    its capacity).  The lists must be the lowest indices of the same point
+    in (distance, index) order."""
+    print(f"knn exact ties prec={prec} points={npts}", flush=True)
     n, d, k = 9000, 16, 20
-    base = datagen.random_unit(5, d, 21)
-    X = base[np.arange(n) % 5]
+    base = datagen.random_unit(npts, d, 21)
+    X = base[np.arange(n) % npts]
     ctx.reset_stats()
     idx, dist = ctx.knn(dev(X), Params(k=k, precision=prec))
     st = ctx.stats()
     I = host(idx)
     for i in list(range(0, n, 97)) + [n - 1]:
-        exp = [j for j in range(i % 5, n, 5) if j != i][:k]
+        exp = [j for j in range(i % npts, n, npts) if j != i][:k]
         assert I[i].tolist() == exp, i
     assert np.all(host(dist) == 0.0)
     assert st["knn_fallback_rows"] == n
+    assert st["knn_exhaustive_rows"] == n, st
