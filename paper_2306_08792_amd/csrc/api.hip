@@ -225,10 +225,12 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
 // Screening + refine for rows [r0, r1) against columns [c0, c1) of X.
 // prev0 / prev1: earlier neighbour lists of the same rows (graph rebuilt
 // from updated features) used to seed the admission thresholds, or nullptr.
+// order: processing order of the rows (rows [0, n) only) or nullptr.
 void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* cam, int64_t r0, int64_t r1,
              int64_t c0, int64_t c1, int exclude_self, int k0, int k1, int32_t* idx0, float* dist0,
              int32_t* idx1, float* dist1, hipStream_t st, const int32_t* prev0 = nullptr,
-             const int32_t* prev1 = nullptr) {
+             const int32_t* prev1 = nullptr, const int32_t* order = nullptr) {
+  if (r0 != 0) order = nullptr;
   fill_u32(kp.maxn2, 0u, 1, st);
   fill_u32(kp.fb_count, 0u, 2, st);
   fill_u32(kp.band_cnt, 0u, kp.band_max, st);
@@ -248,7 +250,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   if (prev0 && r0 == 0 && c0 == 0 && r1 == c1 && (k1 == 0 || prev1)) {
     TimedScope ts(c, 1, st);
     launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, (const float*)kp.maxn2,
-                           sa.eps_s, sa.eps_n, kp.seed, st);
+                           sa.eps_s, sa.eps_n, kp.seed, order, st);
     sa.thr_init = kp.seed;
   }
   {
@@ -267,6 +269,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   ra.fb_cut = kp.fb_cut; ra.eps32 = eps_similarity(GCR_PREC_FP32, d);
   ra.band = kp.band; ra.band_cnt = kp.band_cnt; ra.band_cap = kp.band_cap; ra.band_max = kp.band_max;
   ra.ovf_list = kp.ovf_list; ra.ovf_count = kp.fb_count + 1;
+  ra.order = order;
   {
     TimedScope ts(c, 1, st);
     launch_refine(ra, st);
@@ -333,11 +336,14 @@ size_t layout_graph(Arena& ar, gcr_graph* g, int64_t n, int k, int ck, int has_c
 
 struct GraphTmp {
   int32_t* cnt; float* fsum; int32_t* blk;
+  int32_t* label; int32_t* order;  // locality order of the last graph built
 };
 void plan_graph_tmp(Arena& ar, GraphTmp& t, int64_t n) {
   t.cnt = ar.take<int32_t>((size_t)n + 1);
   t.fsum = ar.take<float>((size_t)n + 1);
   t.blk = ar.take<int32_t>((size_t)(n / 1024 + 2));
+  t.label = ar.take<int32_t>((size_t)n);
+  t.order = ar.take<int32_t>((size_t)n);
 }
 
 void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const gcr_params* p, float coef,
@@ -374,7 +380,8 @@ void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, cons
   if (g->k > 0 || (cross && g->cross_k > 0))
     run_knn(c, kp, X, d, cam, 0, n, 0, n, 1, g->k, cross ? g->cross_k : 0, g->idx, g->dist,
             cross ? g->cr_idx : nullptr, cross ? g->cr_dist : nullptr, st,
-            seed_from_previous ? g->idx : nullptr, seed_from_previous && cross ? g->cr_idx : nullptr);
+            seed_from_previous ? g->idx : nullptr, seed_from_previous && cross ? g->cr_idx : nullptr,
+            seed_from_previous && g->k > 0 ? gt.order : nullptr);
   const float alpha = cross ? p->alpha : 1.0f;
   TimedScope ts(c, 2, st);
   build_one(g, false, n, cam, p, alpha, gt, st, false);
@@ -382,13 +389,15 @@ void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, cons
   build_one(g, false, n, cam, p, alpha, gt, st, true);
   if (cross) build_one(g, true, n, cam, p, 1.0f - alpha, gt, st, true);
   launch_self_coef(n, g->deg, cross ? g->cr_deg : nullptr, alpha, g->self, st);
+  if (g->k > 0) launch_locality_order(n, g->idx, g->k, gt.label, gt.cnt, gt.blk, gt.order, st);
 }
 
 void enqueue_propagate(gcr_ctx* c, const gcr_graph* g, const float* Xin, float* Xout, int64_t n, int d,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t* order) {
   TimedScope ts(c, 3, st);
   PropArgs a;
   a.X = Xin; a.Y = Xout; a.n = n; a.d = d; a.self = g->self;
+  a.order = g->k > 0 ? order : nullptr;
   a.idx = g->idx; a.pf = g->pf; a.k = g->k; a.rev_ptr = g->rev_ptr; a.rev_src = g->rev_src; a.pr = g->pr;
   if (g->has_cross) {
     a.cr_idx = g->cr_idx; a.cr_pf = g->cr_pf; a.ck = g->cross_k; a.cr_rev_ptr = g->cr_rev_ptr;
@@ -582,7 +591,18 @@ gcr_status gcr_propagate(gcr_ctx* c, const gcr_graph* g, const float* X_in, floa
   if (X_in == X_out) return fail(c, GCR_ERR_INVALID, "in-place propagation is not allowed");
   if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported by propagation");
   HIP_TRY(c, hipSetDevice(c->device));
-  enqueue_propagate(c, g, X_in, X_out, n, d, (hipStream_t)stream);
+  GraphTmp gt;
+  Arena dry;
+  plan_graph_tmp(dry, gt, n);
+  gcr_status s = ensure_ws(c, dry.off);
+  if (s != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan_graph_tmp(ar, gt, n);
+  if (g->k > 0) {
+    TimedScope ts(c, 2, (hipStream_t)stream);
+    launch_locality_order(n, g->idx, g->k, gt.label, gt.cnt, gt.blk, gt.order, (hipStream_t)stream);
+  }
+  enqueue_propagate(c, g, X_in, X_out, n, d, (hipStream_t)stream, gt.order);
   HIP_TRY(c, hipGetLastError());
   return GCR_OK;
 }
@@ -680,7 +700,7 @@ gcr_status gcr_rerank(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_
   else HIP_TRY(c, hipMemcpyAsync(xa, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
   for (int t = 0; t < p->rounds; ++t) {
     if (t == 0 || p->rebuild_each_round) enqueue_build_graph(c, kp, gt, xa, n, d, cam, p, &g, st, t > 0);
-    enqueue_propagate(c, &g, xa, xb, n, d, st);
+    enqueue_propagate(c, &g, xa, xb, n, d, st, gt.order);
     std::swap(xa, xb);
   }
   run_final(c, fp, xa, nq, ng, d, p, dist_out, topk_idx, topk_dist, st);

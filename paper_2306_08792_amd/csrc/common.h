@@ -135,6 +135,14 @@ __device__ __forceinline__ void wave_bitonic_sort(uint64_t (&v)[E]) {
 // from the exact n2_c - 2 s by at most the returned bound.
 //   eps_s : bound on |s~ - s| / (||x_r|| ||x_c||) for the precision mode
 //   eps_n : bound on the relative error of the float32 squared norms
+// Position of workgroup b among nb workgroups such that each XCD (the
+// dispatcher deals workgroups to the 8 XCDs in turn) walks one contiguous
+// segment of positions: neighbouring positions then share an L2.
+__device__ __forceinline__ int64_t xcd_position(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 __device__ __forceinline__ float screen_margin(float n2r, float maxn2, float eps_s, float eps_n) {
   float nr = sqrtf(n2r), nm = sqrtf(maxn2);
   float es = eps_s * nr * nm;

@@ -162,4 +162,37 @@ void launch_self_coef(int64_t n, const float* deg, const float* cr_deg, float al
   hipLaunchKernelGGL(self_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, deg, cr_deg, alpha, self);
 }
 
+__global__ void label_count_kernel(int64_t n, const int32_t* __restrict__ idx, int k, int32_t* __restrict__ label,
+                                   int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t m = (int32_t)i;
+  for (int t = 0; t < k; ++t) {
+    const int32_t j = idx[i * k + t];
+    if (j >= 0 && j < m) m = j;
+  }
+  label[i] = m;
+  atomicAdd(&cnt[m], 1);
+}
+
+__global__ void order_scatter_kernel(int64_t n, const int32_t* __restrict__ label, int32_t* __restrict__ off,
+                                     int32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  order[atomicAdd(&off[label[i]], 1)] = (int32_t)i;
+}
+
+void launch_locality_order(int64_t n, const int32_t* idx, int k, int32_t* label, int32_t* cnt, int32_t* blk,
+                           int32_t* order, hipStream_t st) {
+  if (n <= 0) return;
+  const int ntiles = (int)((n + 1023) / 1024);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, cnt, n);
+  hipLaunchKernelGGL(label_count_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, idx, k, label, cnt);
+  // exclusive offsets, scanned in place
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(ntiles), dim3(1024), 0, st, cnt, cnt, n, blk);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, blk, ntiles, cnt + n);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, cnt, n, blk);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, label, cnt, order);
+}
+
 }  // namespace gcr

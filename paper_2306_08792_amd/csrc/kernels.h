@@ -47,7 +47,7 @@ int sim_topk_grid(int RB, int S);
 // an upper bound on the k-th distance): out[row * nl + L].
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
                             int k1, const float* n2, const float* maxn2, float eps_s, float eps_n, float* out,
-                            hipStream_t st);
+                            const int32_t* order, hipStream_t st);
 int sim_topk_tile_cols();
 void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
 
@@ -77,6 +77,7 @@ struct RefineArgs {
   uint32_t* fb_part_col;
   float* fb_cut;      // [(r1-r0) * NL] upper bound on the exact k-th key of queued pair f
   float eps32;        // screening coefficient of the float32 band sweep
+  const int32_t* order;  // processing order of the rows [0, n) (r0 == 0) or nullptr
   uint64_t* band;     // [band_max, band_cap] (key32, column) of the swept band
   int* band_cnt;      // [band_max] zero before the launch
   int band_cap, band_max;
@@ -104,6 +105,11 @@ void launch_graph_build(const GraphBuildArgs& a, hipStream_t st);
 void launch_self_coef(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self,
                       hipStream_t st);
 void launch_finish_values(const GraphBuildArgs& a, hipStream_t st);
+// Row processing order that keeps rows sharing neighbours together: rows
+// sorted (counting sort) by the smallest index among themselves and their
+// list members.  label: [n], cnt: [n + 1], blk: scan tile sums.
+void launch_locality_order(int64_t n, const int32_t* idx, int k, int32_t* label, int32_t* cnt, int32_t* blk,
+                           int32_t* order, hipStream_t st);
 
 // ---- propagate.hip
 struct PropArgs {
@@ -113,6 +119,7 @@ struct PropArgs {
   const int32_t* rev_ptr; const int32_t* rev_src; const float* pr;
   const int32_t* cr_idx; const float* cr_pf; int ck;
   const int32_t* cr_rev_ptr; const int32_t* cr_rev_src; const float* cr_pr;
+  const int32_t* order;  // row processing order or nullptr
 };
 void launch_propagate(const PropArgs& a, hipStream_t st);
 

@@ -58,8 +58,9 @@ __device__ __forceinline__ void gather_list(Acc<V>& acc, const float* __restrict
 template <int V>
 __global__ __launch_bounds__(256) void propagate_vec_kernel(PropArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.n) return;
+  const int64_t pos = xcd_position(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (pos >= a.n) return;
+  const int64_t i = a.order ? (int64_t)a.order[pos] : pos;
   const int d = a.d;
   Acc<V> acc;
   {
@@ -118,8 +119,9 @@ __device__ void gather_scalar(float (&acc)[32], const float* __restrict__ X, int
 }
 __global__ __launch_bounds__(256) void propagate_scalar_kernel(PropArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.n) return;
+  const int64_t pos = xcd_position(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (pos >= a.n) return;
+  const int64_t i = a.order ? (int64_t)a.order[pos] : pos;
   const int d = a.d;
   float acc[32];
   const float s = a.self[i];

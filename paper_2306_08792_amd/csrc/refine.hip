@@ -78,8 +78,10 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   __shared__ float s_tmin;
 
   const int NL = a.NL;
-  const int64_t rrel = blockIdx.x / NL;
-  const int L = blockIdx.x - (int)rrel * NL;
+  const int64_t p = xcd_position(blockIdx.x, gridDim.x);
+  const int64_t prel = p / NL;
+  const int L = (int)(p - prel * NL);
+  const int64_t rrel = a.order ? (int64_t)a.order[prel] : prel;
   const int64_t row = a.r0 + rrel;
   if (row >= a.r1) return;
   const int kk = L == 0 ? a.k0 : a.k1;
@@ -598,12 +600,15 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
                                                               const int32_t* __restrict__ idx1, int k1,
                                                               const float* __restrict__ n2,
                                                               const float* __restrict__ maxn2, float eps_s,
-                                                              float eps_n, float* __restrict__ out) {
+                                                              float eps_n, float* __restrict__ out,
+                                                              const int32_t* __restrict__ order) {
   const int nl = idx1 ? 2 : 1;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= n * nl) return;
-  const int64_t row = w / nl;
-  const int L = (int)(w - row * nl);
+  const int64_t p = xcd_position(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (p >= n * nl) return;
+  const int64_t prow = p / nl;
+  const int L = (int)(p - prow * nl);
+  const int64_t row = order ? (int64_t)order[prow] : prow;
+  const int64_t w = row * nl + L;
   const int kk = L == 0 ? k0 : k1;
   const int32_t* lst = (L == 0 ? idx0 : idx1) + row * kk;
   const float* xr = X + row * (int64_t)d;
@@ -629,11 +634,11 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
 
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
                             int k1, const float* n2, const float* maxn2, float eps_s, float eps_n, float* out,
-                            hipStream_t st) {
+                            const int32_t* order, hipStream_t st) {
   const int nl = idx1 ? 2 : 1;
   const int64_t waves = n * nl;
   hipLaunchKernelGGL(seed_thresholds_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, X, d, n, idx0, k0,
-                     idx1, k1, n2, maxn2, eps_s, eps_n, out);
+                     idx1, k1, n2, maxn2, eps_s, eps_n, out, order);
 }
 
 void launch_refine(const RefineArgs& a, hipStream_t st) {
