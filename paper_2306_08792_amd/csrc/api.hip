@@ -130,20 +130,16 @@ __global__ void add_count_kernel(unsigned long long* dst, const int* src) { *dst
 
 int esize_of(int prec) { return prec == GCR_PREC_FP32 ? 4 : (prec == GCR_PREC_BF16 ? 2 : 1); }
 
-// Bound on |s~ - s| / (||x_r|| ||x_c||) for the screening precision.
-float eps_similarity(int prec, int d) {
+// Relative error of the float32 accumulation of the screening products:
+// |fl(sum) - sum| <= eps * ||x~_r|| ||x~_c||.  BF16 and FP8 products are
+// exact in float32 (m = d rounded additions); float32 products round too
+// (m = d + 1); FP8 similarities are multiplied by the two row scales after
+// the accumulation (two more roundings).
+float eps_accumulation(int prec, int d) {
   const double u23 = ldexp(1.0, -23);
-  double uq = 0.0, m = d;
-  if (prec == GCR_PREC_FP32) m = d + 1;            // rounded products
-  if (prec == GCR_PREC_BF16) uq = ldexp(1.0, -8);
-  if (prec == GCR_PREC_FP8) uq = ldexp(1.0, -4);
-  const double g = m * u23 / (1.0 - m * u23);
-  double e = (2.0 * uq + uq * uq) + g * (1.0 + uq) * (1.0 + uq);
-  if (prec == GCR_PREC_FP8) {
-    // subnormal grid of E4M3 (absolute 2^-10 in scaled units, scale <= ||x|| / 448)
-    e += 2.0 * (1.0 + uq) * sqrt((double)d) * ldexp(1.0, -10) / 448.0 + d * ldexp(1.0, -20) / (448.0 * 448.0);
-    e += 4.0 * u23 * (1.0 + 2.0 * uq);               // scale products in the epilogue
-  }
+  const double m = prec == GCR_PREC_FP32 ? d + 1.0 : (double)d;
+  double e = m * u23 / (1.0 - m * u23);
+  if (prec == GCR_PREC_FP8) e += 4.0 * u23;
   return (float)(e * 1.01);
 }
 float eps_norm(int d) {
@@ -167,11 +163,12 @@ int capacity_for(int prec, int kmax, int nl) {
 struct KnnPlan {
   int prec, nl, C, S, RB, kch, fb_grid;
   int64_t n, npad, ld, W, rows, ncols;
-  uint8_t* Xs; float* n2; float* scale; unsigned* maxn2;
+  uint8_t* Xs; float* n2; float* scale; float* rn; unsigned* maxn2;
   uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
   uint64_t* fb_pk; uint32_t* fb_pc;
   float* seed;
   float* fb_cut; uint64_t* band; int* band_cnt; int band_cap, band_max; int* ovf_list;
+  int32_t *ord, *ord_label, *ord_cnt, *ord_blk;  // refine row order (square sweeps)
 };
 
 void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
@@ -199,6 +196,7 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.Xs = ar.take<uint8_t>((size_t)(kp.npad * kp.ld));
   kp.n2 = ar.take<float>(kp.npad);
   kp.scale = ar.take<float>(kp.npad);
+  kp.rn = ar.take<float>(kp.npad);
   kp.maxn2 = ar.take<unsigned>(64);
   kp.cand = ar.take<uint64_t>((size_t)kp.rows * kp.nl * S * kp.C);
   kp.cnt = ar.take<int>((size_t)kp.rows * kp.nl * S);
@@ -211,6 +209,11 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.band_cap = 2048;
   kp.band = ar.take<uint64_t>((size_t)kp.band_max * kp.band_cap + 1);
   kp.band_cnt = ar.take<int>((size_t)kp.band_max + 1);
+  const bool square = r0 == 0 && c0 == 0 && r1 == c1;
+  kp.ord = square ? ar.take<int32_t>((size_t)r1) : nullptr;
+  kp.ord_label = square ? ar.take<int32_t>((size_t)r1) : nullptr;
+  kp.ord_cnt = square ? ar.take<int32_t>((size_t)r1 + 1) : nullptr;
+  kp.ord_blk = square ? ar.take<int32_t>((size_t)(r1 / 1024 + 2)) : nullptr;
   kp.fb_count = ar.take<int>(64);
   kp.fb_scr = ar.take<uint64_t>((size_t)kp.fb_grid * std::max<int64_t>(kp.ncols, 1));
   {
@@ -231,25 +234,25 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
              int32_t* idx1, float* dist1, hipStream_t st, const int32_t* prev0 = nullptr,
              const int32_t* prev1 = nullptr, const int32_t* order = nullptr) {
   if (r0 != 0) order = nullptr;
-  fill_u32(kp.maxn2, 0u, 1, st);
+  fill_u32(kp.maxn2, 0u, 2, st);
   fill_u32(kp.fb_count, 0u, 2, st);
   fill_u32(kp.band_cnt, 0u, kp.band_max, st);
   {
     TimedScope ts(c, 5, st);
-    launch_screen_prep(kp.prec, X, kp.n, d, kp.npad, kp.Xs, kp.ld, kp.n2, kp.scale, kp.maxn2, st);
+    launch_screen_prep(kp.prec, X, kp.n, d, kp.npad, kp.Xs, kp.ld, kp.n2, kp.scale, kp.rn, kp.maxn2, st);
   }
   SimArgs sa;
   sa.Xs = kp.Xs; sa.npad = kp.npad; sa.ld_bytes = kp.ld; sa.kchunks = kp.kch; sa.n2 = kp.n2;
   sa.scale = kp.prec == GCR_PREC_FP8 ? kp.scale : nullptr;
-  sa.cam = cam; sa.maxn2 = (const float*)kp.maxn2;
+  sa.cam = cam; sa.maxn2 = (const float*)kp.maxn2; sa.rn = kp.rn;
   sa.r0 = r0; sa.r1 = r1; sa.c0 = c0; sa.c1 = c1; sa.W = kp.W; sa.S = kp.S; sa.RB = kp.RB;
   sa.exclude_self = exclude_self; sa.k0 = k0; sa.k1 = k1; sa.C = kp.C;
-  sa.eps_s = eps_similarity(kp.prec, d); sa.eps_n = eps_norm(d);
+  sa.eps_s = eps_accumulation(kp.prec, d); sa.eps_n = eps_norm(d);
   sa.cand = kp.cand; sa.cnt = kp.cnt; sa.thr = kp.thr;
   sa.thr_init = nullptr;
   if (prev0 && r0 == 0 && c0 == 0 && r1 == c1 && (k1 == 0 || prev1)) {
     TimedScope ts(c, 1, st);
-    launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, (const float*)kp.maxn2,
+    launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, kp.rn, (const float*)kp.maxn2,
                            sa.eps_s, sa.eps_n, kp.seed, order, st);
     sa.thr_init = kp.seed;
   }
@@ -260,16 +263,21 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   RefineArgs ra;
   ra.cand = kp.cand; ra.cnt = kp.cnt; ra.thr = kp.thr; ra.S = kp.S; ra.C = kp.C; ra.NL = kp.nl; ra.k0 = k0; ra.k1 = k1;
   ra.r0 = r0; ra.r1 = r1; ra.c0 = c0; ra.c1 = c1; ra.exclude_self = exclude_self;
-  ra.X = X; ra.d = d; ra.cam = cam; ra.n2 = kp.n2; ra.maxn2 = (const float*)kp.maxn2;
+  ra.X = X; ra.d = d; ra.cam = cam; ra.n2 = kp.n2; ra.rn = kp.rn; ra.maxn2 = (const float*)kp.maxn2;
   ra.eps_s = sa.eps_s; ra.eps_n = sa.eps_n;
   ra.idx0 = idx0; ra.dist0 = dist0; ra.idx1 = idx1; ra.dist1 = dist1;
   ra.fb_list = kp.fb_list; ra.fb_count = kp.fb_count; ra.stat_cands = c->stats;
   ra.fb_scratch = kp.fb_scr; ra.fb_grid = kp.fb_grid;
   ra.fb_part_key = kp.fb_pk; ra.fb_part_col = kp.fb_pc;
-  ra.fb_cut = kp.fb_cut; ra.eps32 = eps_similarity(GCR_PREC_FP32, d);
+  ra.fb_cut = kp.fb_cut; ra.eps32 = eps_accumulation(GCR_PREC_FP32, d);
   ra.band = kp.band; ra.band_cnt = kp.band_cnt; ra.band_cap = kp.band_cap; ra.band_max = kp.band_max;
   ra.ovf_list = kp.ovf_list; ra.ovf_count = kp.fb_count + 1;
-  ra.order = order;
+  ra.order = nullptr;
+  if (kp.ord && r0 == 0 && c0 == 0 && r1 == c1 && k0 > 0) {
+    TimedScope ts(c, 1, st);
+    launch_cand_order(r1, kp.cand, kp.cnt, kp.S, kp.C, kp.nl, kp.ord_label, kp.ord_cnt, kp.ord_blk, kp.ord, st);
+    ra.order = kp.ord;
+  }
   {
     TimedScope ts(c, 1, st);
     launch_refine(ra, st);
@@ -621,10 +629,10 @@ static void run_final(gcr_ctx* c, const FinalPlan& fp, const float* X, int64_t n
   const int64_t n = nq + ng;
   if (dist_out) {
     const KnnPlan& kd = fp.kd;
-    fill_u32(kd.maxn2, 0u, 1, st);
+    fill_u32(kd.maxn2, 0u, 2, st);
     {
       TimedScope ts(c, 5, st);
-      launch_screen_prep(GCR_PREC_FP32, X, n, d, kd.npad, kd.Xs, kd.ld, kd.n2, kd.scale, kd.maxn2, st);
+      launch_screen_prep(GCR_PREC_FP32, X, n, d, kd.npad, kd.Xs, kd.ld, kd.n2, kd.scale, kd.rn, kd.maxn2, st);
     }
     TimedScope ts(c, 4, st);
     launch_dense_dist(kd.Xs, kd.ld, kd.kch, kd.n2, 0, nq, nq, ng, dist_out, st);

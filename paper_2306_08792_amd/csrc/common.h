@@ -131,10 +131,6 @@ __device__ __forceinline__ void wave_bitonic_sort(uint64_t (&v)[E]) {
   }
 }
 
-// Margin of the screening: the screened key n2_c - 2 s~ of row r differs
-// from the exact n2_c - 2 s by at most the returned bound.
-//   eps_s : bound on |s~ - s| / (||x_r|| ||x_c||) for the precision mode
-//   eps_n : bound on the relative error of the float32 squared norms
 // Position of workgroup b among nb workgroups such that each XCD (the
 // dispatcher deals workgroups to the 8 XCDs in turn) walks one contiguous
 // segment of positions: neighbouring positions then share an L2.
@@ -143,10 +139,19 @@ __device__ __forceinline__ int64_t xcd_position(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ float screen_margin(float n2r, float maxn2, float eps_s, float eps_n) {
-  float nr = sqrtf(n2r), nm = sqrtf(maxn2);
-  float es = eps_s * nr * nm;
-  // final float32 rounding of the key (|key| <= maxn2 + 2 nr nm)
-  float er = 6.0e-8f * (maxn2 + 2.0f * nr * nm);
-  return (2.0f * es + eps_n * maxn2 + er) * 1.0001f;
+// Bound on |screened key - exact key| for a row, where key_c = ||x_c||^2 -
+// 2 x_r.x_c.  The screening multiplies x~ = x - res (res: the quantisation
+// residual, known per row): x~_r.x~_c - x_r.x_c = -res_r.x~_c - x_r.res_c,
+// bounded by Cauchy-Schwarz with the row's residual norm rn_r, the largest
+// residual norm maxrn and the largest norm; the float32 accumulation adds at
+// most eps_acc ||x~_r|| ||x~_c||, the float32 squared norm n2_c at most
+// eps_n maxn2, and the key's own rounding a few units of 2^-24.  With
+// rn_r = maxrn = 0 this is the bound of a plain float32 product.
+__device__ __forceinline__ float screen_margin(float n2r, float rnr, float maxn2, float maxrn, float eps_acc,
+                                               float eps_n) {
+  const float nr = sqrtf(n2r * (1.0f + eps_n)), nm = sqrtf(maxn2 * (1.0f + eps_n));
+  const float tr = nr + rnr, tm = nm + maxrn;  // bounds on ||x~_r||, ||x~_c||
+  const float es = rnr * tm + nr * maxrn + eps_acc * tr * tm;
+  const float er = 6.0e-8f * (maxn2 + 2.0f * tr * tm);
+  return (2.0f * es + eps_n * maxn2 + er) * 1.00001f;
 }

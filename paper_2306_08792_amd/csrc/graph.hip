@@ -182,12 +182,50 @@ __global__ void order_scatter_kernel(int64_t n, const int32_t* __restrict__ labe
   order[atomicAdd(&off[label[i]], 1)] = (int32_t)i;
 }
 
+// Label of a row from its screening candidates (list 0, every split).
+__global__ void cand_label_count_kernel(int64_t n, const uint64_t* __restrict__ cand, const int32_t* __restrict__ ccnt,
+                                        int S, int C, int NL, int32_t* __restrict__ label,
+                                        int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t m = (uint32_t)i;
+  for (int s = 0; s < S; ++s) {
+    const int64_t o = (i * NL) * (int64_t)S + s;
+    const uint64_t* b = cand + o * C;
+    const int c = ccnt[o];
+    for (int t = 0; t < c; ++t) {
+      const uint32_t j = cand_col(b[t]);
+      m = j < m ? j : m;
+    }
+  }
+  label[i] = (int32_t)m;
+  atomicAdd(&cnt[m], 1);
+}
+
+static void order_from_labels(int64_t n, const int32_t* label, int32_t* cnt, int32_t* blk, int32_t* order,
+                              hipStream_t st);
+
+void launch_cand_order(int64_t n, const uint64_t* cand, const int32_t* ccnt, int S, int C, int NL, int32_t* label,
+                       int32_t* cnt, int32_t* blk, int32_t* order, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, cnt, n);
+  hipLaunchKernelGGL(cand_label_count_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, cand, ccnt, S, C, NL, label,
+                     cnt);
+  order_from_labels(n, label, cnt, blk, order, st);
+}
+
 void launch_locality_order(int64_t n, const int32_t* idx, int k, int32_t* label, int32_t* cnt, int32_t* blk,
                            int32_t* order, hipStream_t st) {
   if (n <= 0) return;
-  const int ntiles = (int)((n + 1023) / 1024);
   hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, cnt, n);
   hipLaunchKernelGGL(label_count_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, idx, k, label, cnt);
+  order_from_labels(n, label, cnt, blk, order, st);
+}
+
+// counts in cnt[label] -> exclusive offsets (in place) -> scatter
+static void order_from_labels(int64_t n, const int32_t* label, int32_t* cnt, int32_t* blk, int32_t* order,
+                              hipStream_t st) {
+  const int ntiles = (int)((n + 1023) / 1024);
   // exclusive offsets, scanned in place
   hipLaunchKernelGGL(scan_tiles_kernel, dim3(ntiles), dim3(1024), 0, st, cnt, cnt, n, blk);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, blk, ntiles, cnt + n);

@@ -13,8 +13,9 @@ namespace gcr {
 
 // ---- prep.hip
 void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st);
+// maxn2_bits[0], [1]: maxima of n2 and rn (zero before the launch)
 void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,
-                        int64_t ld_bytes, float* n2, float* scale, unsigned* maxn2_bits,
+                        int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
                         hipStream_t st);
 
 // ---- simtopk.hip : fused MFMA similarity tiles + streaming per-row top-k
@@ -26,7 +27,8 @@ struct SimArgs {
   const float* n2;    // [npad]
   const float* scale; // [npad] FP8 row scales or nullptr
   const int* cam;     // [n] or nullptr
-  const float* maxn2; // device scalar
+  const float* rn;    // [npad] quantisation residual norms
+  const float* maxn2; // device [max n2, max rn]
   int64_t r0, r1;     // rows [r0, r1)
   int64_t c0, c1;     // columns [c0, c1)
   int64_t W;          // split width (multiple of the 256-column tile)
@@ -35,7 +37,7 @@ struct SimArgs {
   int exclude_self;   // skip column == row
   int k0, k1;         // list sizes (global, cross)
   int C;              // candidate capacity per (row, list, split)
-  float eps_s, eps_n; // screening error coefficients
+  float eps_s, eps_n; // accumulation / squared-norm error coefficients
   uint64_t* cand;     // [(r1-r0), NL, S, C]
   const float* thr_init;  // [(r1-r0), NL] initial admission thresholds or nullptr
   int* cnt;           // [(r1-r0), NL, S] entries kept
@@ -46,8 +48,8 @@ int sim_topk_grid(int RB, int S);
 // Initial admission thresholds from earlier neighbour lists (any k items give
 // an upper bound on the k-th distance): out[row * nl + L].
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
-                            int k1, const float* n2, const float* maxn2, float eps_s, float eps_n, float* out,
-                            const int32_t* order, hipStream_t st);
+                            int k1, const float* n2, const float* rn, const float* maxn2, float eps_s,
+                            float eps_n, float* out, const int32_t* order, hipStream_t st);
 int sim_topk_tile_cols();
 void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
 
@@ -64,6 +66,7 @@ struct RefineArgs {
   int d;
   const int* cam;
   const float* n2;
+  const float* rn;
   const float* maxn2;
   float eps_s, eps_n;
   int32_t* idx0; float* dist0;   // [(r1-r0), k0]
@@ -110,6 +113,10 @@ void launch_finish_values(const GraphBuildArgs& a, hipStream_t st);
 // list members.  label: [n], cnt: [n + 1], blk: scan tile sums.
 void launch_locality_order(int64_t n, const int32_t* idx, int k, int32_t* label, int32_t* cnt, int32_t* blk,
                            int32_t* order, hipStream_t st);
+// The same order with labels taken from the screening candidate buffers of
+// rows [0, n) (list 0, all splits): usable before the lists exist.
+void launch_cand_order(int64_t n, const uint64_t* cand, const int32_t* ccnt, int S, int C, int NL, int32_t* label,
+                       int32_t* cnt, int32_t* blk, int32_t* order, hipStream_t st);
 
 // ---- propagate.hip
 struct PropArgs {

@@ -25,6 +25,15 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// value of an E4M3 code written by f32_to_e4m3_rne
+__device__ __forceinline__ float e4m3_to_f32(uint8_t c) {
+  const int E = (c >> 3) & 15, m = c & 7;
+  const float a = E == 0 ? (float)m * (1.0f / 512.0f) : ldexpf((float)(8 + m), E - 10);
+  return (c & 0x80) ? -a : a;
+}
+
 // OCP E4M3 (bias 7, max 448, no infinities), round to nearest even,
 // saturating at +-448.
 __device__ __forceinline__ uint8_t f32_to_e4m3_rne(float x) {
@@ -43,20 +52,22 @@ __device__ __forceinline__ uint8_t f32_to_e4m3_rne(float x) {
 
 // One wave per padded row.  Writes the screening operand (row stride
 // ld_bytes, zero padding past d and past n), n2[i] = ||x_i||^2 (float32),
-// the FP8 per-row scale, and the maximum n2 (atomic max on the bit pattern,
-// valid for non-negative floats).
+// the FP8 per-row scale, an upper bound rn[i] on the norm of the
+// quantisation residual x_i - x~_i, and the maxima of n2 and rn into
+// maxn2_bits[0] and [1] (atomic max on the bit patterns, valid for
+// non-negative floats).
 template <int PREC>
 __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restrict__ X, int64_t n,
                                                           int d, int64_t npad, uint8_t* Xs,
                                                           int64_t ld_bytes, float* n2,
-                                                          float* scale, unsigned* maxn2_bits) {
+                                                          float* scale, float* rn, unsigned* maxn2_bits) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= npad) return;
   uint8_t* out = Xs + row * ld_bytes;
   if (row >= n) {
     for (int64_t b = lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
-    if (lane == 0) { n2[row] = 0.f; if (scale) scale[row] = 0.f; }
+    if (lane == 0) { n2[row] = 0.f; rn[row] = 0.f; if (scale) scale[row] = 0.f; }
     return;
   }
   const float* x = X + row * d;
@@ -73,6 +84,7 @@ __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restric
     n2[row] = s;
     atomicMax(maxn2_bits, __float_as_uint(s));
   }
+  float r2 = 0.f;  // squared residual norm
   if (PREC == GCR_PREC_FP32) {
     float* o = (float*)out;
     const int64_t cnt = ld_bytes / 4;
@@ -80,11 +92,39 @@ __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restric
   } else if (PREC == GCR_PREC_BF16) {
     uint16_t* o = (uint16_t*)out;
     const int64_t cnt = ld_bytes / 2;
-    for (int64_t e = lane; e < cnt; e += 64) o[e] = e < d ? f32_to_bf16_rne(x[e]) : (uint16_t)0;
+    for (int64_t e = lane; e < cnt; e += 64) {
+      uint16_t h = 0;
+      if (e < d) {
+        h = f32_to_bf16_rne(x[e]);
+        const float r = x[e] - bf16_to_f32(h);  // exact
+        r2 = fmaf(r, r, r2);
+      }
+      o[e] = h;
+    }
   } else {
     const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
     if (lane == 0) scale[row] = sc;
-    for (int64_t e = lane; e < ld_bytes; e += 64) out[e] = e < d ? f32_to_e4m3_rne(x[e] / sc) : (uint8_t)0;
+    for (int64_t e = lane; e < ld_bytes; e += 64) {
+      uint8_t c = 0;
+      if (e < d) {
+        c = f32_to_e4m3_rne(x[e] / sc);
+        const float r = x[e] - e4m3_to_f32(c) * sc;
+        r2 = fmaf(r, r, r2);
+      }
+      out[e] = c;
+    }
+  }
+  if (PREC != GCR_PREC_FP32) {
+    r2 = wave_sum(r2);
+    // float32 sum of d squares: relative error below (d + 2) 2^-23; each
+    // residual itself is off by at most 2^-24 |x_e| (FP8 dequantisation)
+    const float rb = sqrtf(r2 * (1.0f + (float)(d + 2) * 1.2e-7f)) * 1.000001f + 1.0e-7f * sqrtf(s);
+    if (lane == 0) {
+      rn[row] = rb;
+      atomicMax(maxn2_bits + 1, __float_as_uint(rb));
+    }
+  } else if (lane == 0) {
+    rn[row] = 0.f;
   }
 }
 
@@ -94,16 +134,16 @@ void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream
 }
 
 void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,
-                        int64_t ld_bytes, float* n2, float* scale, unsigned* maxn2_bits,
+                        int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
                         hipStream_t st) {
   dim3 g((unsigned)((npad + 3) / 4)), b(256);
   uint8_t* xs = (uint8_t*)Xs;
   if (prec == GCR_PREC_FP32)
-    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP32>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, maxn2_bits);
+    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP32>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, rn, maxn2_bits);
   else if (prec == GCR_PREC_BF16)
-    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_BF16>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, maxn2_bits);
+    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_BF16>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, rn, maxn2_bits);
   else
-    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP8>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, maxn2_bits);
+    hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP8>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, rn, maxn2_bits);
 }
 
 }  // namespace gcr

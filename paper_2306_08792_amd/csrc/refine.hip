@@ -116,7 +116,7 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   block_sort_pairs(U, ec, P);
 
   // cut at tau + 2E
-  const float twoE = 2.0f * screen_margin(a.n2[row], *a.maxn2, a.eps_s, a.eps_n);
+  const float twoE = 2.0f * screen_margin(a.n2[row], a.rn[row], a.maxn2[0], a.maxn2[1], a.eps_s, a.eps_n);
   const float tau = (T >= kk && kk > 0) ? cand_key(U[kk - 1]) : INFINITY;
   const float th = tau + twoE;
   // every split holds all of its items with key <= its threshold; if the
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void band_sweep_kernel(RefineArgs a) {
         s_list[tid] = code & 1;
         s_cam[tid] = a.cam ? a.cam[row] : 0;
         const float n2r = a.n2[row];
-        s_cut[tid] = a.fb_cut[f] + screen_margin(n2r, mx, a.eps32, a.eps_n);
+        s_cut[tid] = a.fb_cut[f] + screen_margin(n2r, 0.f, mx, 0.f, a.eps32, a.eps_n);
       } else {
         s_row[tid] = -1;
         s_list[tid] = 0;
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
     if (tid == 0) s_M = 0;
     __syncthreads();
     block_sort_pairs(U, ux, P);
-    const float e32 = screen_margin(a.n2[row], *a.maxn2, a.eps32, a.eps_n);
+    const float e32 = screen_margin(a.n2[row], 0.f, a.maxn2[0], 0.f, a.eps32, a.eps_n);
     const float th = (T >= kk && kk > 0) ? cand_key(U[kk - 1]) + 2.0f * e32 : INFINITY;
     int mine = 0;
     for (int t = tid; t < T; t += RT) mine += cand_key(U[t]) <= th ? 1 : 0;
@@ -599,6 +599,7 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
                                                               const int32_t* __restrict__ idx0, int k0,
                                                               const int32_t* __restrict__ idx1, int k1,
                                                               const float* __restrict__ n2,
+                                                              const float* __restrict__ rn,
                                                               const float* __restrict__ maxn2, float eps_s,
                                                               float eps_n, float* __restrict__ out,
                                                               const int32_t* __restrict__ order) {
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
   float res = INFINITY;
   if (kk > 0 && valid == kk) {
     const float mx = *maxn2, n2r = n2[row];
-    const float E = screen_margin(n2r, mx, eps_s, eps_n);
+    const float E = screen_margin(n2r, rn[row], mx, maxn2[1], eps_s, eps_n);
     const float u = umax - n2r + eps_n * mx;
     res = u + 3.0f * E + 4e-7f * (fabsf(umax) + n2r + 1.0f);
   }
@@ -633,12 +634,12 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
 }
 
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
-                            int k1, const float* n2, const float* maxn2, float eps_s, float eps_n, float* out,
-                            const int32_t* order, hipStream_t st) {
+                            int k1, const float* n2, const float* rn, const float* maxn2, float eps_s,
+                            float eps_n, float* out, const int32_t* order, hipStream_t st) {
   const int nl = idx1 ? 2 : 1;
   const int64_t waves = n * nl;
   hipLaunchKernelGGL(seed_thresholds_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, X, d, n, idx0, k0,
-                     idx1, k1, n2, maxn2, eps_s, eps_n, out, order);
+                     idx1, k1, n2, rn, maxn2, eps_s, eps_n, out, order);
 }
 
 void launch_refine(const RefineArgs& a, hipStream_t st) {

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     const int64_t r = row0 + t;
     const bool rv = r < a.r1;
     const float n2r = rv ? a.n2[r] : 0.f;
-    row_twoE[t] = 2.0f * screen_margin(n2r, maxn2, a.eps_s, a.eps_n);
+    row_twoE[t] = 2.0f * screen_margin(n2r, rv ? a.rn[r] : 0.f, maxn2, a.maxn2[1], a.eps_s, a.eps_n);
     row_cam[t] = (a.cam && rv) ? a.cam[r] : 0;
     row_sc[t] = (PREC == GCR_PREC_FP8 && rv) ? a.scale[r] : 1.0f;
 #pragma unroll
