@@ -17,6 +17,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,7 +41,55 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-agreement", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=192)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy a device buffer of BYTES five times (reference kernel for the HBM "
+                         "byte counters) and exit")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sim_topk_cross_camera_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_08792_amd", "csrc", f) for f in ("simtopk.hip", "common.h", "kernels.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per similarity/top-k launch from the committed counter
+    summary, or None when the summary is missing or was taken on other
+    kernel sources."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(nbytes: int):
+    import torch
+    n = max(1, nbytes // 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 4, "copies": 5}), flush=True)
 
 
 def cpu_baseline(w, p, sample_rows: int):
@@ -92,6 +141,9 @@ def cpu_baseline(w, p, sample_rows: int):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
                                    "(--gpus must be 1)"}))
@@ -182,7 +234,7 @@ def main():
                    "screening": args.precision + "+exact refine", "parallelism": "single GPU"},
         "top_k_agreement": agreement,
         "roofline": {"bound": "mfma", "kernel": "sim_topk", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic(),
                      "avg_launch_ms": round(sim_avg, 4), "launches": int(sim_n),
                      "flops_per_launch": flops},
         "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
