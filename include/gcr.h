@@ -54,7 +54,8 @@ typedef enum {
   GCR_ERR_INVALID = -1,     /* bad argument (shape, NULL, range)            */
   GCR_ERR_NOMEM = -2,       /* device allocation failed                     */
   GCR_ERR_HIP = -3,         /* a HIP runtime call failed                    */
-  GCR_ERR_UNSUPPORTED = -4  /* valid but not supported by this build        */
+  GCR_ERR_UNSUPPORTED = -4, /* valid but not supported by this build        */
+  GCR_ERR_TIMEOUT = -5      /* gcr_server_wait: the request is not done yet */
 } gcr_status;
 
 /* Precision of the similarity screening.  Every mode re-scores the screened
@@ -229,6 +230,86 @@ gcr_status gcr_profile_vectors(gcr_ctx* ctx, const float* frames,
                                const int32_t* group_host, int32_t nt, int32_t d,
                                int32_t mode, float lambda, float* W_out,
                                void* stream);
+
+/* ---------------------------------------------------------------------
+ * Serving: a resident gallery and a request loop.
+ *
+ * The paper notes that the kNN graph of the database can be computed in
+ * advance, leaving only the queries' part per request (Sec. IV-F).  A server
+ * keeps the gallery's features, its kNN lists and degrees (built on the
+ * gallery alone and then frozen) and its gallery-only propagated features of
+ * every round resident in HBM.  One request with queries Q is computed over
+ * the node set gallery + Q: a query row lists its k nearest gallery items
+ * (Eq. (4)); gallery rows keep their frozen lists; A = (A~ + A~^T)/2 with self
+ * weight 1, D and P = D^-1/2 A D^-1/2 (Eq. (5)-(7)) over that node set;
+ * p->rounds rounds of x <- P x with row renormalisation (Eq. (2), (3)) on
+ * the fixed graph; the result is each query's top-K gallery items
+ * (K = p->topk_out) by squared distance over the propagated features,
+ * ordered by (distance, gallery index).  Requests do not see each other:
+ * a result is the same whether the request ran alone or among others.
+ *
+ * Only gallery rows within `rounds` hops of the gallery items the queries
+ * touch change; the server recomputes exactly those rows (up to
+ * cfg.max_recomputed per round) and reads the rest from the resident copy.
+ *
+ * A worker thread admits submitted requests, in order, into free slots; a
+ * slot is a fixed partition of device memory (sized for cfg.max_batch
+ * queries) with its own HIP stream, so up to cfg.slots requests run on the
+ * device at once.  Cameras (Eq. (8), (9)) are not used in serving.
+ * ------------------------------------------------------------------- */
+typedef struct gcr_server gcr_server;
+
+typedef struct {
+  int32_t slots;          /* requests in flight at once, 1..16 (default 4)    */
+  int32_t max_batch;      /* queries per request (default 512; capped so that
+                             max_batch * k <= 16384)                          */
+  int32_t max_recomputed; /* gallery rows recomputed per round and request
+                             (default 65536)                                  */
+} gcr_server_config;
+void gcr_server_config_default(gcr_server_config* cfg);
+
+typedef struct {
+  int64_t requests_done;       /* requests finished (any status)             */
+  int64_t queries_done;
+  int64_t max_recomputed_rows; /* largest per-round recomputed set seen      */
+  int64_t slots, max_batch, max_recomputed;
+  int64_t device_bytes;        /* device memory held by the server           */
+} gcr_server_stats;
+
+/* Build a server on ctx's device.
+ *   gallery: DEVICE array [ng, d], float32 (gallery_dtype 0) or BF16 bit
+ *   patterns (gallery_dtype 1, widened exactly); rows are used as given
+ *   (queries are normalised when p->normalize_input).  The array is copied;
+ *   the caller may free it afterwards.
+ *   p: k >= 1, rounds, gamma, precision (screening), topk_out (1..120),
+ *   normalize_input; rebuild_each_round must be 0 (the gallery graph is
+ *   fixed); alpha / beta / cross_k are ignored.
+ *   cfg: NULL for the defaults.
+ * Synchronous: builds the gallery graph and the resident propagated copies
+ * with ctx's workspace, then starts the worker thread.
+ * Errors: INVALID, UNSUPPORTED, NOMEM, HIP (message in gcr_last_error(ctx)). */
+gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery,
+                             int32_t gallery_dtype, int64_t ng, int32_t d,
+                             const gcr_params* p, const gcr_server_config* cfg,
+                             gcr_server** out);
+/* Queue one request: q_host is a HOST array [b, d] float32, copied before
+ * the call returns; 1 <= b <= max_batch.  *ticket identifies the request.
+ * Thread-safe.  Errors: INVALID. */
+gcr_status gcr_server_submit(gcr_server* srv, const float* q_host, int32_t b,
+                             uint64_t* ticket);
+/* Wait for a request (timeout_ms < 0: no limit; 0: poll).  On success the
+ * HOST arrays idx_host [b, K] int32 (gallery indices, -1 padding) and
+ * dist_host [b, K] float32 receive the result (either may be NULL) and the
+ * ticket is released.  Returns TIMEOUT (ticket kept) if not done in time;
+ * UNSUPPORTED if the request needed more than max_recomputed rows in a
+ * round; INVALID for an unknown ticket.  Thread-safe. */
+gcr_status gcr_server_wait(gcr_server* srv, uint64_t ticket, int32_t* idx_host,
+                           float* dist_host, int32_t timeout_ms);
+gcr_status gcr_server_get_stats(gcr_server* srv, gcr_server_stats* out);
+/* Message of the last failed server call (never NULL). */
+const char* gcr_server_last_error(const gcr_server* srv);
+/* Finish the requests in flight, fail the queued ones, free everything. */
+gcr_status gcr_server_destroy(gcr_server* srv);
 
 #ifdef __cplusplus
 }

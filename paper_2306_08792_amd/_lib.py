@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgcr.so")
 
 GCR_OK = 0
-STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "UNSUPPORTED"}
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "UNSUPPORTED", -5: "TIMEOUT"}
+GCR_ERR_TIMEOUT = -5
 
 # every exported entry point of include/gcr.h
 EXPORTS = [
@@ -21,6 +22,8 @@ EXPORTS = [
     "gcr_reset_stats", "gcr_normalize_rows", "gcr_knn", "gcr_graph_bytes", "gcr_graph_bind",
     "gcr_build_graph", "gcr_propagate", "gcr_final_distances", "gcr_rerank",
     "gcr_profile_vectors", "gcr_set_timing", "gcr_get_timing",
+    "gcr_server_config_default", "gcr_server_create", "gcr_server_submit", "gcr_server_wait",
+    "gcr_server_get_stats", "gcr_server_last_error", "gcr_server_destroy",
 ]
 NUM_TIMERS = 6
 TIMER_NAMES = ["sim_topk", "refine", "graph", "propagate", "final_dense", "prep"]
@@ -59,6 +62,16 @@ class GcrGraph(C.Structure):
         ("cr_dist", _P), ("cr_w", _P), ("cr_rev_w", _P), ("cr_deg", _P), ("cr_pf", _P), ("cr_pr", _P),
         ("self_", _P),
     ]
+
+
+class GcrServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_batch", C.c_int32), ("max_recomputed", C.c_int32)]
+
+
+class GcrServerStats(C.Structure):
+    _fields_ = [("requests_done", C.c_int64), ("queries_done", C.c_int64),
+                ("max_recomputed_rows", C.c_int64), ("slots", C.c_int64), ("max_batch", C.c_int64),
+                ("max_recomputed", C.c_int64), ("device_bytes", C.c_int64)]
 
 
 _lib = None
@@ -101,6 +114,15 @@ def load(path: str = LIB_PATH):
     L.gcr_set_timing.argtypes = [vp, i32]
     L.gcr_get_timing.argtypes = [vp, C.POINTER(GcrTiming)]
     L.gcr_profile_vectors.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, f32, vp, vp]
+    L.gcr_server_config_default.argtypes = [C.POINTER(GcrServerConfig)]
+    L.gcr_server_config_default.restype = None
+    L.gcr_server_create.argtypes = [vp, vp, i32, i64, i32, pP, C.POINTER(GcrServerConfig), C.POINTER(vp)]
+    L.gcr_server_submit.argtypes = [vp, vp, i32, C.POINTER(C.c_uint64)]
+    L.gcr_server_wait.argtypes = [vp, C.c_uint64, vp, vp, i32]
+    L.gcr_server_get_stats.argtypes = [vp, C.POINTER(GcrServerStats)]
+    L.gcr_server_last_error.argtypes = [vp]
+    L.gcr_server_last_error.restype = C.c_char_p
+    L.gcr_server_destroy.argtypes = [vp]
     for name in EXPORTS:
         fn = getattr(L, name)
         if fn.restype is C.c_int:  # default restype: gcr_status

@@ -10,29 +10,11 @@
 #include <string>
 #include <vector>
 
-#include "gcr.h"
-#include "kernels.h"
+#include "host.h"
 
-struct gcr_timer_rec {
-  hipEvent_t a, b;
-  int cls;
-};
-struct gcr_ctx {
-  int device = 0;
-  int timing = 0;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<gcr_timer_rec> recs;
-  std::string err;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  unsigned long long* stats = nullptr;  // device: [0] candidates, [1] re-swept pairs, [2] exhaustive pairs
-  int64_t knn_rows = 0;
-  int64_t splits = 0;
-};
 
-namespace {
-
-using namespace gcr;
+namespace gcr {
+namespace host {
 
 hipEvent_t pool_event(gcr_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -77,27 +59,7 @@ gcr_status fail(gcr_ctx* c, gcr_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(ctx, call)                                                              \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess) return fail(ctx, GCR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-inline int64_t roundup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
-
-// Two-pass bump planner over the context workspace.
-struct Arena {
-  char* base = nullptr;
-  size_t off = 0;
-  template <class T>
-  T* take(size_t count) {
-    off = align_up(off, 256);
-    T* p = base ? (T*)(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-  }
-};
 
 gcr_status ensure_ws(gcr_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return GCR_OK;
@@ -160,16 +122,6 @@ int capacity_for(int prec, int kmax, int nl) {
   return kmax + 8 <= 512 ? 512 : 1024;
 }
 
-struct KnnPlan {
-  int prec, nl, C, S, RB, kch, fb_grid;
-  int64_t n, npad, ld, W, rows, ncols;
-  uint8_t* Xs; float* n2; float* scale; float* rn; unsigned* maxn2;
-  uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
-  uint64_t* fb_pk; uint32_t* fb_pc;
-  float* seed;
-  float* fb_cut; uint64_t* band; int* band_cnt; int band_cap, band_max; int* ovf_list;
-  int32_t *ord, *ord_label, *ord_cnt, *ord_blk;  // refine row order (square sweeps)
-};
 
 void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
               int64_t c1, int k0, int k1) {
@@ -231,8 +183,8 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
 // order: processing order of the rows (rows [0, n) only) or nullptr.
 void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* cam, int64_t r0, int64_t r1,
              int64_t c0, int64_t c1, int exclude_self, int k0, int k1, int32_t* idx0, float* dist0,
-             int32_t* idx1, float* dist1, hipStream_t st, const int32_t* prev0 = nullptr,
-             const int32_t* prev1 = nullptr, const int32_t* order = nullptr) {
+             int32_t* idx1, float* dist1, hipStream_t st, const int32_t* prev0, const int32_t* prev1,
+             const int32_t* order) {
   if (r0 != 0) order = nullptr;
   fill_u32(kp.maxn2, 0u, 2, st);
   fill_u32(kp.fb_count, 0u, 2, st);
@@ -268,7 +220,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   ra.idx0 = idx0; ra.dist0 = dist0; ra.idx1 = idx1; ra.dist1 = dist1;
   ra.fb_list = kp.fb_list; ra.fb_count = kp.fb_count; ra.stat_cands = c->stats;
   ra.fb_scratch = kp.fb_scr; ra.fb_grid = kp.fb_grid;
-  ra.fb_part_key = kp.fb_pk; ra.fb_part_col = kp.fb_pc;
+  ra.fb_part_key = kp.fb_pk; ra.fb_part_col = kp.fb_pc; ra.fb_max = FB_MAX;
   ra.fb_cut = kp.fb_cut; ra.eps32 = eps_accumulation(GCR_PREC_FP32, d);
   ra.band = kp.band; ra.band_cnt = kp.band_cnt; ra.band_cap = kp.band_cap; ra.band_max = kp.band_max;
   ra.ovf_list = kp.ovf_list; ra.ovf_count = kp.fb_count + 1;
@@ -342,10 +294,6 @@ size_t layout_graph(Arena& ar, gcr_graph* g, int64_t n, int k, int ck, int has_c
   return ar.off;
 }
 
-struct GraphTmp {
-  int32_t* cnt; float* fsum; int32_t* blk;
-  int32_t* label; int32_t* order;  // locality order of the last graph built
-};
 void plan_graph_tmp(Arena& ar, GraphTmp& t, int64_t n) {
   t.cnt = ar.take<int32_t>((size_t)n + 1);
   t.fsum = ar.take<float>((size_t)n + 1);
@@ -383,7 +331,7 @@ void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const 
 // previous round; they bound this round's k-th distances from above.
 void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, const float* X, int64_t n, int d,
                          const int* cam, const gcr_params* p, const gcr_graph* g, hipStream_t st,
-                         bool seed_from_previous = false) {
+                         bool seed_from_previous) {
   const bool cross = g->has_cross != 0;
   if (g->k > 0 || (cross && g->cross_k > 0))
     run_knn(c, kp, X, d, cam, 0, n, 0, n, 1, g->k, cross ? g->cross_k : 0, g->idx, g->dist,
@@ -417,7 +365,11 @@ void enqueue_propagate(gcr_ctx* c, const gcr_graph* g, const float* Xin, float* 
   launch_propagate(a, st);
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace gcr
+
+using namespace gcr;
+using namespace gcr::host;
 
 extern "C" {
 

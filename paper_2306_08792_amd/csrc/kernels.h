@@ -13,10 +13,27 @@ namespace gcr {
 
 // ---- prep.hip
 void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st);
+// Rows [r0, r0 + nmax) of X (only the first *count when count != nullptr)
+// into the operand rows of the same index; maxima into maxn2_bits.
+void launch_screen_prep_rows(int prec, const float* X, int64_t r0, int64_t nmax, const int* count, int d, void* Xs,
+                             int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
+                             hipStream_t st);
 // maxn2_bits[0], [1]: maxima of n2 and rn (zero before the launch)
 void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,
                         int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
                         hipStream_t st);
+
+// Columns of [c0, c1) excluded from a search: column c is out when
+// stamp_of[c] == stamp (a per-request mark array), or when c - c0 is at or
+// past *count (a column count known only on the device).
+struct ColumnFilter {
+  const uint32_t* stamp_of = nullptr;
+  uint32_t stamp = 0;
+  const int* count = nullptr;
+};
+__device__ __forceinline__ bool column_out(const ColumnFilter& f, int64_t c, int64_t c0) {
+  return (f.stamp_of && f.stamp_of[c] == f.stamp) || (f.count && c - c0 >= (int64_t)*f.count);
+}
 
 // ---- simtopk.hip : fused MFMA similarity tiles + streaming per-row top-k
 struct SimArgs {
@@ -43,6 +60,7 @@ struct SimArgs {
   int* cnt;           // [(r1-r0), NL, S] entries kept
   float* thr;         // [(r1-r0), NL, S] final admission threshold: the buffer
                       // holds every item of the split with key <= thr
+  ColumnFilter filt;  // columns left out of the search
 };
 int sim_topk_grid(int RB, int S);
 // Initial admission thresholds from earlier neighbour lists (any k items give
@@ -76,7 +94,8 @@ struct RefineArgs {
   unsigned long long* stat_cands;  // device counter
   uint64_t* fb_scratch;            // [fb_grid, c1 - c0]
   int fb_grid;
-  uint64_t* fb_part_key;           // [min(FB_MAX, pairs), chunks, k] chunk winners
+  int fb_max;                      // pairs taken by the column-chunked path
+  uint64_t* fb_part_key;           // [min(fb_max, pairs), chunks, k] chunk winners
   uint32_t* fb_part_col;
   float* fb_cut;      // [(r1-r0) * NL] upper bound on the exact k-th key of queued pair f
   float eps32;        // screening coefficient of the float32 band sweep
@@ -86,8 +105,9 @@ struct RefineArgs {
   int band_cap, band_max;
   int* ovf_list;      // [(r1-r0) * NL] pairs for the exhaustive path
   int* ovf_count;     // device counter, zero before the launch
+  ColumnFilter filt;  // columns left out of the search
 };
-// queued pairs handled by the column-parallel exhaustive path
+// queued pairs handled by the column-parallel exhaustive path (batch calls)
 constexpr int FB_MAX = 8192;
 void launch_refine(const RefineArgs& a, hipStream_t st);
 
@@ -152,5 +172,35 @@ void launch_scatter_profiles(const float* Wt, const int32_t* members, int nm, in
 void launch_axpby(float* y, const float* x, float a, float b, int64_t n, hipStream_t st);
 void launch_cheb_update(float* Wk, float* Wprev, const float* R, float rho, float cR, int64_t n,
                         hipStream_t st);
+
+// ---- serve.hip : one request against a resident gallery
+void launch_serve_query_edges(int b, int k, const int32_t* q_idx, const float* q_dist, float gamma, float* q_w,
+                              float* Dq, uint64_t* keys, int P, hipStream_t st);
+void launch_serve_sort_pairs(uint64_t* keys, int P, hipStream_t st);  // P: power of two <= 16,384
+void launch_serve_touched(const uint64_t* keys, int npairs, const float* q_w, uint32_t stamp, uint32_t* touched,
+                          float* dD, int32_t* seg_start, int32_t* seg_len, int32_t* T_list, int* T_count,
+                          hipStream_t st);
+void launch_serve_expand(const int32_t* src, const int* src_count, int src_cap, const int32_t* gidx, int k,
+                         const int32_t* rev_ptr, const int32_t* rev_src, uint32_t stamp, uint32_t* mark,
+                         int32_t* pos, int32_t* list, int* count, int cap, hipStream_t st);
+struct ServePropArgs {
+  int d, k, b;
+  const float* Xprev; float* Xcur;    // level t - 1 and t feature arrays
+  int64_t qbase, pbase;               // slot rows: queries, recomputed gallery rows
+  const int32_t* gidx; const float* gw;                    // gallery forward lists [G, k]
+  const int32_t* rev_ptr; const int32_t* rev_src; const float* rev_w;
+  const float* D0;                    // gallery degrees without queries
+  uint32_t stamp;
+  const uint32_t* touched; const float* dD; const int32_t* seg_start; const int32_t* seg_len;
+  const uint64_t* pair_keys;          // sorted (gallery item, query edge) pairs
+  const int32_t* q_idx; const float* q_w; const float* Dq;
+  const uint32_t* prev_mark; const int32_t* prev_pos;      // set of round t - 1 (nullptr at t = 1)
+  const int32_t* cur_list; const int32_t* cur_pos; const int* cur_count; int cap;
+};
+void launch_serve_propagate(const ServePropArgs& a, hipStream_t st);
+void launch_serve_merge(int b, int K, const int32_t* ia, const float* da, const int32_t* ib, const float* db,
+                        const int32_t* list, int32_t* oi, float* od, hipStream_t st);
+void launch_bf16_to_f32(const uint16_t* in, float* out, int64_t n, hipStream_t st);
+void launch_copy_u32(const unsigned* src, unsigned* dst, int n, hipStream_t st);
 
 }  // namespace gcr

@@ -1,5 +1,7 @@
 // Input preparation: row normalisation, squared norms and the padded
 // low-precision copies that the similarity screening reads.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace gcr {
@@ -50,27 +52,14 @@ __device__ __forceinline__ uint8_t f32_to_e4m3_rne(float x) {
   return (uint8_t)(sign | ((uint32_t)(E + 7) << 3) | ((uint32_t)q - 8u));
 }
 
-// One wave per padded row.  Writes the screening operand (row stride
-// ld_bytes, zero padding past d and past n), n2[i] = ||x_i||^2 (float32),
-// the FP8 per-row scale, an upper bound rn[i] on the norm of the
-// quantisation residual x_i - x~_i, and the maxima of n2 and rn into
-// maxn2_bits[0] and [1] (atomic max on the bit patterns, valid for
+// One wave per row: the screening operand row (ld_bytes, zero past d),
+// n2 = ||x||^2 (float32), the FP8 scale, an upper bound rn on the norm of
+// the quantisation residual x - x~, and the maxima of n2 and rn into
+// maxbits[0] and [1] (atomic max on the bit patterns, valid for
 // non-negative floats).
 template <int PREC>
-__global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restrict__ X, int64_t n,
-                                                          int d, int64_t npad, uint8_t* Xs,
-                                                          int64_t ld_bytes, float* n2,
-                                                          float* scale, float* rn, unsigned* maxn2_bits) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= npad) return;
-  uint8_t* out = Xs + row * ld_bytes;
-  if (row >= n) {
-    for (int64_t b = lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
-    if (lane == 0) { n2[row] = 0.f; rn[row] = 0.f; if (scale) scale[row] = 0.f; }
-    return;
-  }
-  const float* x = X + row * d;
+__device__ void prep_row(const float* __restrict__ x, int d, uint8_t* out, int64_t ld_bytes, float* n2o,
+                         float* scaleo, float* rno, unsigned* maxbits, int lane) {
   float s = 0.f, amax = 0.f;
   for (int e = lane; e < d; e += 64) {
     float v = x[e];
@@ -81,8 +70,8 @@ __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restric
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
   if (lane == 0) {
-    n2[row] = s;
-    atomicMax(maxn2_bits, __float_as_uint(s));
+    *n2o = s;
+    atomicMax(maxbits, __float_as_uint(s));
   }
   float r2 = 0.f;  // squared residual norm
   if (PREC == GCR_PREC_FP32) {
@@ -103,7 +92,7 @@ __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restric
     }
   } else {
     const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
-    if (lane == 0) scale[row] = sc;
+    if (lane == 0) *scaleo = sc;
     for (int64_t e = lane; e < ld_bytes; e += 64) {
       uint8_t c = 0;
       if (e < d) {
@@ -120,17 +109,69 @@ __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restric
     // residual itself is off by at most 2^-24 |x_e| (FP8 dequantisation)
     const float rb = sqrtf(r2 * (1.0f + (float)(d + 2) * 1.2e-7f)) * 1.000001f + 1.0e-7f * sqrtf(s);
     if (lane == 0) {
-      rn[row] = rb;
-      atomicMax(maxn2_bits + 1, __float_as_uint(rb));
+      *rno = rb;
+      atomicMax(maxbits + 1, __float_as_uint(rb));
     }
   } else if (lane == 0) {
-    rn[row] = 0.f;
+    *rno = 0.f;
+  }
+}
+
+// Rows [0, npad): rows past n are zero (operand, n2, rn, scale).
+template <int PREC>
+__global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restrict__ X, int64_t n,
+                                                          int d, int64_t npad, uint8_t* Xs,
+                                                          int64_t ld_bytes, float* n2,
+                                                          float* scale, float* rn, unsigned* maxn2_bits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= npad) return;
+  uint8_t* out = Xs + row * ld_bytes;
+  if (row >= n) {
+    for (int64_t b = lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
+    if (lane == 0) { n2[row] = 0.f; rn[row] = 0.f; if (scale) scale[row] = 0.f; }
+    return;
+  }
+  prep_row<PREC>(X + row * d, d, out, ld_bytes, n2 + row, scale ? scale + row : nullptr, rn + row, maxn2_bits,
+                 lane);
+}
+
+// Rows [r0, r0 + nmax), or only the first *count of them when count is
+// given (a row count known on the device); grid-stride over rows.
+template <int PREC>
+__global__ __launch_bounds__(256) void screen_prep_rows_kernel(const float* __restrict__ X, int64_t r0, int64_t nmax,
+                                                               const int* count, int d, uint8_t* Xs,
+                                                               int64_t ld_bytes, float* n2, float* scale, float* rn,
+                                                               unsigned* maxn2_bits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nr = count ? min<int64_t>(nmax, (int64_t)*count) : nmax;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < nr; t += (int64_t)gridDim.x * 4) {
+    const int64_t row = r0 + t;
+    prep_row<PREC>(X + row * d, d, Xs + row * ld_bytes, ld_bytes, n2 + row, scale ? scale + row : nullptr,
+                   rn + row, maxn2_bits, lane);
   }
 }
 
 void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(normalize_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, Y, n, d);
+}
+
+void launch_screen_prep_rows(int prec, const float* X, int64_t r0, int64_t nmax, const int* count, int d, void* Xs,
+                             int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
+                             hipStream_t st) {
+  if (nmax <= 0) return;
+  const dim3 g((unsigned)std::min<int64_t>((nmax + 3) / 4, 4096)), b(256);
+  uint8_t* xs = (uint8_t*)Xs;
+  if (prec == GCR_PREC_FP32)
+    hipLaunchKernelGGL(screen_prep_rows_kernel<GCR_PREC_FP32>, g, b, 0, st, X, r0, nmax, count, d, xs, ld_bytes, n2,
+                       scale, rn, maxn2_bits);
+  else if (prec == GCR_PREC_BF16)
+    hipLaunchKernelGGL(screen_prep_rows_kernel<GCR_PREC_BF16>, g, b, 0, st, X, r0, nmax, count, d, xs, ld_bytes, n2,
+                       scale, rn, maxn2_bits);
+  else
+    hipLaunchKernelGGL(screen_prep_rows_kernel<GCR_PREC_FP8>, g, b, 0, st, X, r0, nmax, count, d, xs, ld_bytes, n2,
+                       scale, rn, maxn2_bits);
 }
 
 void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,

@@ -185,10 +185,10 @@ __device__ __forceinline__ uint64_t wave_exact_sqdist_reg(const float (&xr)[32],
   return ((uint64_t)ord_f32(hi) << 32) | (uint64_t)ord_f32(lo);
 }
 
-// Column-parallel exhaustive path for the first FB_MAX queued pairs: each
+// Column-parallel exhaustive path for the first fb_max queued pairs: each
 // work item scores one 2,048-column chunk of one pair exactly and keeps the
 // chunk's k smallest (distance, column); a merge then takes the k smallest
-// over the chunks.  Pairs past FB_MAX use the one-block-per-pair kernel.
+// over the chunks.  Pairs past fb_max use the one-block-per-pair kernel.
 __device__ __forceinline__ bool lex_less(uint64_t ka, uint32_t ca, uint64_t kb, uint32_t cb) {
   return ka < kb || (ka == kb && ca < cb);
 }
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(RefineArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ncols = a.c1 - a.c0;
   const int nch = (int)((ncols + FB_CW - 1) / FB_CW);
-  const int nfb = min(*a.ovf_count, FB_MAX);
+  const int nfb = min(*a.ovf_count, a.fb_max);
   for (int64_t wi = blockIdx.x; wi < (int64_t)nfb * nch; wi += gridDim.x) {
     const int f = (int)(wi / nch), ch = (int)(wi - (int64_t)f * nch);
     const int code = a.ovf_list[f];
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(RefineArgs a) {
     const int nj = (int)min<int64_t>(FB_CW, ncols - j0);
     for (int j = wave; j < nj; j += 4) {
       const int64_t col = a.c0 + j0 + j;
-      bool ok = !(a.exclude_self && col == row);
+      bool ok = !(a.exclude_self && col == row) && !column_out(a.filt, col, a.c0);
       if (L == 1) ok = ok && a.cam[col] != rcam;
       uint64_t v = GCR_EMPTY;
       if (ok) v = wave_exact_sqdist_reg(xr, a.X + col * (int64_t)a.d, a.d);
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(RefineArgs a) {
   const int tid = threadIdx.x;
   const int64_t ncols = a.c1 - a.c0;
   const int nch = (int)((ncols + FB_CW - 1) / FB_CW);
-  const int nfb = min(*a.ovf_count, FB_MAX);
+  const int nfb = min(*a.ovf_count, a.fb_max);
   for (int f = blockIdx.x; f < nfb; f += gridDim.x) {
     const int code = a.ovf_list[f];
     const int64_t rrel = code >> 1;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
   const int64_t ncols = a.c1 - a.c0;
   uint64_t* scr = a.fb_scratch + (int64_t)blockIdx.x * ncols;
   const int nfb = *a.ovf_count;
-  for (int f = FB_MAX + blockIdx.x; f < nfb; f += gridDim.x) {
+  for (int f = a.fb_max + blockIdx.x; f < nfb; f += gridDim.x) {
     const int code = a.ovf_list[f];
     const int64_t rrel = code >> 1;
     const int L = code & 1;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
     const int rcam = a.cam ? a.cam[row] : 0;
     for (int64_t j = wave; j < ncols; j += NW) {
       const int64_t col = a.c0 + j;
-      bool ok = !(a.exclude_self && col == row);
+      bool ok = !(a.exclude_self && col == row) && !column_out(a.filt, col, a.c0);
       if (L == 1) ok = ok && a.cam[col] != rcam;
       uint64_t v = GCR_EMPTY;
       if (ok) v = wave_exact_sqdist_reg(xr, a.X + col * (int64_t)a.d, a.d);
@@ -507,6 +507,7 @@ __global__ __launch_bounds__(256) void band_sweep_kernel(RefineArgs a) {
         if (jr >= ncols) continue;
         const int64_t col = a.c0 + jr;
         if (a.exclude_self && col == row) continue;
+        if (column_out(a.filt, col, a.c0)) continue;
         if (L == 1 && a.cam[col] == s_cam[pr]) continue;
         const float key = a.n2[col] - 2.0f * acc[i][j];
         if (key <= cut) {

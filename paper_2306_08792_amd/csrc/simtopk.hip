@@ -248,7 +248,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = a.r0 + (int64_t)rb * BM;
   const int64_t sc0 = a.c0 + (int64_t)cs * a.W;
-  const int64_t sc1 = min(a.c1, sc0 + a.W);
+  const int64_t sc1 = min(a.filt.count ? a.c0 + (int64_t)*a.filt.count : a.c1, min(a.c1, sc0 + a.W));
   const int ntiles = sc1 > sc0 ? (int)((sc1 - sc0 + BN - 1) / BN) : 0;
   const float maxn2 = *a.maxn2;
 
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     const int64_t ct0 = sc0 + (int64_t)tile * BN;
     {
       const int64_t c = ct0 + tid;  // NT == BN
-      const bool cv = c < sc1;
+      const bool cv = c < sc1 && !column_out(a.filt, c, a.c0);
       col_n2[tid] = cv ? a.n2[c] : INFINITY;
       col_cam[tid] = (a.cam && cv) ? a.cam[c] : 0;
       col_sc[tid] = (PREC == GCR_PREC_FP8 && cv) ? a.scale[c] : 1.0f;

@@ -289,3 +289,87 @@ class Context:
         out = self.rerank(W, nq, p, cam, dense=dense, topk=topk, keep_features=True)
         out["W"] = W
         return out
+
+
+class Server:
+    """Resident gallery + request loop (gcr_server_*).
+
+    gallery: CUDA tensor [G, d], float32, or bfloat16 / int16 / uint16 BF16
+    bit patterns.  p.rebuild_each_round must be False (the gallery graph is
+    fixed).  submit() takes a host float32 array [b, d] and returns a ticket;
+    wait() returns (indices int32 [b, K], distances float32 [b, K]).
+    """
+
+    def __init__(self, ctx: Context, gallery: torch.Tensor, p: Params, slots: int = 4, max_batch: int = 512,
+                 max_recomputed: int = 65536):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        if gallery.device != ctx.device or not gallery.is_contiguous():
+            raise ValueError("gallery must be a contiguous tensor on the context's device")
+        if gallery.dtype == torch.float32:
+            dtype = 0
+        elif gallery.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+            dtype = 1
+        else:
+            raise TypeError("gallery must be float32 or BF16")
+        ng, d = gallery.shape
+        self.d, self.K = d, p.topk_out
+        cfg = L.GcrServerConfig(slots, max_batch, max_recomputed)
+        h = C.c_void_p()
+        pc = p.c()
+        st = self.lib.gcr_server_create(ctx.h, _ptr(gallery), dtype, ng, d, C.byref(pc), C.byref(cfg), C.byref(h))
+        if st != L.GCR_OK:
+            raise GcrError(f"gcr_server_create failed ({L.STATUS_NAMES.get(st, st)}): "
+                           f"{self.lib.gcr_last_error(ctx.h).decode()}")
+        self.h = h
+        self._b = {}
+
+    def _err(self) -> str:
+        return self.lib.gcr_server_last_error(self.h).decode()
+
+    def submit(self, q) -> int:
+        import numpy as np
+
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        if q.ndim != 2 or q.shape[1] != self.d:
+            raise ValueError(f"queries must be [b, {self.d}]")
+        t = C.c_uint64()
+        st = self.lib.gcr_server_submit(self.h, q.ctypes.data, q.shape[0], C.byref(t))
+        if st != L.GCR_OK:
+            raise GcrError(f"gcr_server_submit failed ({L.STATUS_NAMES.get(st, st)}): {self._err()}")
+        self._b[t.value] = q.shape[0]
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(indices, distances), or None on timeout."""
+        import numpy as np
+
+        b = self._b[ticket]
+        idx = np.empty((b, self.K), dtype=np.int32)
+        dist = np.empty((b, self.K), dtype=np.float32)
+        st = self.lib.gcr_server_wait(self.h, ticket, idx.ctypes.data, dist.ctypes.data, timeout_ms)
+        if st == L.GCR_ERR_TIMEOUT:
+            return None
+        del self._b[ticket]
+        if st != L.GCR_OK:
+            raise GcrError(f"request {ticket} failed ({L.STATUS_NAMES.get(st, st)}): {self._err()}")
+        return idx, dist
+
+    def query(self, q):
+        return self.wait(self.submit(q))
+
+    def stats(self) -> dict:
+        s = L.GcrServerStats()
+        self.lib.gcr_server_get_stats(self.h, C.byref(s))
+        return {f: getattr(s, f) for f, _ in L.GcrServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gcr_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
