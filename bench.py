@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-agreement", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=192)
+    ap.add_argument("--workload", default="cross_camera", choices=["cross_camera", "serving"],
+                    help="cross_camera: whole re-ranking steps (default); serving: resident 500,000 x 512 "
+                         "gallery and a Poisson request trace")
+    ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="serving: offered load of the Poisson phase as a fraction of the saturated throughput")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (reference kernel for the HBM "
                          "byte counters) and exit")
@@ -139,6 +145,119 @@ def cpu_baseline(w, p, sample_rows: int):
     }
 
 
+def serving_bench(args):
+    """Resident 500,000 x 512 BF16 gallery (10,000 centres), k = 20, L = 2,
+    K = 100; requests of 1..512 queries (log-uniform).  Phase 1 queues the
+    whole trace at once (saturated throughput); phase 2 replays it with
+    Poisson arrivals at `load` x that throughput and records each request's
+    latency from arrival to result."""
+    import threading
+
+    import torch
+
+    from paper_2306_08792_amd import datagen
+    from paper_2306_08792_amd.gcr import BF16, FP32, Context, Params, Server
+
+    print("generating the serving gallery", file=sys.stderr, flush=True)
+    bits, vals, centres = datagen.serving_gallery()
+    ng, d = vals.shape
+    trace = datagen.serving_trace(centres, args.requests, 1000.0)
+    nq_total = sum(q.shape[0] for _, q, _ in trace)
+    ctx = Context(0)
+    g = torch.from_numpy(bits.view(np.int16)).cuda()
+    del vals
+    p = Params(k=20, rounds=2, gamma=0.2, topk_out=100, precision=BF16, rebuild_each_round=False)
+    print("building the resident gallery state (BF16 screening)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    srv = Server(ctx, g, p, slots=4, max_batch=512, max_recomputed=65536)
+    t_build = time.perf_counter() - t0
+
+    agreement = None
+    if not args.no_agreement:
+        print("checking top-100 agreement against FP32 screening", file=sys.stderr, flush=True)
+        p32 = Params(**{**p.__dict__, "precision": FP32})
+        s32 = Server(ctx, g, p32, slots=1, max_batch=512, max_recomputed=65536)
+        same = 0
+        tot = 0
+        for _, q, _ in trace[:8]:
+            a = srv.query(q)
+            b = s32.query(q)
+            same += int(np.sum(np.all(a[0] == b[0], axis=1)))
+            tot += q.shape[0]
+        s32.close()
+        agreement = {"final_top100": same / max(1, tot), "queries_checked": tot}
+
+    for _, q, _ in trace[:4]:  # warm-up
+        srv.query(q)
+    print("phase 1: saturated", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(q) for _, q, _ in trace]
+    for t in tickets:
+        srv.wait(t)
+    t_sat = time.perf_counter() - t0
+    qps_sat = nq_total / t_sat
+
+    rate = args.load * qps_sat / (nq_total / len(trace))  # requests per second
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(trace)))
+    lat = [0.0] * len(trace)
+    done_at = [0.0] * len(trace)
+    tick = [None] * len(trace)
+    ready = threading.Semaphore(0)
+    print(f"phase 2: Poisson arrivals at {args.load:.0%} of saturation", file=sys.stderr, flush=True)
+
+    def waiter():
+        for i in range(len(trace)):
+            ready.acquire()
+            srv.wait(tick[i])
+            done_at[i] = time.perf_counter()
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    start = time.perf_counter()
+    for i, (_, q, _) in enumerate(trace):
+        delay = start + arrivals[i] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tick[i] = srv.submit(q)
+        ready.release()
+    th.join()
+    for i in range(len(trace)):
+        lat[i] = (done_at[i] - (start + arrivals[i])) * 1e3
+    span = max(done_at) - start
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    lat = np.array(lat)
+    res = {
+        "metric": METRIC,
+        "value": round(qps_sat, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": len(trace),
+        "warmup": 4,
+        "ms_per_step": round(t_sat * 1e3 / len(trace), 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"serving_gallery_{ng}x{d}_bf16", "gallery": ng, "d": d, "centres": 10000,
+                   "k": 20, "rounds": 2, "top_k": 100, "batch": "log-uniform 1..512",
+                   "requests": len(trace), "queries": nq_total, "slots": 4, "parallelism": "single GPU"},
+        "top_k_agreement": agreement,
+        "poisson_phase": {"offered_load": args.load, "requests_per_s": round(rate, 2),
+                          "queries_per_s": round(nq_total / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                          "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3)},
+        "saturated_phase": {"seconds": round(t_sat, 3), "queries_per_s": round(qps_sat, 2)},
+        "gallery_build_s": round(t_build, 3),
+        "server": st,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -148,6 +267,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
                                    "(--gpus must be 1)"}))
         sys.exit(2)
+    if args.workload == "serving":
+        serving_bench(args)
+        return
     import torch
 
     from paper_2306_08792_amd import datagen
