@@ -24,8 +24,8 @@
 // decreases during the sweep and the true k-th key is <= tau_final + E_i,
 // every true neighbour has a screened key <= tau_final + 2 E_i, so the
 // buffer always keeps the exact top-k (ties included).  A full buffer is
-// compacted by one wave: bitonic sort, new tau_i, drop keys above the
-// threshold.  If the margin band alone fills the buffer (a split's local
+// compacted by one wave: a radix select finds the new tau_i and the keys
+// above the threshold are dropped.  If the margin band alone fills the buffer (a split's local
 // k-th neighbour can sit in a dense region of unrelated items), the buffer
 // keeps its smallest keys and the admission threshold drops below the first
 // key it gave up; the split's final threshold is written out, and the
@@ -73,21 +73,20 @@ __device__ __forceinline__ i32x4 make_res(const void* p, uint64_t range) {
 // Issue this wave's share of one chunk: 1 KB blocks of 8 rows, lane l
 // bringing logical 16-byte part (l & 7) ^ (row & 7) of row blk*8 + l/8 so the
 // data lands swizzled.  Block blk = wave + 4 i has row & 7 == l / 8, so the
-// per-lane offset is the same for every block and the block step goes into
-// the scalar offset.
-__device__ __forceinline__ void issue_chunk(uint8_t* stage, i32x4 rres, i32x4 cres, int ld, int ch, int wave,
-                                            int lane) {
-  const int rsub = lane >> 3, pp = lane & 7;
-  const int voff = (wave * 8 + rsub) * ld + ((pp ^ rsub) << 4) + ch * 128;
-  const int step = 32 * ld;  // 4 blocks of 8 rows
+// per-lane offset voff is the same for every block and chunk; the byte
+// offsets of the row tile, the column tile, the chunk and the block are
+// wave-uniform and go into the scalar offset of one descriptor that spans
+// the whole operand.
+__device__ __forceinline__ void issue_chunk(uint8_t* stage, i32x4 res, int voff, uint32_t roff, uint32_t coff,
+                                            uint32_t step, int wave) {
 #pragma unroll
   for (int i = 0; i < BM / 32; ++i)
-    gcr_buffer_load_lds(rres, (lds_u32_ptr)(stage + (wave + 4 * i) * 1024), 16, voff,
-                        __builtin_amdgcn_readfirstlane(i * step), 0, 0);
+    gcr_buffer_load_lds(res, (lds_u32_ptr)(stage + (wave + 4 * i) * 1024), 16, voff,
+                        __builtin_amdgcn_readfirstlane(roff + i * step), 0, 0);
 #pragma unroll
   for (int i = 0; i < BN / 32; ++i)
-    gcr_buffer_load_lds(cres, (lds_u32_ptr)(stage + RBYTES + (wave + 4 * i) * 1024), 16, voff,
-                        __builtin_amdgcn_readfirstlane(i * step), 0, 0);
+    gcr_buffer_load_lds(res, (lds_u32_ptr)(stage + RBYTES + (wave + 4 * i) * 1024), 16, voff,
+                        __builtin_amdgcn_readfirstlane(coff + i * step), 0, 0);
 }
 
 __device__ __forceinline__ const uint8_t* frag(const uint8_t* base, int r, int lp) {
@@ -234,7 +233,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ float row_twoE[BM], row_sc[BM];
   __shared__ int row_cam[BM];
   __shared__ int any_flag[2];
-  __shared__ uint32_t cb_vote[2];
 
   // XCD-aware placement: workgroup ids go round-robin over the 8 XCDs and
   // the split is id mod S, so every workgroup an XCD runs sweeps the same
@@ -250,9 +248,9 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   const int64_t sc0 = a.c0 + (int64_t)cs * a.W;
   const int64_t sc1 = min(a.filt.count ? a.c0 + (int64_t)*a.filt.count : a.c1, min(a.c1, sc0 + a.W));
   const int ntiles = sc1 > sc0 ? (int)((sc1 - sc0 + BN - 1) / BN) : 0;
-  const float maxn2 = *a.maxn2;
+  const float maxn2 = a.maxn2[0];
 
-  if (tid < 2) { any_flag[tid] = 0; cb_vote[tid] = 0u; }
+  if (tid < 2) any_flag[tid] = 0;
   for (int t = tid; t < BM; t += NT) {
     const int64_t r = row0 + t;
     const bool rv = r < a.r1;
@@ -272,195 +270,181 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
   const int kch = a.kchunks;
   const int total = ntiles * kch;
-  const int ld = (int)a.ld_bytes;
+  const uint32_t ld = (uint32_t)a.ld_bytes;
   const int l32 = lane & 31, half = lane >> 5;
   const int64_t rrel0 = row0 - a.r0;
-  const uint64_t tot_bytes = (uint64_t)a.npad * (uint64_t)ld;
-  const i32x4 rres = make_res(a.Xs + row0 * ld, tot_bytes - (uint64_t)row0 * ld);
+  // one descriptor over the whole operand (its size is below 4 GiB)
+  const i32x4 res = make_res(a.Xs, (uint64_t)a.npad * ld);
+  const int voff = (wave * 8 + (lane >> 3)) * (int)ld + (((lane & 7) ^ (lane >> 3)) << 4);
+  const uint32_t roff0 = (uint32_t)row0 * ld;
+  const uint32_t step = 32u * ld;
 
   f32x16 acc[4][2];
 
-  // prologue: chunks 0 and 1 in flight
-  for (int g = 0; g < 2 && g < total; ++g) {
-    const int t = g / kch;
-    const int64_t ct = sc0 + (int64_t)t * BN;
-    issue_chunk(smem + (g % NSTAGE) * STAGE, rres, make_res(a.Xs + ct * ld, tot_bytes - (uint64_t)ct * ld), ld,
-                g - t * kch, wave, lane);
-  }
+  // the chunk to prefetch next: tile pt, chunk pc, ring stage ps
+  int pt = 0, pc = 0, ps = 0;
+#define GCR_ISSUE_NEXT()                                                                              \
+  do {                                                                                               \
+    issue_chunk(smem + ps * STAGE, res, voff, roff0 + (uint32_t)pc * 128u,                           \
+                (uint32_t)(sc0 + (int64_t)pt * BN) * ld + (uint32_t)pc * 128u, step, wave);          \
+    ps = ps + 1 == NSTAGE ? 0 : ps + 1;                                                              \
+    if (++pc == kch) { pc = 0; ++pt; }                                                              \
+  } while (0)
 
+  // prologue: chunks 0 and 1 in flight
+  if (total > 0) GCR_ISSUE_NEXT();
+  if (total > 1) GCR_ISSUE_NEXT();
+
+  int g = 0, gs = 0;  // chunk being multiplied and its stage
   for (int tile = 0; tile < ntiles; ++tile) {
+    const int64_t ct0 = sc0 + (int64_t)tile * BN;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
       for (int rb2 = 0; rb2 < 2; ++rb2)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[cb][rb2][i] = 0.f;
-    // descriptors of this tile's and the next tile's columns
-    const int64_t ctc = sc0 + (int64_t)tile * BN;
-    const i32x4 cres_cur = make_res(a.Xs + ctc * ld, tot_bytes - (uint64_t)ctc * ld);
-    const int64_t ctn = ctc + BN;
-    const i32x4 cres_nxt = make_res(a.Xs + ctn * ld, tot_bytes > (uint64_t)ctn * ld ? tot_bytes - (uint64_t)ctn * ld : 0);
-    for (int ch = 0; ch < kch; ++ch) {
-      const int g = tile * kch + ch;
+    float pf_n2 = INFINITY, pf_sc = 1.0f;
+    int pf_cam = 0;
+    uint32_t pf_stamp = 0u;
+    for (int ch = 0; ch < kch; ++ch, ++g) {
       // chunk g has landed once at most the next chunk's loads are pending;
       // right after an epilogue (candidate stores, compaction loads) and at
       // the end drain everything
       if (ch == 0 || g + 1 >= total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
       else __builtin_amdgcn_s_waitcnt(waitcnt_vm(DMA_PER_WAVE));
-      __syncthreads();
-      if (g + 2 < total) {
-        const int t2 = (g + 2) / kch, ch2 = (g + 2) - t2 * kch;
-        i32x4 cres = t2 == tile ? cres_cur : cres_nxt;
-        if (t2 > tile + 1) {  // one chunk per tile: the prefetch runs two tiles ahead
-          const int64_t ct2 = sc0 + (int64_t)t2 * BN;
-          cres = make_res(a.Xs + ct2 * ld, tot_bytes - (uint64_t)ct2 * ld);
+      // Every wave has waited for its own part of chunk g above; a plain
+      // barrier (no fence: a fence would also wait for the chunks still in
+      // flight) then makes the whole chunk visible.  The stage refilled next
+      // was last read by fragment loads that completed before the previous
+      // chunk's MFMAs issued.
+      asm volatile("s_barrier" ::: "memory");
+      if (g + 2 < total) GCR_ISSUE_NEXT();
+      if (ch == 0) {
+        // column data of this tile for the epilogue: independent loads
+        // issued after the chunk loads above, so their latency hides under
+        // the multiplies (the device-side column count is already in sc1)
+        const int64_t c = ct0 + tid;  // NT == BN
+        if (c < sc1) {
+          pf_n2 = a.n2[c];
+          if (a.cam) pf_cam = a.cam[c];
+          if (PREC == GCR_PREC_FP8) pf_sc = a.scale[c];
+          if (a.filt.stamp_of) pf_stamp = a.filt.stamp_of[c];
         }
-        issue_chunk(smem + ((g + 2) % NSTAGE) * STAGE, rres, cres, ld, ch2, wave, lane);
       }
-      const uint8_t* S = smem + (g % NSTAGE) * STAGE;
+      const uint8_t* S = smem + gs * STAGE;
+      gs = gs + 1 == NSTAGE ? 0 : gs + 1;
       mma_chunk<PREC>(S, S + RBYTES, wr, wc, lane, acc);
     }
 
     // ---------------- epilogue of one 128 x 256 tile ----------------
-    const int64_t ct0 = sc0 + (int64_t)tile * BN;
-    {
-      const int64_t c = ct0 + tid;  // NT == BN
-      const bool cv = c < sc1 && !column_out(a.filt, c, a.c0);
-      col_n2[tid] = cv ? a.n2[c] : INFINITY;
-      col_cam[tid] = (a.cam && cv) ? a.cam[c] : 0;
-      col_sc[tid] = (PREC == GCR_PREC_FP8 && cv) ? a.scale[c] : 1.0f;
-    }
+    col_n2[tid] = (a.filt.stamp_of && pf_stamp == a.filt.stamp) ? INFINITY : pf_n2;
+    col_cam[tid] = pf_cam;
+    col_sc[tid] = pf_sc;
     __syncthreads();
 
-    // Keys of the whole tile (ineligible entries become +inf), and a vote:
-    // which 32-column blocks hold any key under its row's threshold.  Blocks
-    // nobody votes for skip the admission protocol altogether, which after
-    // the first tiles is almost every block.
-    uint32_t myvote = 0;
+    // The lane's first tile column, hidden from the optimiser once per tile
+    // so that the per-element column offsets below are formed at their use
+    // instead of being hoisted out of the tile loop as 128 live registers.
+    int lcol = wc + 4 * half;
+    asm volatile("" : "+v"(lcol));
+    // keys of the whole tile in place (ineligible entries become +inf) and,
+    // per row and list, the mask of entries under the admission threshold:
+    // bit cb * 16 + i of pend[rb2][L]
+    uint64_t pend[2][NL];
 #pragma unroll
     for (int rb2 = 0; rb2 < 2; ++rb2) {
       const int lr = wr + 32 * rb2 + l32;
-      const int64_t row = row0 + lr;
-      const float tmax = NL > 1 ? fmaxf(row_thr[0][lr], row_thr[NL - 1][lr]) : row_thr[0][lr];
+      const float t0 = row_thr[0][lr];
+      const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
       const float rs = row_sc[lr];
-      const bool rvalid = row < a.r1;
+      const int rc = row_cam[lr];
+      const bool rvalid = row0 + lr < a.r1;
+      // column offset (within the tile) of this row's own column, if any
+      const int64_t selfc = row0 + lr - ct0;
+      const int selfoff = (a.exclude_self && selfc >= 0 && selfc < BN) ? (int)selfc : -1;
+#pragma unroll
+      for (int L = 0; L < NL; ++L) pend[rb2][L] = 0ull;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        float mn = INFINITY;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
-          const int64_t col = ct0 + lc;
-          float s = acc[cb][rb2][i];
-          if (PREC == GCR_PREC_FP8) s = s * (rs * col_sc[lc]);
-          const bool valid = rvalid && col < sc1 && !(a.exclude_self && col == row);
-          const float key = valid ? col_n2[lc] - 2.0f * s : INFINITY;
+          const int lc = lcol + 32 * cb + 8 * (i >> 2) + (i & 3);
+          float sv = acc[cb][rb2][i];
+          if (PREC == GCR_PREC_FP8) sv = sv * (rs * col_sc[lc]);
+          const bool valid = rvalid && lc != selfoff;
+          const float key = valid ? col_n2[lc] - 2.0f * sv : INFINITY;
           acc[cb][rb2][i] = key;
-          mn = fminf(mn, key);
+          const uint64_t bit = 1ull << (cb * 16 + i);
+          if (key <= t0) pend[rb2][0] |= bit;
+          if (NL > 1 && col_cam[lc] != rc && key <= t1) pend[rb2][NL - 1] |= bit;
         }
-        if (mn <= tmax) myvote |= 1u << cb;
       }
     }
-    {
-      uint32_t wv = 0;
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        if (__any((myvote >> cb) & 1u)) wv |= 1u << cb;
-      if (lane == 0 && wv) atomicOr(&cb_vote[tile & 1], wv);
-    }
-    __syncthreads();
-    const uint32_t votes = cb_vote[tile & 1];
-    if (tid == 0) cb_vote[(tile + 1) & 1] = 0u;
-    int it = 0;
 
+    // admission: one pass in the common case; when a buffer fills, the full
+    // buffers are compacted (lower thresholds) and the rest re-screened
+    for (int it = 0;; ++it) {
+      bool left = false;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      if (!((votes >> cb) & 1u)) continue;  // uniform over the workgroup
-      uint32_t pend[NL];
+      for (int rb2 = 0; rb2 < 2; ++rb2) {
+        const int lr = wr + 32 * rb2 + l32;
 #pragma unroll
-      for (int L = 0; L < NL; ++L) pend[L] = 0u;
+        for (int L = 0; L < NL; ++L) {
+          const uint64_t m = pend[rb2][L];
+          const int c = __popcll(m);
+          if (c == 0) continue;
+          // one atomic per (row, list) reserves all of this lane's slots;
+          // each pending entry goes to base + its rank among them
+          const int base = atomicAdd(&row_cnt[L][lr], c);
+          const int room = max(0, min(c, a.C - base));
+          uint64_t* rowbuf = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C + base;
+          uint64_t done = 0ull;
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              const int bi = cb * 16 + i;
+              const uint64_t bit = 1ull << bi;
+              if (m & bit) {
+                const int rank = __popcll(m & (bit - 1ull));
+                if (rank < room) {
+                  const int lc = lcol + 32 * cb + 8 * (i >> 2) + (i & 3);
+                  rowbuf[rank] = pack_cand(acc[cb][rb2][i], (uint32_t)(ct0 - a.c0) + (uint32_t)lc);
+                  done |= bit;
+                }
+              }
+            }
+          }
+          pend[rb2][L] = m & ~done;
+          if (pend[rb2][L]) left = true;
+        }
+      }
+      if (__any(left) && lane == 0) any_flag[it & 1] = 1;
+      __syncthreads();
+      const int more = any_flag[it & 1];
+      if (tid == 0) any_flag[(it + 1) & 1] = 0;
+      if (!more) break;
+      for (int q = wave; q < NL * BM; q += NT / 64) {
+        const int L = q / BM, lr = q - L * BM;
+        if (row_cnt[L][lr] >= a.C) {
+          uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
+          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
+        }
+      }
+      __syncthreads();
 #pragma unroll
       for (int rb2 = 0; rb2 < 2; ++rb2) {
         const int lr = wr + 32 * rb2 + l32;
         const float t0 = row_thr[0][lr];
         const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
-        const int rc = row_cam[lr];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
-          const float key = acc[cb][rb2][i];
-          const int bit = rb2 * 16 + i;
-          if (key <= t0) pend[0] |= 1u << bit;
-          if (NL > 1 && col_cam[lc] != rc && key <= t1) pend[NL - 1] |= 1u << bit;
-        }
-      }
-      while (true) {
-        uint32_t anyp = 0;
-#pragma unroll
-        for (int L = 0; L < NL; ++L) anyp |= pend[L];
-        if (__any(anyp != 0u)) {
-          // one atomic per (row, list) reserves all of this lane's slots;
-          // each pending score then goes to base + its rank among them
-          int base[2][NL], room[2][NL];
-#pragma unroll
-          for (int rb2 = 0; rb2 < 2; ++rb2) {
-            const int lr = wr + 32 * rb2 + l32;
-#pragma unroll
-            for (int L = 0; L < NL; ++L) {
-              const int c = __popc((pend[L] >> (rb2 * 16)) & 0xffffu);
-              base[rb2][L] = c ? atomicAdd(&row_cnt[L][lr], c) : 0;
-              room[rb2][L] = max(0, min(c, a.C - base[rb2][L]));
-            }
-          }
-#pragma unroll
-          for (int rb2 = 0; rb2 < 2; ++rb2) {
-            const int lr = wr + 32 * rb2 + l32;
-#pragma unroll
-            for (int L = 0; L < NL; ++L) {
-              const uint32_t m16 = (pend[L] >> (rb2 * 16)) & 0xffffu;
-              if (room[rb2][L] > 0) {
-                uint64_t* rowbuf = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C + base[rb2][L];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                  const uint32_t bit = 1u << i;
-                  const int rank = __popc(m16 & (bit - 1u));
-                  if ((m16 & bit) && rank < room[rb2][L]) {
-                    const int lc = wc + 32 * cb + 8 * (i >> 2) + 4 * half + (i & 3);
-                    rowbuf[rank] = pack_cand(acc[cb][rb2][i], (uint32_t)(ct0 + lc - a.c0));
-                    pend[L] &= ~(bit << (rb2 * 16));
-                  }
-                }
-              }
-            }
-          }
-        }
-        anyp = 0;
-#pragma unroll
-        for (int L = 0; L < NL; ++L) anyp |= pend[L];
-        if (__any(anyp != 0u) && lane == 0) any_flag[it & 1] = 1;
-        __syncthreads();
-        const int any = any_flag[it & 1];
-        if (tid == 0) any_flag[(it + 1) & 1] = 0;
-        ++it;
-        if (!any) break;
-        for (int q = wave; q < NL * BM; q += NT / 64) {
-          const int L = q / BM, lr = q - L * BM;
-          if (row_cnt[L][lr] >= a.C) {
-            uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
-            compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int rb2 = 0; rb2 < 2; ++rb2) {
-          const int lr = wr + 32 * rb2 + l32;
-          const float t0 = row_thr[0][lr];
-          const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
+        for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            const uint32_t m = 1u << (rb2 * 16 + i);
-            if (!(acc[cb][rb2][i] <= t0)) pend[0] &= ~m;
-            if (NL > 1 && !(acc[cb][rb2][i] <= t1)) pend[NL - 1] &= ~m;
+            const uint64_t bit = 1ull << (cb * 16 + i);
+            if (!(acc[cb][rb2][i] <= t0)) pend[rb2][0] &= ~bit;
+            if (NL > 1 && !(acc[cb][rb2][i] <= t1)) pend[rb2][NL - 1] &= ~bit;
           }
         }
       }
@@ -479,6 +463,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       __syncthreads();
     }
   }
+#undef GCR_ISSUE_NEXT
 
   __syncthreads();
   for (int t = tid; t < BM * NL; t += NT) {
