@@ -92,6 +92,17 @@ __global__ void add_count_kernel(unsigned long long* dst, const int* src) { *dst
 
 int esize_of(int prec) { return prec == GCR_PREC_FP32 ? 4 : (prec == GCR_PREC_BF16 ? 2 : 1); }
 
+// Compute units of the current device (one similarity workgroup each).
+int compute_units() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return n;
+}
+
 // Relative error of the float32 accumulation of the screening products:
 // |fl(sum) - sum| <= eps * ||x~_r|| ||x~_c||.  BF16 and FP8 products are
 // exact in float32 (m = d rounded additions); float32 products round too
@@ -142,6 +153,19 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   // the GPU.
   int S = 1;
   while ((int64_t)kp.RB * S < 128 && (int64_t)S * 2 * TC <= kp.ncols && S * 2 * kp.C <= 2048 && S < 64) S *= 2;
+  // With many row blocks the sweep is cut evenly over one workgroup per
+  // compute unit instead (a row block split over workgroups becomes extra
+  // splits), so that no unit idles behind the last row blocks.
+  const int G = compute_units();
+  const int Sb = sim_topk_balanced_splits(kp.rows, kp.ncols, G);
+  kp.balanced = 0;
+  if (Sb > 0 && Sb * kp.C <= 2048) {
+    S = Sb;
+    kp.balanced = 1;
+    kp.grid = G;
+    kp.ntr = (int)((kp.ncols + TC - 1) / TC);
+    kp.total_tiles = (int64_t)kp.RB * kp.ntr;
+  }
   kp.S = S;
   kp.W = roundup((kp.ncols + S - 1) / S, TC);
   kp.fb_grid = 256;
@@ -202,6 +226,13 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   sa.eps_s = eps_accumulation(kp.prec, d); sa.eps_n = eps_norm(d);
   sa.cand = kp.cand; sa.cnt = kp.cnt; sa.thr = kp.thr;
   sa.thr_init = nullptr;
+  sa.balanced = kp.balanced; sa.grid = kp.grid; sa.ntr = kp.ntr; sa.total_tiles = kp.total_tiles;
+  if (kp.balanced) {
+    // a row block has up to S pieces; the ones no workgroup sweeps stay
+    // empty with an infinite threshold
+    fill_u32(kp.cnt, 0u, kp.rows * kp.nl * kp.S, st);
+    fill_u32(kp.thr, 0x7f800000u, kp.rows * kp.nl * kp.S, st);
+  }
   if (prev0 && r0 == 0 && c0 == 0 && r1 == c1 && (k1 == 0 || prev1)) {
     TimedScope ts(c, 1, st);
     launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, kp.rn, (const float*)kp.maxn2,

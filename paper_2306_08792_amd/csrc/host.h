@@ -48,6 +48,8 @@ struct Arena {
 
 struct KnnPlan {
   int prec, nl, C, S, RB, kch, fb_grid;
+  int balanced = 0, grid = 0, ntr = 0;  // balanced similarity schedule
+  int64_t total_tiles = 0;
   int64_t n, npad, ld, W, rows, ncols;
   uint8_t* Xs; float* n2; float* scale; float* rn; unsigned* maxn2;
   uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
@@ -66,6 +68,7 @@ gcr_status fail(gcr_ctx* c, gcr_status s, const char* fmt, ...);
 gcr_status ensure_ws(gcr_ctx* c, size_t bytes);
 void fill_u32(void* p, unsigned v, int64_t n, hipStream_t st);
 int esize_of(int prec);
+int compute_units();
 float eps_accumulation(int prec, int d);
 float eps_norm(int d);
 int capacity_for(int prec, int kmax, int nl);

@@ -61,8 +61,13 @@ struct SimArgs {
   float* thr;         // [(r1-r0), NL, S] final admission threshold: the buffer
                       // holds every item of the split with key <= thr
   ColumnFilter filt;  // columns left out of the search
+  int balanced = 0;   // balanced schedule (S = most pieces of a row block)
+  int grid = 0;       // balanced: workgroups
+  int ntr = 0;        // balanced: 256-column tiles per row
+  int64_t total_tiles = 0;  // balanced: RB * ntr
 };
 int sim_topk_grid(int RB, int S);
+int sim_topk_balanced_splits(int64_t rows, int64_t ncols, int G);
 // Initial admission thresholds from earlier neighbour lists (any k items give
 // an upper bound on the k-th distance): out[row * nl + L].
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,

@@ -48,6 +48,18 @@ constexpr int waitcnt_vm(int n) { return 0xF70 | (n & 0xF) | (((n >> 4) & 3) << 
 }  // namespace
 
 int sim_topk_grid(int RB, int S) { return RB * S; }
+
+// Balanced schedule for rows [r0, r0 + rows) x ncols columns on G
+// workgroups: the largest number of pieces (splits) one row block can be
+// cut into, or 0 when the rows are too few for it.
+int sim_topk_balanced_splits(int64_t rows, int64_t ncols, int G) {
+  const int64_t RB = (rows + BM - 1) / BM, nt = (ncols + BN - 1) / BN;
+  if (RB < 64 || nt < 1) return 0;
+  const int64_t T = RB * nt;
+  if (T < G) return 0;
+  const int64_t per = T / G;  // every workgroup gets per or per + 1 tiles
+  return (int)((nt + per - 1) / per + 1);
+}
 int sim_topk_tile_cols() { return BN; }
 
 typedef uint32_t __attribute__((address_space(3)))* lds_u32_ptr;
@@ -234,21 +246,50 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ int row_cam[BM];
   __shared__ int any_flag[2];
 
-  // XCD-aware placement: workgroup ids go round-robin over the 8 XCDs and
-  // the split is id mod S, so every workgroup an XCD runs sweeps the same
-  // column split (S <= 8 divides 8) and the column tiles are shared in that
-  // XCD's L2; consecutive row blocks spread over all XCDs.
   const int id = blockIdx.x;
-  const int cs = id % a.S;
-  const int rb = id / a.S;
-  if (rb >= a.RB) return;
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = a.r0 + (int64_t)rb * BM;
-  const int64_t sc0 = a.c0 + (int64_t)cs * a.W;
-  const int64_t sc1 = min(a.filt.count ? a.c0 + (int64_t)*a.filt.count : a.c1, min(a.c1, sc0 + a.W));
-  const int ntiles = sc1 > sc0 ? (int)((sc1 - sc0 + BN - 1) / BN) : 0;
   const float maxn2 = a.maxn2[0];
+  const int64_t cend = a.filt.count ? min(a.c1, a.c0 + (int64_t)*a.filt.count) : a.c1;
+
+  // Work pieces.  Split mode: workgroup id sweeps column split id mod S of
+  // row block id / S (workgroup ids go round-robin over the 8 XCDs, so with
+  // S dividing 8 every workgroup an XCD runs sweeps the same split and
+  // shares its column tiles in L2).  Balanced mode (many row blocks): the
+  // row-block x tile space is cut into gridDim.x equal ranges, one per
+  // workgroup; the part of a row block that one workgroup sweeps is that
+  // row's split number (workgroup - first workgroup of the row block).
+  int64_t g_cur = 0, g_end = 0;
+  if (a.balanced) {
+    g_cur = (int64_t)id * a.total_tiles / gridDim.x;
+    g_end = (int64_t)(id + 1) * a.total_tiles / gridDim.x;
+  }
+  for (bool first = true;; first = false) {
+  int rb, cs, ntiles;
+  int64_t sc0, sc1;
+  if (a.balanced) {
+    if (g_cur >= g_end) break;
+    rb = (int)(g_cur / a.ntr);
+    const int64_t x = (int64_t)rb * a.ntr;
+    const int t0 = (int)(g_cur - x);
+    const int t1 = (int)min<int64_t>(a.ntr, t0 + (g_end - g_cur));
+    // first workgroup w with (w + 1) T / G > x, i.e. w = ceil((x + 1) G / T) - 1
+    const int64_t G = gridDim.x;
+    cs = id - (int)(((x + 1) * G + a.total_tiles - 1) / a.total_tiles - 1);
+    sc0 = a.c0 + (int64_t)t0 * BN;
+    sc1 = min(cend, a.c0 + (int64_t)t1 * BN);
+    ntiles = t1 - t0;
+    g_cur += t1 - t0;
+  } else {
+    if (!first) break;
+    cs = id % a.S;
+    rb = id / a.S;
+    if (rb >= a.RB) break;
+    sc0 = a.c0 + (int64_t)cs * a.W;
+    sc1 = min(cend, sc0 + a.W);
+    ntiles = sc1 > sc0 ? (int)((sc1 - sc0 + BN - 1) / BN) : 0;
+  }
+  __syncthreads();  // the previous piece is done with the shared state
+  const int64_t row0 = a.r0 + (int64_t)rb * BM;
 
   if (tid < 2) any_flag[tid] = 0;
   for (int t = tid; t < BM; t += NT) {
@@ -474,11 +515,12 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       a.thr[o] = row_thr[L][lr];
     }
   }
+  }  // pieces
 }
 
 template <int PREC, int NL>
 static void launch_prec_nl(const SimArgs& a, hipStream_t st) {
-  const dim3 grid(sim_topk_grid(a.RB, a.S)), block(NT);
+  const dim3 grid(a.balanced ? a.grid : sim_topk_grid(a.RB, a.S)), block(NT);
   if (a.C <= 64) {
     auto k = sim_topk_kernel<PREC, NL, 1>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
