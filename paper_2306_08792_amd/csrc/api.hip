@@ -181,6 +181,7 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.fb_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
   kp.fb_cut = ar.take<float>((size_t)kp.rows * kp.nl + 1);
   kp.ovf_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
+  kp.heavy_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
   kp.band_max = (int)std::min<int64_t>(2048, kp.rows * kp.nl);
   kp.band_cap = 2048;
   kp.band = ar.take<uint64_t>((size_t)kp.band_max * kp.band_cap + 1);
@@ -211,7 +212,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
              const int32_t* order) {
   if (r0 != 0) order = nullptr;
   fill_u32(kp.maxn2, 0u, 2, st);
-  fill_u32(kp.fb_count, 0u, 2, st);
+  fill_u32(kp.fb_count, 0u, 3, st);
   fill_u32(kp.band_cnt, 0u, kp.band_max, st);
   {
     TimedScope ts(c, 5, st);
@@ -255,6 +256,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   ra.fb_cut = kp.fb_cut; ra.eps32 = eps_accumulation(GCR_PREC_FP32, d);
   ra.band = kp.band; ra.band_cnt = kp.band_cnt; ra.band_cap = kp.band_cap; ra.band_max = kp.band_max;
   ra.ovf_list = kp.ovf_list; ra.ovf_count = kp.fb_count + 1;
+  ra.heavy_list = kp.heavy_list; ra.heavy_count = kp.fb_count + 2;
   ra.order = nullptr;
   if (kp.ord && r0 == 0 && c0 == 0 && r1 == c1 && k0 > 0) {
     TimedScope ts(c, 1, st);

@@ -110,6 +110,8 @@ struct RefineArgs {
   int band_cap, band_max;
   int* ovf_list;      // [(r1-r0) * NL] pairs for the exhaustive path
   int* ovf_count;     // device counter, zero before the launch
+  int* heavy_list;    // [(r1-r0) * NL] pairs for the block refine kernel
+  int* heavy_count;   // device counter, zero before the launch
   ColumnFilter filt;  // columns left out of the search
 };
 // queued pairs handled by the column-parallel exhaustive path (batch calls)

@@ -69,6 +69,8 @@ __device__ void block_sort_pairs(uint64_t* key, uint32_t* aux, int n) {
   }
 }
 
+// Block version for the (row, list) pairs the wave kernel passes on (more
+// than 128 candidates inside the cut): the union is sorted in LDS.
 __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   __shared__ uint64_t U[UMAX];
   __shared__ uint64_t ek[UMAX];
@@ -78,12 +80,13 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   __shared__ float s_tmin;
 
   const int NL = a.NL;
-  const int64_t p = xcd_position(blockIdx.x, gridDim.x);
-  const int64_t prel = p / NL;
-  const int L = (int)(p - prel * NL);
-  const int64_t rrel = a.order ? (int64_t)a.order[prel] : prel;
+  const int nheavy = *a.heavy_count;
+  for (int f = blockIdx.x; f < nheavy; f += gridDim.x) {
+  __syncthreads();
+  const int code = a.heavy_list[f];
+  const int64_t rrel = code >> 1;
+  const int L = code & 1;
   const int64_t row = a.r0 + rrel;
-  if (row >= a.r1) return;
   const int kk = L == 0 ? a.k0 : a.k1;
   int32_t* oidx = (L == 0 ? a.idx0 : a.idx1) + rrel * kk;
   float* odist = (L == 0 ? a.dist0 : a.dist1) + rrel * kk;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
       // hence so does the exact k-th smallest key of the row
       a.fb_cut[slot] = tau + 0.5f * twoE;
     }
-    return;
+    continue;
   }
   if (tid == 0) s_M = 0;
   __syncthreads();
@@ -162,6 +165,255 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
     }
   }
   if (tid == 0 && a.stat_cands) atomicAdd(a.stat_cands, (unsigned long long)M);
+  }  // heavy pairs
+}
+
+// ---------------------------------------------------------------------------
+// One wave per (row, list): the union of the split buffers goes to the
+// wave's LDS region, a radix select over the ordered keys gives tau (the
+// k-th smallest screened key), the candidates with key <= tau + 2E (at most
+// 128, else the pair goes to the block kernel) are re-scored exactly two at
+// a time with the row held in registers, and a wave bitonic sort by
+// (distance, index) orders them.
+constexpr int WR_MAX = 128;  // re-scored candidates handled by one wave
+
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// float-float squared distances of the register-held row to two rows
+__device__ __forceinline__ void wave_exact_sqdist2_reg(const float (&xr)[32], const float* __restrict__ xa,
+                                                       const float* __restrict__ xb, int d, uint64_t& ka,
+                                                       uint64_t& kb) {
+  const int lane = threadIdx.x & 63;
+  float ha = 0.f, la = 0.f, hb = 0.f, lb = 0.f;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const int e = lane + 64 * t;
+    if (e < d) {
+      ff_acc_sqdiff(ha, la, xr[t], xa[e]);
+      ff_acc_sqdiff(hb, lb, xr[t], xb[e]);
+    }
+  }
+  float h, l;
+  fast_two_sum(ha, la, h, l);
+  wave_ff_sum(h, l);
+  fast_two_sum(h, l, ha, la);
+  fast_two_sum(hb, lb, h, l);
+  wave_ff_sum(h, l);
+  fast_two_sum(h, l, hb, lb);
+  ka = ((uint64_t)ord_f32(ha) << 32) | (uint64_t)ord_f32(la);
+  kb = ((uint64_t)ord_f32(hb) << 32) | (uint64_t)ord_f32(lb);
+}
+
+// The same with 16-byte loads when d is a multiple of 256 (lane l holds
+// elements 4 l + 256 t .. + 3 of the row in xr4[t]).
+template <int V>
+__device__ __forceinline__ void wave_exact_sqdist2_vec(const f32x4 (&xr4)[V], const float* __restrict__ xa,
+                                                       const float* __restrict__ xb, uint64_t& ka, uint64_t& kb) {
+  const int lane = threadIdx.x & 63;
+  f32x4 va[V], vb[V];
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    va[t] = ((const f32x4*)xa)[t * 64 + lane];
+    vb[t] = ((const f32x4*)xb)[t * 64 + lane];
+  }
+  float ha = 0.f, la = 0.f, hb = 0.f, lb = 0.f;
+#pragma unroll
+  for (int t = 0; t < V; ++t) {
+    ff_acc_sqdiff(ha, la, xr4[t].x, va[t].x);
+    ff_acc_sqdiff(ha, la, xr4[t].y, va[t].y);
+    ff_acc_sqdiff(ha, la, xr4[t].z, va[t].z);
+    ff_acc_sqdiff(ha, la, xr4[t].w, va[t].w);
+    ff_acc_sqdiff(hb, lb, xr4[t].x, vb[t].x);
+    ff_acc_sqdiff(hb, lb, xr4[t].y, vb[t].y);
+    ff_acc_sqdiff(hb, lb, xr4[t].z, vb[t].z);
+    ff_acc_sqdiff(hb, lb, xr4[t].w, vb[t].w);
+  }
+  float h, l;
+  fast_two_sum(ha, la, h, l);
+  wave_ff_sum(h, l);
+  fast_two_sum(h, l, ha, la);
+  fast_two_sum(hb, lb, h, l);
+  wave_ff_sum(h, l);
+  fast_two_sum(h, l, hb, lb);
+  ka = ((uint64_t)ord_f32(ha) << 32) | (uint64_t)ord_f32(la);
+  kb = ((uint64_t)ord_f32(hb) << 32) | (uint64_t)ord_f32(lb);
+}
+
+// ascending bitonic sort of 128 (key, index) pairs, two per lane
+// (element j * 64 + lane in k[j], c[j]), by key then index
+__device__ __forceinline__ void wave_sort_pairs2(uint64_t (&k)[2], uint32_t (&c)[2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride == 64) {
+        const bool asc = (lane & size) == 0;  // element lane vs lane + 64
+        const bool gt = k[0] > k[1] || (k[0] == k[1] && c[0] > c[1]);
+        if (gt == asc) {
+          const uint64_t tk = k[0]; k[0] = k[1]; k[1] = tk;
+          const uint32_t tc = c[0]; c[0] = c[1]; c[1] = tc;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int e = j * 64 + lane;
+          const bool asc = (e & size) == 0;
+          const bool lower = (lane & stride) == 0;
+          const uint64_t ok = shfl_xor_u64(k[j], stride);
+          const uint32_t oc = __shfl_xor(c[j], stride, 64);
+          const bool mine_le = k[j] < ok || (k[j] == ok && c[j] <= oc);
+          const bool keep_mine = (lower == asc) ? mine_le : !mine_le;
+          if (!keep_mine) { k[j] = ok; c[j] = oc; }
+        }
+      }
+    }
+  }
+}
+
+// V > 0: d == 256 V with 16-byte aligned rows; V == 0: any d <= 2048.
+template <int V>
+__global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
+  extern __shared__ uint64_t wsm[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int UW = a.S * a.C;
+  uint64_t* U = wsm + (size_t)wave * UW;
+  uint32_t* Mc = (uint32_t*)(wsm + (size_t)4 * UW) + wave * WR_MAX;
+  const int NL = a.NL;
+  const int64_t items = (a.r1 - a.r0) * NL;
+  const int64_t p = xcd_position(blockIdx.x, gridDim.x) * 4 + wave;
+  if (p >= items) return;
+  const int64_t prel = p / NL;
+  const int L = (int)(p - prel * NL);
+  const int64_t rrel = a.order ? (int64_t)a.order[prel] : prel;
+  const int64_t row = a.r0 + rrel;
+  const int kk = L == 0 ? a.k0 : a.k1;
+  int32_t* oidx = (L == 0 ? a.idx0 : a.idx1) + rrel * kk;
+  float* odist = (L == 0 ? a.dist0 : a.dist1) + rrel * kk;
+
+  // split counts (prefix over lanes) and the smallest split threshold
+  const int64_t o = (rrel * NL + L) * (int64_t)a.S;
+  int c = 0;
+  float ts = INFINITY;
+  if (lane < a.S) {
+    c = min(a.cnt[o + lane], a.C);
+    ts = a.thr[o + lane];
+  }
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const int T = __shfl(incl, 63, 64);
+  const int excl = incl - c;
+  float tmin = ts;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tmin = fminf(tmin, __shfl_xor(tmin, off, 64));
+  const uint64_t* cbase = a.cand + o * a.C;
+  for (int s = 0; s < a.S; ++s) {
+    const int cs = __shfl(c, s, 64), os = __shfl(excl, s, 64);
+    for (int t = lane; t < cs; t += 64) U[os + t] = cbase[(int64_t)s * a.C + t];
+  }
+  wave_lds_sync();
+
+  // tau: smallest ordered key u with at least kk keys <= u
+  float tau = INFINITY;
+  if (T >= kk && kk > 0) {
+    uint32_t lo = 0u, hi = 0xfffffffeu;
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      int n = 0;
+      for (int e = lane; e < T; e += 64) n += (uint32_t)(U[e] >> 32) <= mid ? 1 : 0;
+      if (wave_sum_i(n) >= kk) hi = mid;
+      else lo = mid + 1u;
+    }
+    tau = unord_f32(lo);
+  }
+  const float twoE = 2.0f * screen_margin(a.n2[row], a.rn[row], a.maxn2[0], a.maxn2[1], a.eps_s, a.eps_n);
+  const float th = tau + twoE;
+  if (kk > 0 && th > tmin) {
+    if (lane == 0) {
+      const int slot = atomicAdd(a.fb_count, 1);
+      a.fb_list[slot] = (int)(rrel * 2 + L);
+      a.fb_cut[slot] = tau + 0.5f * twoE;
+    }
+    return;
+  }
+  // the candidates inside the cut, compacted (order irrelevant)
+  const uint32_t tho = ord_f32(th);
+  int M = 0;
+  for (int e0 = 0; e0 < T; e0 += 64) {
+    const int e = e0 + lane;
+    const uint64_t v = e < T ? U[e] : GCR_EMPTY;
+    const bool keep = e < T && (uint32_t)(v >> 32) <= tho;
+    const uint64_t bal = __ballot(keep);
+    const int pos = M + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (keep && pos < WR_MAX) Mc[pos] = cand_col(v);
+    M += __popcll(bal);
+  }
+  if (M > WR_MAX) {
+    if (lane == 0) a.heavy_list[atomicAdd(a.heavy_count, 1)] = (int)(rrel * 2 + L);
+    return;
+  }
+  wave_lds_sync();
+  // exact re-score, two candidates per step, the row in registers
+  const float* xrow = a.X + row * (int64_t)a.d;
+  constexpr int NR = V > 0 ? V : 1;
+  constexpr int NS = V > 0 ? 1 : 32;
+  f32x4 xr4[NR];
+  float xr[NS];
+  if constexpr (V > 0) {
+#pragma unroll
+    for (int t = 0; t < V; ++t) xr4[t] = ((const f32x4*)xrow)[t * 64 + lane];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int e = lane + 64 * t;
+      xr[t] = e < a.d ? xrow[e] : 0.f;
+    }
+  }
+  uint64_t ek[2] = {GCR_EMPTY, GCR_EMPTY};
+  uint32_t ec[2] = {0xffffffffu, 0xffffffffu};
+  for (int m = 0; m < M; m += 2) {
+    const uint32_t ca = Mc[m];
+    const uint32_t cb = m + 1 < M ? Mc[m + 1] : ca;
+    uint64_t ka, kb;
+    const float* pa = a.X + (a.c0 + (int64_t)ca) * a.d;
+    const float* pb = a.X + (a.c0 + (int64_t)cb) * a.d;
+    if constexpr (V > 0) wave_exact_sqdist2_vec<V>(xr4, pa, pb, ka, kb);
+    else wave_exact_sqdist2_reg(xr, pa, pb, a.d, ka, kb);
+    if ((m & 63) == lane) {
+      if (m < 64) { ek[0] = ka; ec[0] = ca; } else { ek[1] = ka; ec[1] = ca; }
+    }
+    if (m + 1 < M && ((m + 1) & 63) == lane) {
+      if (m + 1 < 64) { ek[0] = kb; ec[0] = cb; } else { ek[1] = kb; ec[1] = cb; }
+    }
+  }
+  wave_sort_pairs2(ek, ec);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = j * 64 + lane;
+    if (t < kk) {
+      if (t < M) {
+        oidx[t] = (int32_t)ec[j];
+        odist[t] = exact_hi(ek[j]);
+      } else {
+        oidx[t] = -1;
+        odist[t] = INFINITY;
+      }
+    }
+  }
+  if (lane == 0 && a.stat_cands) atomicAdd(a.stat_cands, (unsigned long long)M);
 }
 
 // Exhaustive exact path for (row, list) pairs whose cut reached past a
@@ -646,7 +898,22 @@ void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx
 void launch_refine(const RefineArgs& a, hipStream_t st) {
   const int64_t rows = a.r1 - a.r0;
   if (rows <= 0) return;
-  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)(rows * a.NL)), dim3(RT), 0, st, a);
+  {
+    const int64_t items = rows * a.NL;
+    const size_t lds = (size_t)4 * a.S * a.C * sizeof(uint64_t) + (size_t)4 * WR_MAX * sizeof(uint32_t);
+    const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+    const bool vec = a.d % 256 == 0 && (((uintptr_t)a.X) & 15) == 0;
+    auto go = [&](auto kern) {
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, a);
+    };
+    if (vec && a.d == 2048) go(refine_wave_kernel<8>);
+    else if (vec && a.d == 1024) go(refine_wave_kernel<4>);
+    else if (vec && a.d == 512) go(refine_wave_kernel<2>);
+    else if (vec && a.d == 256) go(refine_wave_kernel<1>);
+    else go(refine_wave_kernel<0>);
+  }
+  hipLaunchKernelGGL(refine_kernel, dim3(1024), dim3(RT), 0, st, a);
   hipLaunchKernelGGL(band_sweep_kernel, dim3(2048), dim3(256), 0, st, a);
   hipLaunchKernelGGL(band_select_kernel, dim3(1024), dim3(RT), 0, st, a);
   hipLaunchKernelGGL(fallback_scan_kernel, dim3(2048), dim3(256), 0, st, a);

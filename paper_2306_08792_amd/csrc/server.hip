@@ -41,6 +41,7 @@ struct KnnScratch {
   int64_t rows_cap = 0, ncols = 0;
   uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
   uint64_t* fb_pk; uint32_t* fb_pc; float* fb_cut; uint64_t* band; int* band_cnt; int* ovf_list;
+  int* heavy_list;
 };
 
 void plan_scratch(Arena& ar, KnnScratch& s, int64_t rows_cap, int64_t ncols, int k) {
@@ -66,13 +67,14 @@ void plan_scratch(Arena& ar, KnnScratch& s, int64_t rows_cap, int64_t ncols, int
   s.band = ar.take<uint64_t>((size_t)s.band_max * s.band_cap + 1);
   s.band_cnt = ar.take<int>((size_t)s.band_max + 1);
   s.ovf_list = ar.take<int>((size_t)rows_cap + 1);
+  s.heavy_list = ar.take<int>((size_t)rows_cap + 1);
 }
 
 // Rows [r0, r0 + b) against columns [c0, c1) of the operand: the k nearest
 // (distance, index) per row, exact (screening + exact re-score).
 void serve_knn(const Operand& op, const float* maxn2, const float* X, int d, const KnnScratch& s, int64_t r0, int b,
                int64_t c0, int64_t c1, int k, int32_t* idx, float* dist, const ColumnFilter& filt, hipStream_t st) {
-  fill_u32(s.fb_count, 0u, 2, st);
+  fill_u32(s.fb_count, 0u, 3, st);
   fill_u32(s.band_cnt, 0u, s.band_max, st);
   SimArgs sa;
   sa.Xs = op.Xs; sa.npad = op.npad; sa.ld_bytes = op.ld; sa.kchunks = op.kch; sa.n2 = op.n2;
@@ -99,6 +101,7 @@ void serve_knn(const Operand& op, const float* maxn2, const float* X, int d, con
   ra.fb_cut = s.fb_cut; ra.eps32 = eps_accumulation(GCR_PREC_FP32, d);
   ra.band = s.band; ra.band_cnt = s.band_cnt; ra.band_cap = s.band_cap; ra.band_max = s.band_max;
   ra.ovf_list = s.ovf_list; ra.ovf_count = s.fb_count + 1;
+  ra.heavy_list = s.heavy_list; ra.heavy_count = s.fb_count + 2;
   ra.order = nullptr;
   ra.filt = filt;
   launch_refine(ra, st);
