@@ -54,12 +54,12 @@ __device__ __forceinline__ uint8_t f32_to_e4m3_rne(float x) {
 
 // One wave per row: the screening operand row (ld_bytes, zero past d),
 // n2 = ||x||^2 (float32), the FP8 scale, an upper bound rn on the norm of
-// the quantisation residual x - x~, and the maxima of n2 and rn into
-// maxbits[0] and [1] (atomic max on the bit patterns, valid for
-// non-negative floats).
+// the quantisation residual x - x~; lane 0 folds n2 and rn into the running
+// maxima maxbits[0] and [1] (bit patterns: their unsigned order is the
+// order of non-negative floats).
 template <int PREC>
-__device__ void prep_row(const float* __restrict__ x, int d, uint8_t* out, int64_t ld_bytes, float* n2o,
-                         float* scaleo, float* rno, unsigned* maxbits, int lane) {
+__device__ __forceinline__ void prep_row(const float* __restrict__ x, int d, uint8_t* out, int64_t ld_bytes,
+                                         float* n2o, float* scaleo, float* rno, unsigned (&maxbits)[2], int lane) {
   float s = 0.f, amax = 0.f;
   for (int e = lane; e < d; e += 64) {
     float v = x[e];
@@ -71,7 +71,7 @@ __device__ void prep_row(const float* __restrict__ x, int d, uint8_t* out, int64
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
   if (lane == 0) {
     *n2o = s;
-    atomicMax(maxbits, __float_as_uint(s));
+    maxbits[0] = max(maxbits[0], __float_as_uint(s));
   }
   float r2 = 0.f;  // squared residual norm
   if (PREC == GCR_PREC_FP32) {
@@ -110,30 +110,117 @@ __device__ void prep_row(const float* __restrict__ x, int d, uint8_t* out, int64
     const float rb = sqrtf(r2 * (1.0f + (float)(d + 2) * 1.2e-7f)) * 1.000001f + 1.0e-7f * sqrtf(s);
     if (lane == 0) {
       *rno = rb;
-      atomicMax(maxbits + 1, __float_as_uint(rb));
+      maxbits[1] = max(maxbits[1], __float_as_uint(rb));
     }
   } else if (lane == 0) {
     *rno = 0.f;
   }
 }
 
-// Rows [0, npad): rows past n are zero (operand, n2, rn, scale).
+// prep_row for d % 4 == 0 and 16-byte aligned rows: 16-byte loads, the
+// operand written 4 elements per store, the padding past d zeroed.
+template <int PREC>
+__device__ __forceinline__ void prep_row_vec(const float* __restrict__ x, int d, uint8_t* out, int64_t ld_bytes,
+                                             float* n2o, float* scaleo, float* rno, unsigned (&maxbits)[2],
+                                             int lane) {
+  const f32x4* x4 = (const f32x4*)x;
+  const int d4 = d >> 2;
+  float s = 0.f, amax = 0.f;
+  for (int e = lane; e < d4; e += 64) {
+    const f32x4 v = x4[e];
+    s = fmaf(v.x, v.x, s); s = fmaf(v.y, v.y, s); s = fmaf(v.z, v.z, s); s = fmaf(v.w, v.w, s);
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+  }
+  s = wave_sum(s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) {
+    *n2o = s;
+    maxbits[0] = max(maxbits[0], __float_as_uint(s));
+  }
+  constexpr int ES = PREC == GCR_PREC_FP32 ? 4 : (PREC == GCR_PREC_BF16 ? 2 : 1);
+  float r2 = 0.f;
+  const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
+  if (PREC == GCR_PREC_FP8 && lane == 0) *scaleo = sc;
+  for (int e = lane; e < d4; e += 64) {
+    const f32x4 v = x4[e];
+    if (PREC == GCR_PREC_FP32) {
+      ((f32x4*)out)[e] = v;
+    } else if (PREC == GCR_PREC_BF16) {
+      const uint16_t h0 = f32_to_bf16_rne(v.x), h1 = f32_to_bf16_rne(v.y);
+      const uint16_t h2 = f32_to_bf16_rne(v.z), h3 = f32_to_bf16_rne(v.w);
+      const float r0 = v.x - bf16_to_f32(h0), r1 = v.y - bf16_to_f32(h1);
+      const float q2 = v.z - bf16_to_f32(h2), q3 = v.w - bf16_to_f32(h3);
+      r2 = fmaf(r0, r0, r2); r2 = fmaf(r1, r1, r2); r2 = fmaf(q2, q2, r2); r2 = fmaf(q3, q3, r2);
+      uint2 w;
+      w.x = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      w.y = (uint32_t)h2 | ((uint32_t)h3 << 16);
+      ((uint2*)out)[e] = w;
+    } else {
+      const uint8_t c0 = f32_to_e4m3_rne(v.x / sc), c1 = f32_to_e4m3_rne(v.y / sc);
+      const uint8_t c2 = f32_to_e4m3_rne(v.z / sc), c3 = f32_to_e4m3_rne(v.w / sc);
+      const float r0 = v.x - e4m3_to_f32(c0) * sc, r1 = v.y - e4m3_to_f32(c1) * sc;
+      const float q2 = v.z - e4m3_to_f32(c2) * sc, q3 = v.w - e4m3_to_f32(c3) * sc;
+      r2 = fmaf(r0, r0, r2); r2 = fmaf(r1, r1, r2); r2 = fmaf(q2, q2, r2); r2 = fmaf(q3, q3, r2);
+      ((uint32_t*)out)[e] = (uint32_t)c0 | ((uint32_t)c1 << 8) | ((uint32_t)c2 << 16) | ((uint32_t)c3 << 24);
+    }
+  }
+  // zero padding past d (whole 4-byte words: d * ES is a multiple of 4)
+  for (int64_t b = (int64_t)d * ES + lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
+  if (PREC != GCR_PREC_FP32) {
+    r2 = wave_sum(r2);
+    const float rb = sqrtf(r2 * (1.0f + (float)(d + 2) * 1.2e-7f)) * 1.000001f + 1.0e-7f * sqrtf(s);
+    if (lane == 0) {
+      *rno = rb;
+      maxbits[1] = max(maxbits[1], __float_as_uint(rb));
+    }
+  } else if (lane == 0) {
+    *rno = 0.f;
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void prep_row_any(const float* __restrict__ x, int d, uint8_t* out, int64_t ld_bytes,
+                                             float* n2o, float* scaleo, float* rno, unsigned (&maxbits)[2],
+                                             int lane) {
+  if ((d & 3) == 0 && (((uintptr_t)x) & 15) == 0)
+    prep_row_vec<PREC>(x, d, out, ld_bytes, n2o, scaleo, rno, maxbits, lane);
+  else
+    prep_row<PREC>(x, d, out, ld_bytes, n2o, scaleo, rno, maxbits, lane);
+}
+
+// Per-workgroup maxima of the waves' rows, merged with one atomic each.
+__device__ __forceinline__ void block_max_merge(unsigned (&mine)[2], unsigned* maxn2_bits) {
+  __shared__ unsigned sm[2][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sm[0][wave] = mine[0]; sm[1][wave] = mine[1]; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const unsigned m = max(max(sm[threadIdx.x][0], sm[threadIdx.x][1]), max(sm[threadIdx.x][2], sm[threadIdx.x][3]));
+    if (m) atomicMax(maxn2_bits + threadIdx.x, m);
+  }
+}
+
+// Rows [0, npad), one wave per row (grid-stride): rows past n are zero
+// (operand, n2, rn, scale).
 template <int PREC>
 __global__ __launch_bounds__(256) void screen_prep_kernel(const float* __restrict__ X, int64_t n,
                                                           int d, int64_t npad, uint8_t* Xs,
                                                           int64_t ld_bytes, float* n2,
                                                           float* scale, float* rn, unsigned* maxn2_bits) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= npad) return;
-  uint8_t* out = Xs + row * ld_bytes;
-  if (row >= n) {
-    for (int64_t b = lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
-    if (lane == 0) { n2[row] = 0.f; rn[row] = 0.f; if (scale) scale[row] = 0.f; }
-    return;
+  unsigned mine[2] = {0u, 0u};
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < npad; row += (int64_t)gridDim.x * 4) {
+    uint8_t* out = Xs + row * ld_bytes;
+    if (row >= n) {
+      for (int64_t b = lane * 4; b < ld_bytes; b += 256) *(uint32_t*)(out + b) = 0u;
+      if (lane == 0) { n2[row] = 0.f; rn[row] = 0.f; if (scale) scale[row] = 0.f; }
+      continue;
+    }
+    prep_row_any<PREC>(X + row * d, d, out, ld_bytes, n2 + row, scale ? scale + row : nullptr, rn + row, mine,
+                       lane);
   }
-  prep_row<PREC>(X + row * d, d, out, ld_bytes, n2 + row, scale ? scale + row : nullptr, rn + row, maxn2_bits,
-                 lane);
+  block_max_merge(mine, maxn2_bits);
 }
 
 // Rows [r0, r0 + nmax), or only the first *count of them when count is
@@ -145,11 +232,13 @@ __global__ __launch_bounds__(256) void screen_prep_rows_kernel(const float* __re
                                                                unsigned* maxn2_bits) {
   const int lane = threadIdx.x & 63;
   const int64_t nr = count ? min<int64_t>(nmax, (int64_t)*count) : nmax;
+  unsigned mine[2] = {0u, 0u};
   for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < nr; t += (int64_t)gridDim.x * 4) {
     const int64_t row = r0 + t;
-    prep_row<PREC>(X + row * d, d, Xs + row * ld_bytes, ld_bytes, n2 + row, scale ? scale + row : nullptr,
-                   rn + row, maxn2_bits, lane);
+    prep_row_any<PREC>(X + row * d, d, Xs + row * ld_bytes, ld_bytes, n2 + row, scale ? scale + row : nullptr,
+                       rn + row, mine, lane);
   }
+  block_max_merge(mine, maxn2_bits);
 }
 
 void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st) {
@@ -161,7 +250,7 @@ void launch_screen_prep_rows(int prec, const float* X, int64_t r0, int64_t nmax,
                              int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
                              hipStream_t st) {
   if (nmax <= 0) return;
-  const dim3 g((unsigned)std::min<int64_t>((nmax + 3) / 4, 4096)), b(256);
+  const dim3 g((unsigned)std::min<int64_t>((nmax + 3) / 4, 2048)), b(256);
   uint8_t* xs = (uint8_t*)Xs;
   if (prec == GCR_PREC_FP32)
     hipLaunchKernelGGL(screen_prep_rows_kernel<GCR_PREC_FP32>, g, b, 0, st, X, r0, nmax, count, d, xs, ld_bytes, n2,
@@ -177,7 +266,7 @@ void launch_screen_prep_rows(int prec, const float* X, int64_t r0, int64_t nmax,
 void launch_screen_prep(int prec, const float* X, int64_t n, int d, int64_t npad, void* Xs,
                         int64_t ld_bytes, float* n2, float* scale, float* rn, unsigned* maxn2_bits,
                         hipStream_t st) {
-  dim3 g((unsigned)((npad + 3) / 4)), b(256);
+  dim3 g((unsigned)std::min<int64_t>((npad + 3) / 4, 2048)), b(256);
   uint8_t* xs = (uint8_t*)Xs;
   if (prec == GCR_PREC_FP32)
     hipLaunchKernelGGL(screen_prep_kernel<GCR_PREC_FP32>, g, b, 0, st, X, n, d, npad, xs, ld_bytes, n2, scale, rn, maxn2_bits);

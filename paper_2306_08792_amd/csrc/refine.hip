@@ -848,6 +848,7 @@ __global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
 // U = max_j ||x_i - x_j||^2 - n2_i (up to the float32 error of n2_i), so the
 // final screened k-th key is <= U + E and the screening never needs to keep
 // keys above U + 3E, E being the row's screening margin.
+template <int V>
 __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __restrict__ X, int d, int64_t n,
                                                               const int32_t* __restrict__ idx0, int k0,
                                                               const int32_t* __restrict__ idx1, int k1,
@@ -857,6 +858,7 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
                                                               float eps_n, float* __restrict__ out,
                                                               const int32_t* __restrict__ order) {
   const int nl = idx1 ? 2 : 1;
+  const int lane = threadIdx.x & 63;
   const int64_t p = xcd_position(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (p >= n * nl) return;
   const int64_t prow = p / nl;
@@ -865,17 +867,41 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
   const int64_t w = row * nl + L;
   const int kk = L == 0 ? k0 : k1;
   const int32_t* lst = (L == 0 ? idx0 : idx1) + row * kk;
-  const float* xr = X + row * (int64_t)d;
+  const float* xrow = X + row * (int64_t)d;
+  constexpr int NR = V > 0 ? V : 1;
+  constexpr int NS = V > 0 ? 1 : 32;
+  f32x4 xr4[NR];
+  float xr[NS];
+  if constexpr (V > 0) {
+#pragma unroll
+    for (int t = 0; t < V; ++t) xr4[t] = ((const f32x4*)xrow)[t * 64 + lane];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int e = lane + 64 * t;
+      xr[t] = e < d ? xrow[e] : 0.f;
+    }
+  }
+  // the list's valid members come first; two exact distances per step
   float umax = -INFINITY;
   int valid = 0;
-  for (int t = 0; t < kk; ++t) {
-    const int j = lst[t];
-    if (j < 0) break;
-    const float dj = exact_hi(wave_exact_sqdist(xr, X + (int64_t)j * d, d));
-    umax = fmaxf(umax, dj);
+  for (int t = 0; t < kk; t += 2) {
+    const int32_t ja = lst[t];
+    if (ja < 0) break;
+    const int32_t jb0 = t + 1 < kk ? lst[t + 1] : -1;
+    const int32_t jb = jb0 >= 0 ? jb0 : ja;
+    uint64_t ka, kb;
+    const float* pa = X + (int64_t)ja * d;
+    const float* pb = X + (int64_t)jb * d;
+    if constexpr (V > 0) wave_exact_sqdist2_vec<V>(xr4, pa, pb, ka, kb);
+    else wave_exact_sqdist2_reg(xr, pa, pb, d, ka, kb);
+    umax = fmaxf(umax, exact_hi(ka));
+    ++valid;
+    if (jb0 < 0) break;
+    umax = fmaxf(umax, exact_hi(kb));
     ++valid;
   }
-  if ((threadIdx.x & 63) != 0) return;
+  if (lane != 0) return;
   float res = INFINITY;
   if (kk > 0 && valid == kk) {
     const float mx = *maxn2, n2r = n2[row];
@@ -891,8 +917,16 @@ void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx
                             float eps_n, float* out, const int32_t* order, hipStream_t st) {
   const int nl = idx1 ? 2 : 1;
   const int64_t waves = n * nl;
-  hipLaunchKernelGGL(seed_thresholds_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, X, d, n, idx0, k0,
-                     idx1, k1, n2, rn, maxn2, eps_s, eps_n, out, order);
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  const bool vec = d % 256 == 0 && (((uintptr_t)X) & 15) == 0;
+#define GCR_SEED(V) hipLaunchKernelGGL(seed_thresholds_kernel<V>, grid, block, 0, st, X, d, n, idx0, k0, idx1, k1, \
+                                       n2, rn, maxn2, eps_s, eps_n, out, order)
+  if (vec && d == 2048) GCR_SEED(8);
+  else if (vec && d == 1024) GCR_SEED(4);
+  else if (vec && d == 512) GCR_SEED(2);
+  else if (vec && d == 256) GCR_SEED(1);
+  else GCR_SEED(0);
+#undef GCR_SEED
 }
 
 void launch_refine(const RefineArgs& a, hipStream_t st) {
