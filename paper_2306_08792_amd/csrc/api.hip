@@ -177,6 +177,7 @@ void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, in
   kp.cand = ar.take<uint64_t>((size_t)kp.rows * kp.nl * S * kp.C);
   kp.cnt = ar.take<int>((size_t)kp.rows * kp.nl * S);
   kp.seed = ar.take<float>((size_t)kp.rows * kp.nl);
+  kp.thr_shared = ar.take<unsigned>((size_t)kp.rows * kp.nl);
   kp.thr = ar.take<float>((size_t)kp.rows * kp.nl * S);
   kp.fb_list = ar.take<int>((size_t)kp.rows * kp.nl + 1);
   kp.fb_cut = ar.take<float>((size_t)kp.rows * kp.nl + 1);
@@ -228,6 +229,11 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   sa.cand = kp.cand; sa.cnt = kp.cnt; sa.thr = kp.thr;
   sa.thr_init = nullptr;
   sa.balanced = kp.balanced; sa.grid = kp.grid; sa.ntr = kp.ntr; sa.total_tiles = kp.total_tiles;
+  sa.thr_shared = nullptr;
+  if (kp.S > 1) {
+    fill_u32(kp.thr_shared, 0xffffffffu, kp.rows * kp.nl, st);
+    sa.thr_shared = kp.thr_shared;
+  }
   if (kp.balanced) {
     // a row block has up to S pieces; the ones no workgroup sweeps stay
     // empty with an infinite threshold

@@ -55,6 +55,7 @@ struct KnnPlan {
   uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
   uint64_t* fb_pk; uint32_t* fb_pc;
   float* seed;
+  unsigned* thr_shared;
   float* fb_cut; uint64_t* band; int* band_cnt; int band_cap, band_max; int* ovf_list; int* heavy_list;
   int32_t *ord, *ord_label, *ord_cnt, *ord_blk;  // refine row order (square sweeps)
 };

@@ -61,6 +61,8 @@ struct SimArgs {
   float* thr;         // [(r1-r0), NL, S] final admission threshold: the buffer
                       // holds every item of the split with key <= thr
   ColumnFilter filt;  // columns left out of the search
+  unsigned* thr_shared = nullptr;  // [(r1-r0), NL] ordered-bits admission thresholds shared by
+                                   // the splits of a row (all ones = none yet), or nullptr
   int balanced = 0;   // balanced schedule (S = most pieces of a row block)
   int grid = 0;       // balanced: workgroups
   int ntr = 0;        // balanced: 256-column tiles per row
@@ -114,6 +116,15 @@ struct RefineArgs {
   int* heavy_count;   // device counter, zero before the launch
   ColumnFilter filt;  // columns left out of the search
 };
+// Merge of groups of GS consecutive split buffers into one buffer each
+// (S / GS splits out), keeping every item within reach of the exact top-k.
+struct MergeArgs {
+  const uint64_t* cand; const int* cnt; const float* thr;  // [rows, NL, S, C]
+  int64_t rows, r0; int NL, S, GS, C, k0, k1;
+  const float* n2; const float* rn; const float* maxn2; float eps_s, eps_n;
+  uint64_t* out_cand; int* out_cnt; float* out_thr;        // [rows, NL, S / GS, C]
+};
+void launch_merge_splits(const MergeArgs& m, hipStream_t st);
 // queued pairs handled by the column-parallel exhaustive path (batch calls)
 constexpr int FB_MAX = 8192;
 void launch_refine(const RefineArgs& a, hipStream_t st);

@@ -843,6 +843,101 @@ __global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split merge: one wave per (row, list, group of GS consecutive splits).
+// Every split buffer holds all of its items with key <= its threshold, so the
+// group's union holds all of the group's items with key <= tmin (the group's
+// smallest threshold).  Items above the group's own k-th key + 2E cannot be
+// within 2E of the global k-th key (which is no larger), so the merged buffer
+// keeps the union up to cut = min(tmin, tau_g + 2E), and if that is more than
+// C items, only the keys below the (C+1)-th smallest, lowering the cut; the
+// merged threshold is the cut.  The exactness argument of the refine is
+// unchanged: a merged buffer is a split buffer with a recorded threshold.
+__global__ __launch_bounds__(256) void merge_splits_kernel(MergeArgs m) {
+  extern __shared__ uint64_t msm[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int GS = m.GS, C = m.C, S2 = m.S / GS;
+  uint64_t* U = msm + (size_t)wave * GS * C;
+  const int64_t items = m.rows * m.NL * S2;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= items) return;
+  const int64_t rl = it / S2;            // (row, list)
+  const int g = (int)(it - rl * S2);
+  const int64_t rrel = rl / m.NL;
+  const int L = (int)(rl - rrel * m.NL);
+  const int kk = L == 0 ? m.k0 : m.k1;
+  const int64_t o = rl * m.S + (int64_t)g * GS;  // first split of the group
+  int c = 0;
+  float ts = INFINITY;
+  if (lane < GS) {
+    c = min(m.cnt[o + lane], C);
+    ts = m.thr[o + lane];
+  }
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const int T = __shfl(incl, 63, 64);
+  const int excl = incl - c;
+  float tmin = ts;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tmin = fminf(tmin, __shfl_xor(tmin, off, 64));
+  const uint64_t* src = m.cand + o * C;
+  for (int s = 0; s < GS; ++s) {
+    const int cs = __shfl(c, s, 64), os = __shfl(excl, s, 64);
+    for (int t = lane; t < cs; t += 64) U[os + t] = src[(int64_t)s * C + t];
+  }
+  wave_lds_sync();
+  auto count_le = [&](uint32_t u) {
+    int n = 0;
+    for (int e = lane; e < T; e += 64) n += (uint32_t)(U[e] >> 32) <= u ? 1 : 0;
+    return wave_sum_i(n);
+  };
+  auto select = [&](int r) {  // smallest ordered key with at least r keys <= it
+    uint32_t lo = 0u, hi = 0xfffffffeu;
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (count_le(mid) >= r) hi = mid;
+      else lo = mid + 1u;
+    }
+    return lo;
+  };
+  float cut = tmin;
+  if (kk > 0 && T >= kk) {
+    const int64_t row = m.r0 + rrel;
+    const float twoE = 2.0f * screen_margin(m.n2[row], m.rn[row], m.maxn2[0], m.maxn2[1], m.eps_s, m.eps_n);
+    cut = fminf(cut, unord_f32(select(kk)) + twoE);
+  }
+  if (kk == 0) cut = -INFINITY;
+  if (count_le(ord_f32(cut)) > C) cut = fminf(cut, nextafterf(unord_f32(select(C + 1)), -INFINITY));
+  const uint32_t co = ord_f32(cut);
+  uint64_t* dst = m.out_cand + (rl * S2 + g) * C;
+  int n = 0;
+  for (int e0 = 0; e0 < T; e0 += 64) {
+    const int e = e0 + lane;
+    const uint64_t v = e < T ? U[e] : GCR_EMPTY;
+    const bool keep = e < T && (uint32_t)(v >> 32) <= co;
+    const uint64_t bal = __ballot(keep);
+    const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (keep) dst[pos] = v;
+    n += __popcll(bal);
+  }
+  if (lane == 0) {
+    m.out_cnt[rl * S2 + g] = n;
+    m.out_thr[rl * S2 + g] = cut;
+  }
+}
+
+void launch_merge_splits(const MergeArgs& m, hipStream_t st) {
+  const int64_t items = m.rows * m.NL * (m.S / m.GS);
+  if (items <= 0) return;
+  const size_t lds = (size_t)4 * m.GS * m.C * sizeof(uint64_t);
+  (void)hipFuncSetAttribute((const void*)merge_splits_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(merge_splits_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), lds, st, m);
+}
+
 // One wave per (row, list).  If the previous list of the row has k valid
 // members j, the k-th smallest exact key of the row is at most
 // U = max_j ||x_i - x_j||^2 - n2_i (up to the float32 error of n2_i), so the

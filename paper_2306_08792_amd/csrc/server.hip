@@ -37,9 +37,12 @@ struct Operand {
 
 // Per-slot scratch of one screened search (rows <= rows_cap, ncols columns).
 struct KnnScratch {
-  int C = 0, S = 0, fb_grid = 8, fb_max = 32, band_cap = 2048, band_max = 0;
+  int C = 0, S = 0, GS = 1, fb_grid = 8, fb_max = 32, band_cap = 2048, band_max = 0;
   int64_t rows_cap = 0, ncols = 0;
-  uint64_t* cand; int* cnt; float* thr; int* fb_list; int* fb_count; uint64_t* fb_scr;
+  uint64_t* cand; int* cnt; float* thr;
+  uint64_t* cand2; int* cnt2; float* thr2;  // merged groups of GS splits
+  unsigned* thr_shared;                       // per-row thresholds shared by the splits
+  int* fb_list; int* fb_count; uint64_t* fb_scr;
   uint64_t* fb_pk; uint32_t* fb_pc; float* fb_cut; uint64_t* band; int* band_cnt; int* ovf_list;
   int* heavy_list;
 };
@@ -48,14 +51,23 @@ void plan_scratch(Arena& ar, KnnScratch& s, int64_t rows_cap, int64_t ncols, int
   s.rows_cap = rows_cap;
   s.ncols = ncols;
   s.C = k + 16 <= 64 ? 64 : (k + 16 <= 128 ? 128 : 256);
-  // few rows per request: split the columns so that the sweep fills the GPU
+  // few rows per request: split the columns over up to 256 workgroups so
+  // that the sweep fills the GPU; groups of GS splits are merged before the
+  // refine, whose union holds at most 2,048 entries
   int S = 1;
-  while (S * 2 * s.C <= 2048 && (int64_t)S * 2 * sim_topk_tile_cols() <= ncols && S < 64) S *= 2;
+  while ((int64_t)S * 2 * sim_topk_tile_cols() <= ncols && S < 256) S *= 2;
+  int GS = 1;
+  while ((int64_t)(S / GS) * s.C > 2048) GS *= 2;
   s.S = S;
+  s.GS = GS;
   s.band_max = (int)std::min<int64_t>(64, rows_cap);
   s.cand = ar.take<uint64_t>((size_t)rows_cap * S * s.C);
   s.cnt = ar.take<int>((size_t)rows_cap * S);
   s.thr = ar.take<float>((size_t)rows_cap * S);
+  s.thr_shared = ar.take<unsigned>((size_t)rows_cap);
+  s.cand2 = ar.take<uint64_t>((size_t)rows_cap * (S / GS) * s.C);
+  s.cnt2 = ar.take<int>((size_t)rows_cap * (S / GS));
+  s.thr2 = ar.take<float>((size_t)rows_cap * (S / GS));
   s.fb_list = ar.take<int>((size_t)rows_cap + 1);
   s.fb_count = ar.take<int>(64);
   s.fb_scr = ar.take<uint64_t>((size_t)s.fb_grid * std::max<int64_t>(ncols, 1));
@@ -88,9 +100,23 @@ void serve_knn(const Operand& op, const float* maxn2, const float* X, int d, con
   sa.eps_s = eps_accumulation(op.prec, d); sa.eps_n = eps_norm(d);
   sa.cand = s.cand; sa.cnt = s.cnt; sa.thr = s.thr; sa.thr_init = nullptr;
   sa.filt = filt;
+  fill_u32(s.thr_shared, 0xffffffffu, b, st);
+  sa.thr_shared = s.thr_shared;
   launch_sim_topk(op.prec, 1, sa, st);
+  const uint64_t* cand = s.cand;
+  const int* cnt = s.cnt;
+  const float* thr = s.thr;
+  if (s.GS > 1) {
+    MergeArgs m;
+    m.cand = s.cand; m.cnt = s.cnt; m.thr = s.thr;
+    m.rows = b; m.r0 = r0; m.NL = 1; m.S = s.S; m.GS = s.GS; m.C = s.C; m.k0 = k; m.k1 = 0;
+    m.n2 = op.n2; m.rn = op.rn; m.maxn2 = maxn2; m.eps_s = sa.eps_s; m.eps_n = sa.eps_n;
+    m.out_cand = s.cand2; m.out_cnt = s.cnt2; m.out_thr = s.thr2;
+    launch_merge_splits(m, st);
+    cand = s.cand2; cnt = s.cnt2; thr = s.thr2;
+  }
   RefineArgs ra;
-  ra.cand = s.cand; ra.cnt = s.cnt; ra.thr = s.thr; ra.S = s.S; ra.C = s.C; ra.NL = 1; ra.k0 = k; ra.k1 = 0;
+  ra.cand = cand; ra.cnt = cnt; ra.thr = thr; ra.S = s.S / s.GS; ra.C = s.C; ra.NL = 1; ra.k0 = k; ra.k1 = 0;
   ra.r0 = r0; ra.r1 = r0 + b; ra.c0 = c0; ra.c1 = c1; ra.exclude_self = 0;
   ra.X = X; ra.d = d; ra.cam = nullptr; ra.n2 = op.n2; ra.rn = op.rn; ra.maxn2 = maxn2;
   ra.eps_s = sa.eps_s; ra.eps_n = sa.eps_n;

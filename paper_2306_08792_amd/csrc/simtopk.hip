@@ -348,6 +348,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     float pf_n2 = INFINITY, pf_sc = 1.0f;
     int pf_cam = 0;
     uint32_t pf_stamp = 0u;
+    uint32_t pf_sh = 0xffffffffu;  // shared threshold of (row, list) tid (ordered bits)
     for (int ch = 0; ch < kch; ++ch, ++g) {
       // chunk g has landed once at most the next chunk's loads are pending;
       // right after an epilogue (candidate stores, compaction loads) and at
@@ -372,6 +373,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
           if (PREC == GCR_PREC_FP8) pf_sc = a.scale[c];
           if (a.filt.stamp_of) pf_stamp = a.filt.stamp_of[c];
         }
+        if (a.thr_shared && tid < BM * NL && row0 + (tid % BM) < a.r1)
+          pf_sh = a.thr_shared[(rrel0 + tid % BM) * NL + tid / BM];
       }
       const uint8_t* S = smem + gs * STAGE;
       gs = gs + 1 == NSTAGE ? 0 : gs + 1;
@@ -382,6 +385,12 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     col_n2[tid] = (a.filt.stamp_of && pf_stamp == a.filt.stamp) ? INFINITY : pf_n2;
     col_cam[tid] = pf_cam;
     col_sc[tid] = pf_sc;
+    // adopt the row's threshold published by the other splits of the row
+    // (every split's k-th key + 2E bounds the row's k-th key + 2E from above)
+    if (a.thr_shared && tid < BM * NL && pf_sh != 0xffffffffu) {
+      float& t = row_thr[tid / BM][tid % BM];
+      t = fminf(t, unord_f32(pf_sh));
+    }
     __syncthreads();
 
     // The lane's first tile column, hidden from the optimiser once per tile
@@ -471,6 +480,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         if (row_cnt[L][lr] >= a.C) {
           uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
           compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
+          if (a.thr_shared && lane == 0)
+            atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
         }
       }
       __syncthreads();
@@ -499,6 +510,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         if (kk > 0 && row_cnt[L][lr] >= kk) {
           uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
           compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, kk, row_twoE[lr]);
+          if (a.thr_shared && lane == 0)
+            atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
         }
       }
       __syncthreads();
