@@ -75,7 +75,8 @@ typedef struct {
   int32_t normalize_input;    /* 1: L2-normalise input rows first              */
   int32_t precision;          /* gcr_precision of the similarity screening     */
   int32_t topk_out;           /* K of gcr_rerank's per-query output list       */
-  int32_t symmetric;          /* 1: Eq. (7)+(2) (only mode supported)          */
+  int32_t symmetric;          /* 1: A = (A~ + A~^T)/2, Eq. (7) + (2); 0: the
+                                 asymmetric D_r^-1/2 A~ D_c^-1/2 of Eq. (6)     */
   float gamma;                /* temperature of Eq. (4), > 0                   */
   float alpha;                /* blend of Eq. (9) in [0, 1]; 1: global only    */
   float beta_same;            /* factor on global-graph edges, same camera     */
@@ -146,7 +147,7 @@ gcr_status gcr_knn(gcr_ctx* ctx, const float* X, int64_t n, int32_t d,
                    int32_t* idx, float* dist, int32_t* cr_idx, float* cr_dist,
                    void* stream);
 
-/* Sparse symmetric propagation graph (Eq. (4)-(9)), in caller memory.
+/* Sparse propagation graph (Eq. (4)-(9)), in caller memory.
  * For each of the global graph and (if has_cross) the cross-camera graph:
  *   idx [n,k] int32, dist [n,k] float32   forward kNN lists
  *   w   [n,k] float32   beta * exp(-dist / gamma)   (0 for padding)
@@ -157,12 +158,20 @@ gcr_status gcr_knn(gcr_ctx* ctx, const float* X, int64_t n, int32_t d,
  *   pf [n,k], pr [n*k] float32: normalised values c * w / (2 sqrt(D_i D_j))
  *       of the forward and reverse entries, with c = alpha for the global
  *       graph and 1 - alpha for the cross graph
+ *   Asymmetric graphs (built with p->symmetric = 0, Eq. (5), (6)): deg holds
+ *   the row degrees D_r(i) = 1 + sum of the forward w, pf = c * w /
+ *   sqrt(D_r(i) D_c(j)) with the column degrees D_c(j) = 1 + sum of the
+ *   reverse w, pr is unused and self = c / sqrt(D_r(i) D_c(i)) summed over
+ *   the graphs
  * and self[n] float32 = alpha / D_i + (1 - alpha) / D^cr_i (diagonal of the
  * blended operator).  gcr_graph_bytes gives the size of one device buffer
  * holding all of it; gcr_graph_bind carves that buffer into the fields. */
 typedef struct {
   int64_t n;
-  int32_t k, cross_k, has_cross, reserved;
+  int32_t k, cross_k, has_cross;
+  int32_t asymmetric; /* set by gcr_build_graph: 0 symmetric (Eq. (7)),
+                         1 asymmetric (Eq. (6)): deg holds the row degrees
+                         and the reverse lists are not propagated */
   int32_t *idx, *rev_ptr, *rev_src;
   float *dist, *w, *rev_w, *deg, *pf, *pr;
   int32_t *cr_idx, *cr_rev_ptr, *cr_rev_src;

@@ -55,7 +55,7 @@ class GcrTiming(C.Structure):
 class GcrGraph(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("k", C.c_int32), ("cross_k", C.c_int32), ("has_cross", C.c_int32),
-        ("reserved", C.c_int32),
+        ("asymmetric", C.c_int32),
         ("idx", _P), ("rev_ptr", _P), ("rev_src", _P),
         ("dist", _P), ("w", _P), ("rev_w", _P), ("deg", _P), ("pf", _P), ("pr", _P),
         ("cr_idx", _P), ("cr_rev_ptr", _P), ("cr_rev_src", _P),

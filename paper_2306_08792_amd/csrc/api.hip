@@ -289,7 +289,7 @@ gcr_status check_params(gcr_ctx* c, const gcr_params* p) {
   if (!(p->beta_same > 0.f && p->beta_cross > 0.f)) return fail(c, GCR_ERR_INVALID, "beta factors must be > 0");
   if (p->precision < 0 || p->precision > 2) return fail(c, GCR_ERR_INVALID, "unknown precision %d", p->precision);
   if (p->rounds < 0) return fail(c, GCR_ERR_INVALID, "rounds must be >= 0");
-  if (p->symmetric != 1) return fail(c, GCR_ERR_UNSUPPORTED, "only the symmetric normalisation is built");
+  if (p->symmetric != 0 && p->symmetric != 1) return fail(c, GCR_ERR_INVALID, "symmetric must be 0 or 1");
   return GCR_OK;
 }
 
@@ -339,6 +339,8 @@ void plan_graph_tmp(Arena& ar, GraphTmp& t, int64_t n) {
   t.blk = ar.take<int32_t>((size_t)(n / 1024 + 2));
   t.label = ar.take<int32_t>((size_t)n);
   t.order = ar.take<int32_t>((size_t)n);
+  t.dc = ar.take<float>((size_t)n);
+  t.dc_cr = ar.take<float>((size_t)n);
 }
 
 void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const gcr_params* p, float coef,
@@ -361,6 +363,8 @@ void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const 
   a.pr = cross ? g->cr_pr : g->pr;
   a.coef = coef;
   a.tmp_cnt = t.cnt; a.tmp_fsum = t.fsum; a.tmp_blk = t.blk;
+  a.asym = p->symmetric ? 0 : 1;
+  a.deg_c = cross ? t.dc_cr : t.dc;
   if (!finish) launch_graph_build(a, st);
   else launch_finish_values(a, st);
 }
@@ -383,7 +387,10 @@ void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, cons
   if (cross) build_one(g, true, n, cam, p, 1.0f - alpha, gt, st, false);
   build_one(g, false, n, cam, p, alpha, gt, st, true);
   if (cross) build_one(g, true, n, cam, p, 1.0f - alpha, gt, st, true);
-  launch_self_coef(n, g->deg, cross ? g->cr_deg : nullptr, alpha, g->self, st);
+  const bool asym = p->symmetric == 0;
+  launch_self_coef(n, g->deg, asym ? gt.dc : nullptr, cross ? g->cr_deg : nullptr, asym && cross ? gt.dc_cr : nullptr,
+                   alpha, g->self, st);
+  const_cast<gcr_graph*>(g)->asymmetric = asym ? 1 : 0;
   if (g->k > 0) launch_locality_order(n, g->idx, g->k, gt.label, gt.cnt, gt.blk, gt.order, st);
 }
 
@@ -394,9 +401,11 @@ void enqueue_propagate(gcr_ctx* c, const gcr_graph* g, const float* Xin, float* 
   a.X = Xin; a.Y = Xout; a.n = n; a.d = d; a.self = g->self;
   a.order = g->k > 0 ? order : nullptr;
   a.idx = g->idx; a.pf = g->pf; a.k = g->k; a.rev_ptr = g->rev_ptr; a.rev_src = g->rev_src; a.pr = g->pr;
+  if (g->asymmetric) a.rev_ptr = nullptr;  // Eq. (6): forward lists only
   if (g->has_cross) {
     a.cr_idx = g->cr_idx; a.cr_pf = g->cr_pf; a.ck = g->cross_k; a.cr_rev_ptr = g->cr_rev_ptr;
     a.cr_rev_src = g->cr_rev_src; a.cr_pr = g->cr_pr;
+    if (g->asymmetric) a.cr_rev_ptr = nullptr;
   } else {
     a.cr_idx = nullptr; a.cr_pf = nullptr; a.ck = 0; a.cr_rev_ptr = nullptr; a.cr_rev_src = nullptr;
     a.cr_pr = nullptr;

@@ -6,6 +6,8 @@
 //   w_ji / 2); a mutual pair simply appears in both, which sums to A_ij.
 //   D_i = 1 + sum_fwd w/2 + sum_rev w/2                              (Eq. (5), (7))
 //   P_ij = A_ij / sqrt(D_i D_j), P_ii = 1 / D_i                       (Eq. (2))
+// Asymmetric variant (Eq. (5), (6)): D_r(i) = 1 + sum_fwd w, D_c(j) = 1 +
+// sum_rev w, P = D_r^-1/2 A~ D_c^-1/2 with the forward lists only.
 // The reverse lists are a CSR built by a count / exclusive scan / scatter,
 // then each row is sorted by source so that sums run in a fixed order.
 #include "kernels.h"
@@ -113,13 +115,26 @@ __global__ void rev_sort_degree_kernel(GraphBuildArgs a) {
   }
   float rs = 0.f;
   for (int p = b; p < e; ++p) rs += a.rev_w[p];
-  a.deg[i] = 1.0f + 0.5f * a.tmp_fsum[i] + 0.5f * rs;
+  if (a.asym) {
+    a.deg[i] = 1.0f + a.tmp_fsum[i];  // row degree D_r
+    a.deg_c[i] = 1.0f + rs;           // column degree D_c
+  } else {
+    a.deg[i] = 1.0f + 0.5f * a.tmp_fsum[i] + 0.5f * rs;
+  }
 }
 
 __global__ void values_kernel(GraphBuildArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const float di = a.deg[i];
+  if (a.asym) {
+    for (int s = 0; s < a.k; ++s) {
+      const int64_t e = i * a.k + s;
+      const int j = a.idx[e];
+      a.pf[e] = j >= 0 ? a.coef * a.w[e] / sqrtf(di * a.deg_c[j]) : 0.f;
+    }
+    return;  // no reverse terms
+  }
   for (int s = 0; s < a.k; ++s) {
     const int64_t e = i * a.k + s;
     const int j = a.idx[e];
@@ -129,11 +144,13 @@ __global__ void values_kernel(GraphBuildArgs a) {
   for (int p = b; p < en; ++p) a.pr[p] = a.coef * 0.5f * a.rev_w[p] / sqrtf(di * a.deg[a.rev_src[p]]);
 }
 
-__global__ void self_kernel(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self) {
+// deg_c / cr_deg_c: column degrees of asymmetric graphs (nullptr: symmetric)
+__global__ void self_kernel(int64_t n, const float* deg, const float* deg_c, const float* cr_deg,
+                            const float* cr_deg_c, float alpha, float* self) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float s = alpha / deg[i];
-  if (cr_deg) s += (1.0f - alpha) / cr_deg[i];
+  float s = deg_c ? alpha / sqrtf(deg[i] * deg_c[i]) : alpha / deg[i];
+  if (cr_deg) s += cr_deg_c ? (1.0f - alpha) / sqrtf(cr_deg[i] * cr_deg_c[i]) : (1.0f - alpha) / cr_deg[i];
   self[i] = s;
 }
 
@@ -157,9 +174,10 @@ void launch_finish_values(const GraphBuildArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(values_kernel, dim3(nblk(a.n, 256)), dim3(256), 0, st, a);
 }
 
-void launch_self_coef(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(self_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, deg, cr_deg, alpha, self);
+void launch_self_coef(int64_t n, const float* deg, const float* deg_c, const float* cr_deg, const float* cr_deg_c,
+                      float alpha, float* self, hipStream_t st) {
+  hipLaunchKernelGGL(self_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, n, deg, deg_c, cr_deg, cr_deg_c, alpha,
+                     self);
 }
 
 __global__ void label_count_kernel(int64_t n, const int32_t* __restrict__ idx, int k, int32_t* __restrict__ label,

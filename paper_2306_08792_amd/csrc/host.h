@@ -63,6 +63,7 @@ struct KnnPlan {
 struct GraphTmp {
   int32_t* cnt; float* fsum; int32_t* blk;
   int32_t* label; int32_t* order;  // locality order of the last graph built
+  float* dc; float* dc_cr;         // column degrees of asymmetric graphs
 };
 
 gcr_status fail(gcr_ctx* c, gcr_status s, const char* fmt, ...);

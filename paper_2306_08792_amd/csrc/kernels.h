@@ -141,10 +141,12 @@ struct GraphBuildArgs {
   int32_t* tmp_cnt;    // [n]
   float* tmp_fsum;     // [n]
   int32_t* tmp_blk;    // scan block sums
+  int asym = 0;        // asymmetric normalisation: deg = row degrees, deg_c = column degrees
+  float* deg_c = nullptr;
 };
 void launch_graph_build(const GraphBuildArgs& a, hipStream_t st);
-void launch_self_coef(int64_t n, const float* deg, const float* cr_deg, float alpha, float* self,
-                      hipStream_t st);
+void launch_self_coef(int64_t n, const float* deg, const float* deg_c, const float* cr_deg, const float* cr_deg_c,
+                      float alpha, float* self, hipStream_t st);
 void launch_finish_values(const GraphBuildArgs& a, hipStream_t st);
 // Row processing order that keeps rows sharing neighbours together: rows
 // sorted (counting sort) by the smallest index among themselves and their

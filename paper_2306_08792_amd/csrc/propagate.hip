@@ -73,14 +73,16 @@ __global__ __launch_bounds__(256) void propagate_vec_kernel(PropArgs a) {
     }
   }
   gather_list<V>(acc, a.X, d, a.idx + i * a.k, a.pf + i * a.k, a.k, lane);
-  {
+  if (a.rev_ptr) {
     const int b = a.rev_ptr[i], e = a.rev_ptr[i + 1];
     gather_list<V>(acc, a.X, d, a.rev_src + b, a.pr + b, e - b, lane);
   }
   if (a.cr_idx) {
     gather_list<V>(acc, a.X, d, a.cr_idx + i * a.ck, a.cr_pf + i * a.ck, a.ck, lane);
-    const int b = a.cr_rev_ptr[i], e = a.cr_rev_ptr[i + 1];
-    gather_list<V>(acc, a.X, d, a.cr_rev_src + b, a.cr_pr + b, e - b, lane);
+    if (a.cr_rev_ptr) {
+      const int b = a.cr_rev_ptr[i], e = a.cr_rev_ptr[i + 1];
+      gather_list<V>(acc, a.X, d, a.cr_rev_src + b, a.cr_pr + b, e - b, lane);
+    }
   }
   float ss = 0.f;
 #pragma unroll
@@ -131,14 +133,16 @@ __global__ __launch_bounds__(256) void propagate_scalar_kernel(PropArgs a) {
     acc[t] = e < d ? s * a.X[i * d + e] : 0.f;
   }
   gather_scalar(acc, a.X, d, a.idx + i * a.k, a.pf + i * a.k, a.k, lane);
-  {
+  if (a.rev_ptr) {
     const int b = a.rev_ptr[i], e = a.rev_ptr[i + 1];
     gather_scalar(acc, a.X, d, a.rev_src + b, a.pr + b, e - b, lane);
   }
   if (a.cr_idx) {
     gather_scalar(acc, a.X, d, a.cr_idx + i * a.ck, a.cr_pf + i * a.ck, a.ck, lane);
-    const int b = a.cr_rev_ptr[i], e = a.cr_rev_ptr[i + 1];
-    gather_scalar(acc, a.X, d, a.cr_rev_src + b, a.cr_pr + b, e - b, lane);
+    if (a.cr_rev_ptr) {
+      const int b = a.cr_rev_ptr[i], e = a.cr_rev_ptr[i + 1];
+      gather_scalar(acc, a.X, d, a.cr_rev_src + b, a.cr_pr + b, e - b, lane);
+    }
   }
   float ss = 0.f;
 #pragma unroll

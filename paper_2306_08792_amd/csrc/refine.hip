@@ -175,7 +175,8 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
 // 128, else the pair goes to the block kernel) are re-scored exactly two at
 // a time with the row held in registers, and a wave bitonic sort by
 // (distance, index) orders them.
-constexpr int WR_MAX = 128;  // re-scored candidates handled by one wave
+constexpr int WR_MAX = 256;  // re-scored candidates handled by one wave
+constexpr int WR_EX = WR_MAX / 64;
 
 __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -248,24 +249,32 @@ __device__ __forceinline__ void wave_exact_sqdist2_vec(const f32x4 (&xr4)[V], co
   kb = ((uint64_t)ord_f32(hb) << 32) | (uint64_t)ord_f32(lb);
 }
 
-// ascending bitonic sort of 128 (key, index) pairs, two per lane
+// ascending bitonic sort of 64 EX (key, index) pairs, EX per lane
 // (element j * 64 + lane in k[j], c[j]), by key then index
-__device__ __forceinline__ void wave_sort_pairs2(uint64_t (&k)[2], uint32_t (&c)[2]) {
+template <int EX>
+__device__ __forceinline__ void wave_sort_pairs(uint64_t (&k)[EX], uint32_t (&c)[EX]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int size = 2; size <= 128; size <<= 1) {
+  for (int size = 2; size <= 64 * EX; size <<= 1) {
 #pragma unroll
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (stride == 64) {
-        const bool asc = (lane & size) == 0;  // element lane vs lane + 64
-        const bool gt = k[0] > k[1] || (k[0] == k[1] && c[0] > c[1]);
-        if (gt == asc) {
-          const uint64_t tk = k[0]; k[0] = k[1]; k[1] = tk;
-          const uint32_t tc = c[0]; c[0] = c[1]; c[1] = tc;
+      if (stride >= 64) {
+        const int rs = stride >> 6;
+#pragma unroll
+        for (int j = 0; j < EX; ++j) {
+          if ((j & rs) == 0) {
+            const int e = j * 64 + lane;
+            const bool asc = (e & size) == 0;
+            const bool gt = k[j] > k[j | rs] || (k[j] == k[j | rs] && c[j] > c[j | rs]);
+            if (gt == asc) {
+              const uint64_t tk = k[j]; k[j] = k[j | rs]; k[j | rs] = tk;
+              const uint32_t tc = c[j]; c[j] = c[j | rs]; c[j | rs] = tc;
+            }
+          }
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < EX; ++j) {
           const int e = j * 64 + lane;
           const bool asc = (e & size) == 0;
           const bool lower = (lane & stride) == 0;
@@ -382,8 +391,10 @@ __global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
       xr[t] = e < a.d ? xrow[e] : 0.f;
     }
   }
-  uint64_t ek[2] = {GCR_EMPTY, GCR_EMPTY};
-  uint32_t ec[2] = {0xffffffffu, 0xffffffffu};
+  uint64_t ek[WR_EX];
+  uint32_t ec[WR_EX];
+#pragma unroll
+  for (int j = 0; j < WR_EX; ++j) { ek[j] = GCR_EMPTY; ec[j] = 0xffffffffu; }
   for (int m = 0; m < M; m += 2) {
     const uint32_t ca = Mc[m];
     const uint32_t cb = m + 1 < M ? Mc[m + 1] : ca;
@@ -392,16 +403,28 @@ __global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
     const float* pb = a.X + (a.c0 + (int64_t)cb) * a.d;
     if constexpr (V > 0) wave_exact_sqdist2_vec<V>(xr4, pa, pb, ka, kb);
     else wave_exact_sqdist2_reg(xr, pa, pb, a.d, ka, kb);
-    if ((m & 63) == lane) {
-      if (m < 64) { ek[0] = ka; ec[0] = ca; } else { ek[1] = ka; ec[1] = ca; }
-    }
-    if (m + 1 < M && ((m + 1) & 63) == lane) {
-      if (m + 1 < 64) { ek[0] = kb; ec[0] = cb; } else { ek[1] = kb; ec[1] = cb; }
+#pragma unroll
+    for (int j = 0; j < WR_EX; ++j) {
+      if ((m >> 6) == j && (m & 63) == lane) { ek[j] = ka; ec[j] = ca; }
+      if (m + 1 < M && ((m + 1) >> 6) == j && ((m + 1) & 63) == lane) { ek[j] = kb; ec[j] = cb; }
     }
   }
-  wave_sort_pairs2(ek, ec);
+  // sort only as many slots as there are candidates
+  if (M <= 64) {
+    uint64_t k1[1] = {ek[0]};
+    uint32_t c1[1] = {ec[0]};
+    wave_sort_pairs<1>(k1, c1);
+    ek[0] = k1[0]; ec[0] = c1[0];
+  } else if (M <= 128) {
+    uint64_t k2[2] = {ek[0], ek[1]};
+    uint32_t c2[2] = {ec[0], ec[1]};
+    wave_sort_pairs<2>(k2, c2);
+    ek[0] = k2[0]; ek[1] = k2[1]; ec[0] = c2[0]; ec[1] = c2[1];
+  } else {
+    wave_sort_pairs<WR_EX>(ek, ec);
+  }
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < WR_EX; ++j) {
     const int t = j * 64 + lane;
     if (t < kk) {
       if (t < M) {
@@ -853,6 +876,7 @@ __global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
 // C items, only the keys below the (C+1)-th smallest, lowering the cut; the
 // merged threshold is the cut.  The exactness argument of the refine is
 // unchanged: a merged buffer is a split buffer with a recorded threshold.
+template <int NK>  // keys per lane: GS * C / 64
 __global__ __launch_bounds__(256) void merge_splits_kernel(MergeArgs m) {
   extern __shared__ uint64_t msm[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -890,10 +914,17 @@ __global__ __launch_bounds__(256) void merge_splits_kernel(MergeArgs m) {
     for (int t = lane; t < cs; t += 64) U[os + t] = src[(int64_t)s * C + t];
   }
   wave_lds_sync();
+  uint32_t key[NK];
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const int e = j * 64 + lane;
+    key[j] = e < T ? (uint32_t)(U[e] >> 32) : 0xffffffffu;
+  }
   auto count_le = [&](uint32_t u) {
     int n = 0;
-    for (int e = lane; e < T; e += 64) n += (uint32_t)(U[e] >> 32) <= u ? 1 : 0;
-    return wave_sum_i(n);
+#pragma unroll
+    for (int j = 0; j < NK; ++j) n += __popcll(__ballot(key[j] <= u));
+    return n;
   };
   auto select = [&](int r) {  // smallest ordered key with at least r keys <= it
     uint32_t lo = 0u, hi = 0xfffffffeu;
@@ -934,8 +965,17 @@ void launch_merge_splits(const MergeArgs& m, hipStream_t st) {
   const int64_t items = m.rows * m.NL * (m.S / m.GS);
   if (items <= 0) return;
   const size_t lds = (size_t)4 * m.GS * m.C * sizeof(uint64_t);
-  (void)hipFuncSetAttribute((const void*)merge_splits_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(merge_splits_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), lds, st, m);
+  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+  auto go = [&](auto k) {
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, block, lds, st, m);
+  };
+  const int nk = (m.GS * m.C + 63) / 64;
+  if (nk <= 2) go(merge_splits_kernel<2>);
+  else if (nk <= 4) go(merge_splits_kernel<4>);
+  else if (nk <= 8) go(merge_splits_kernel<8>);
+  else if (nk <= 16) go(merge_splits_kernel<16>);
+  else go(merge_splits_kernel<32>);
 }
 
 // One wave per (row, list).  If the previous list of the row has k valid
@@ -1042,11 +1082,14 @@ void launch_refine(const RefineArgs& a, hipStream_t st) {
     else if (vec && a.d == 256) go(refine_wave_kernel<1>);
     else go(refine_wave_kernel<0>);
   }
-  hipLaunchKernelGGL(refine_kernel, dim3(1024), dim3(RT), 0, st, a);
-  hipLaunchKernelGGL(band_sweep_kernel, dim3(2048), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(band_select_kernel, dim3(1024), dim3(RT), 0, st, a);
-  hipLaunchKernelGGL(fallback_scan_kernel, dim3(2048), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(fallback_merge_kernel, dim3(1024), dim3(256), 0, st, a);
+  // the follow-up kernels find their work counts on the device and are
+  // usually empty: grids of about one workgroup per compute unit keep the
+  // empty launches cheap and still fill the GPU when there is work
+  hipLaunchKernelGGL(refine_kernel, dim3(256), dim3(RT), 0, st, a);
+  hipLaunchKernelGGL(band_sweep_kernel, dim3(512), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(band_select_kernel, dim3(256), dim3(RT), 0, st, a);
+  hipLaunchKernelGGL(fallback_scan_kernel, dim3(512), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(fallback_merge_kernel, dim3(256), dim3(256), 0, st, a);
   hipLaunchKernelGGL(fallback_kernel, dim3(a.fb_grid), dim3(FBT), 0, st, a);
 }
 

@@ -450,6 +450,7 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_
   if (p->topk_out < 1 || p->topk_out > 120) return fail(ctx, GCR_ERR_UNSUPPORTED, "top-K output must be in 1..120");
   if (p->rebuild_each_round) return fail(ctx, GCR_ERR_INVALID, "serving keeps the gallery graph fixed "
                                                                "(rebuild_each_round must be 0)");
+  if (p->symmetric != 1) return fail(ctx, GCR_ERR_UNSUPPORTED, "serving uses the symmetric normalisation");
   gcr_server_config c;
   gcr_server_config_default(&c);
   if (cfg) c = *cfg;

@@ -45,6 +45,7 @@ class Params:
     beta_same: float = 1.0
     beta_cross: float = 1.0
     lam: float = 10.0
+    symmetric: bool = True
 
     def c(self) -> L.GcrParams:
         p = L.GcrParams()
@@ -53,7 +54,7 @@ class Params:
         p.normalize_input = int(self.normalize_input)
         p.precision = int(self.precision)
         p.topk_out = self.topk_out
-        p.symmetric = 1
+        p.symmetric = int(self.symmetric)
         p.gamma, p.alpha = self.gamma, self.alpha
         p.beta_same, p.beta_cross, p.lambda_ = self.beta_same, self.beta_cross, self.lam
         return p

@@ -459,3 +459,20 @@ def test_plain_gcr_small_map():
     before = mean_average_precision(O.final_distances(out["X"][0], w.nq), qid, gid)
     after = mean_average_precision(O.final_distances(out["X"][-1], w.nq), qid, gid)
     assert before >= 0.99 and after >= 0.99
+
+
+def test_asymmetric_closed_form_two_nodes():
+    # Eq. (5)-(6) by hand: A~ = [[1, a], [0, 1]] (node 1 is node 0's only
+    # neighbour, not the reverse): D_r = (1 + a, 1), D_c = (1, 1 + a), so
+    # P = [[1/sqrt(1+a), a/(1+a)], [0, 1/sqrt(1+a)]]
+    a = math.exp(-0.3 / 0.2)
+    At = np.array([[1.0, a], [0.0, 1.0]])
+    P, Dr, Dc = O.asym_propagation_matrix(At)
+    np.testing.assert_allclose(Dr, [1 + a, 1.0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Dc, [1.0, 1 + a], rtol=0, atol=1e-15)
+    s = 1.0 / math.sqrt(1 + a)
+    np.testing.assert_allclose(P, [[s, a / (1 + a)], [0.0, s]], rtol=0, atol=1e-15)
+    # the symmetric form of the same pair averages the edge: A_01 = a / 2
+    Ps, As, Ds = O.sym_propagation_matrix(At)
+    np.testing.assert_allclose(As, [[1.0, a / 2], [a / 2, 1.0]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Ps[0, 1], (a / 2) / (1 + a / 2), rtol=1e-15)
