@@ -24,6 +24,8 @@ Retrieval, Sec. III):
   * Sec. III-C text: the neighbour graphs change between iterations, so the
     graph is rebuilt from the current features before every round
   * Eq. (10) mean tracklet profile; Eq. (16) profile vector closed form
+  * Alg. 1   DSFP ("GCR_Local"): per node, a dense local affinity over the
+             node and its k neighbours, local degrees, T local rounds
   * Alg. 2   GCRV: profile vectors, then T rounds on the profile vectors
   * Sec. IV-E (efficiency analysis): gallery graphs may be computed in
     advance (used by the serving reading)
@@ -42,7 +44,14 @@ listed with its reason in the design notes):
     graph's off-diagonal weights (1.0 unless asked otherwise);
   * Eq. (16) is used as printed with X^T X (d x d, the covariance the text
     names) in place of the garbled X X^T, per camera group;
-  * final ranking distances are squared Euclidean on X_T only.
+  * final ranking distances are squared Euclidean on X_T only;
+  * DSFP (Alg. 1): the local degree is the row sum of A^i for every member
+    of the local set (the printed degree names only node i's own entry);
+    A^i covers all pairs of the local set with 1 on its diagonal; the local
+    rounds run t = 1..T and each ends with the same row re-normalisation as
+    a global round; node i's row of the local X_T is its output; the kNN
+    lists come once from the (normalised) input features and are not
+    rebuilt; cameras and the blend of Eq. (9) do not apply.
 """
 from __future__ import annotations
 
@@ -69,6 +78,9 @@ __all__ = [
     "degrees_from_lists",
     "knn_rows",
     "serve_request",
+    "local_set",
+    "dsfp",
+    "gcr_local",
 ]
 
 NORM_FLOOR = 1e-12
@@ -437,3 +449,59 @@ def serve_request(XG0: np.ndarray, g_idx: np.ndarray, g_dist: np.ndarray,
     dfin = np.maximum(np.sum(Xq * Xq, 1)[:, None] + np.sum(Xg * Xg, 1)[None, :] - 2.0 * (Xq @ Xg.T), 0.0)
     order = np.argsort(dfin, axis=1, kind="stable")[:, :topk]
     return order, np.take_along_axis(dfin, order, axis=1)
+
+
+# ----------------------------------------------------------------------------
+# Alg. 1: decentralised and synchronous feature propagation (DSFP, GCR_Local)
+
+
+def local_set(i: int, idx_row) -> list:
+    """The local node set N_i plus i itself (Alg. 1, first two steps), node i
+    first and then the listed neighbours in list order.  Padding (-1), i
+    itself and repeated entries add nothing: the set is a set."""
+    nodes = [int(i)]
+    for j in np.asarray(idx_row).tolist():
+        if j >= 0 and j not in nodes:
+            nodes.append(int(j))
+    return nodes
+
+
+def dsfp_node(X: np.ndarray, nodes: list, gamma: float, rounds: int) -> np.ndarray:
+    """Alg. 1 for one node (nodes[0]): local affinity A over every pair of the
+    local set (exp(-||x_u - x_v||^2 / gamma), 1 on the diagonal), local
+    degrees D = row sums of A, then T rounds X <- D^-1/2 A D^-1/2 X, each
+    followed by the row re-normalisation of a global round.  Returns the
+    node's own row of the local X_T."""
+    Xl = np.asarray(X, dtype=np.float64)[nodes]
+    A = np.exp(-sq_dists(Xl) / gamma)
+    deg = A.sum(axis=1)
+    P = A / np.sqrt(deg)[:, None] / np.sqrt(deg)[None, :]
+    for _ in range(rounds):
+        Xl = row_normalize(P @ Xl)
+    return Xl[0]
+
+
+def dsfp(X0: np.ndarray, p: Params, idx: Optional[np.ndarray] = None) -> np.ndarray:
+    """DSFP over all nodes (Alg. 1).  X0: input features (normalised first if
+    p.normalize_input).  idx: neighbour lists [n, k] (-1 padding allowed);
+    default: the exact k nearest other rows of the normalised input.
+    Every node is updated from the input features only (the rounds are
+    local and synchronous), so nodes are independent."""
+    X = np.asarray(X0, dtype=np.float64)
+    if p.normalize_input:
+        X = row_normalize(X)
+    n = X.shape[0]
+    if idx is None:
+        idx, _ = knn_lists(sq_dists(X), p.k)
+    out = np.empty_like(X)
+    for i in range(n):
+        out[i] = dsfp_node(X, local_set(i, idx[i]), p.gamma, p.rounds)
+    return out
+
+
+def gcr_local(X0: np.ndarray, nq: int, p: Params, idx: Optional[np.ndarray] = None):
+    """GCR_Local re-ranking: DSFP features, then the squared distances between
+    the first nq rows (queries) and the rest (gallery).  Returns (dist
+    [nq, ng], X_T)."""
+    XT = dsfp(X0, p, idx)
+    return final_distances(XT, nq), XT

@@ -476,3 +476,97 @@ def test_asymmetric_closed_form_two_nodes():
     Ps, As, Ds = O.sym_propagation_matrix(At)
     np.testing.assert_allclose(As, [[1.0, a / 2], [a / 2, 1.0]], rtol=0, atol=1e-15)
     np.testing.assert_allclose(Ps[0, 1], (a / 2) / (1 + a / 2), rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# DSFP (Alg. 1): closed forms, special cases and locality
+
+
+def test_dsfp_three_nodes_closed_form():
+    """x0 = (1,0), x1 = (0,1), x2 = (-1,0), gamma = 1, k = 2: the local set of
+    every node is all three.  Squared distances 2, 4, 2, so A has a = e^-2
+    next to the diagonal and b = e^-4 in the corners; degrees s0 = s2 =
+    1 + a + b, s1 = 1 + 2a.  By hand, with P_uv = A_uv / sqrt(s_u s_v):
+      round 1: y0 = ((1-b)/s0, a/sqrt(s0 s1)), y1 = (0, 1/s1),
+               y2 = (-(1-b)/s0, a/sqrt(s0 s1)); rows re-normalised;
+      round 2: w0 = z0/s0 + a z1/sqrt(s0 s1) + b z2/s0, re-normalised.
+    The degree of every member (not only node i's) and the per-round
+    re-normalisation both change these numbers."""
+    X = np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])
+    idx = np.array([[1, 2], [0, 2], [1, 0]])
+    a, b = E(-2.0), E(-4.0)
+    s0, s1 = 1 + a + b, 1 + 2 * a
+    y0 = np.array([(1 - b) / s0, a / math.sqrt(s0 * s1)])
+    y2 = np.array([-(1 - b) / s0, a / math.sqrt(s0 * s1)])
+    z0, z1, z2 = y0 / np.linalg.norm(y0), np.array([0.0, 1.0]), y2 / np.linalg.norm(y2)
+    w0 = z0 / s0 + a * z1 / math.sqrt(s0 * s1) + b * z2 / s0
+    p1 = O.Params(k=2, gamma=1.0, rounds=1)
+    np.testing.assert_allclose(O.dsfp(X, p1, idx)[0], y0 / np.linalg.norm(y0), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(O.dsfp(X, p1, idx)[1], [0.0, 1.0], rtol=0, atol=1e-14)
+    p2 = O.Params(k=2, gamma=1.0, rounds=2)
+    np.testing.assert_allclose(O.dsfp(X, p2, idx)[0], w0 / np.linalg.norm(w0), rtol=0, atol=1e-14)
+
+
+def test_dsfp_two_nodes_closed_form():
+    """Two orthogonal unit vectors, gamma = 1, w = e^-2: after T rounds node
+    0's direction is that of (1, w) for T = 1 and (1 + w^2, 2w) for T = 2."""
+    X = np.array([[1.0, 0.0], [0.0, 1.0]])
+    w = E(-2.0)
+    for T, v in ((1, (1.0, w)), (2, (1.0 + w * w, 2.0 * w))):
+        got = O.dsfp(X, O.Params(k=1, gamma=1.0, rounds=T))
+        v = np.array(v) / math.hypot(*v)
+        np.testing.assert_allclose(got[0], v, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(got[1], v[::-1], rtol=0, atol=1e-14)
+
+
+def test_dsfp_flat_affinity_gives_local_mean():
+    """gamma -> infinity makes A all ones: for any T >= 1 node i becomes the
+    normalised mean of its local set (i and its listed neighbours), for any
+    lists, including -1 padding and repeats."""
+    rng = np.random.default_rng(21)
+    n, d, k = 14, 6, 4
+    X = O.row_normalize(rng.standard_normal((n, d)))
+    idx = np.array([rng.choice(np.delete(np.arange(n), i), size=k, replace=False) for i in range(n)])
+    idx[3, 1] = -1
+    idx[5, 2] = idx[5, 0]
+    for T in (1, 3):
+        got = O.dsfp(X, O.Params(k=k, gamma=1e13, rounds=T), idx)
+        for i in range(n):
+            nodes = {i} | {int(j) for j in idx[i] if j >= 0}
+            m = X[sorted(nodes)].mean(axis=0)
+            np.testing.assert_allclose(got[i], m / np.linalg.norm(m), rtol=0, atol=1e-9)
+
+
+def test_dsfp_zero_rounds_is_identity():
+    rng = np.random.default_rng(22)
+    X = rng.standard_normal((7, 5))
+    got = O.dsfp(X, O.Params(k=3, rounds=0))
+    np.testing.assert_allclose(got, X / np.linalg.norm(X, axis=1, keepdims=True), rtol=0, atol=1e-15)
+
+
+def test_dsfp_complete_graph_equals_global():
+    """k = N - 1: every local set is the whole node set and A^i is the global
+    affinity of the complete graph, so DSFP equals global GCR with the graph
+    built once (alpha = 1)."""
+    rng = np.random.default_rng(23)
+    n, d = 9, 4
+    X = rng.standard_normal((n, d))
+    for T in (1, 3):
+        got = O.dsfp(X, O.Params(k=n - 1, gamma=0.7, rounds=T))
+        ref = O.gcr(X, O.Params(k=n - 1, gamma=0.7, rounds=T, rebuild_each_round=False))["X"][-1]
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+
+
+def test_dsfp_node_depends_on_its_local_set_only():
+    """Node i's output is node i's row of global GCR run on the local set
+    alone as a complete graph (the local rounds never look outside it)."""
+    rng = np.random.default_rng(24)
+    n, d, k = 30, 8, 5
+    X = O.row_normalize(rng.standard_normal((n, d)))
+    p = O.Params(k=k, gamma=0.5, rounds=2)
+    got = O.dsfp(X, p)
+    idx, _ = O.knn_lists(O.sq_dists(X), k)
+    for i in range(n):
+        sub = X[[i] + [int(j) for j in idx[i]]]
+        ref = O.gcr(sub, O.Params(k=k, gamma=0.5, rounds=2, rebuild_each_round=False))["X"][-1][0]
+        np.testing.assert_allclose(got[i], ref, rtol=0, atol=1e-12)
