@@ -19,6 +19,11 @@
  *                       (Sec. III-C) or fixed, then final distances
  *   gcr_profile_vectors tracklet profile vectors for video (Eq. (10), (16);
  *                       Alg. 2 step 1)
+ *   gcr_dsfp            decentralised synchronous feature propagation
+ *                       (DSFP, Alg. 1): every node propagates on its own
+ *                       local neighbourhood graph
+ *   gcr_rerank_local    the GCR_Local pipeline: kNN once, DSFP, final
+ *                       distances
  *
  * Conventions
  *   Memory: every array argument is a DEVICE pointer owned by the caller,
@@ -116,7 +121,7 @@ gcr_status gcr_reset_stats(gcr_ctx* ctx);
  * around every launch of that class while timing is on (off by default).
  * Classes: 0 similarity + top-k screening, 1 exact refine (with the
  * exhaustive fallback), 2 graph build (weights, reverse lists, degrees,
- * normalised values), 3 propagation, 4 dense final distances, 5 input
+ * normalised values), 3 propagation (global rounds, or the DSFP kernel), 4 dense final distances, 5 input
  * preparation (normalisation and screening operands).
  * gcr_get_timing synchronises the device, returns the totals since the last
  * reset (milliseconds and launch counts) and resets them. */
@@ -221,6 +226,41 @@ gcr_status gcr_rerank(gcr_ctx* ctx, const float* X, int64_t nq, int64_t ng,
                       int32_t d, const int32_t* cam, const gcr_params* p,
                       float* dist_out, int32_t* topk_idx, float* topk_dist,
                       float* X_final, void* stream);
+
+/* Decentralised synchronous feature propagation, DSFP (Alg. 1).  For every
+ * node i independently: the local set L_i = {i} plus the entries of row i
+ * of idx; the local affinity A_uv = exp(-||x_u - x_v||^2 / gamma) over all
+ * pairs u, v of L_i (1 on the diagonal); the local degrees D_u = sum_v A_uv
+ * for every member u (Alg. 1 prints the degree of node i only; the
+ * normalisation needs every member's); then `rounds` local rounds
+ *   X_L <- rownorm(D^-1/2 A D^-1/2 X_L),  rownorm(y) = y / max(||y||, 1e-12),
+ * starting from the rows of X, as a global round does; Y[i] = node i's row
+ * of the local X_L after the last round.  Nodes never see each other's
+ * local updates (synchronous: every node starts from X).
+ *   X: float32 [n, d], used as given (no normalisation).
+ *   idx: int32 [n, k] neighbour lists (as gcr_knn writes them); entries < 0
+ *     or >= n, equal to i, or repeating an earlier entry of the row are
+ *     ignored; may be NULL when k = 0.
+ *   Y: float32 [n, d] out; must not overlap X.  rounds = 0 copies X to Y.
+ * Errors: INVALID (NULL or overlapping buffers, n < 1, d < 1, k < 0,
+ * rounds < 0, gamma not finite and > 0), UNSUPPORTED (k > 59: the local
+ * matrices must fit one workgroup's LDS; d > 2048), NOMEM, HIP. */
+gcr_status gcr_dsfp(gcr_ctx* ctx, const float* X, const int32_t* idx,
+                    int64_t n, int32_t d, int32_t k, float gamma,
+                    int32_t rounds, float* Y, void* stream);
+
+/* GCR_Local re-ranking (DSFP in place of the global rounds, Alg. 1) of
+ * X = [queries; gallery] (float32 [nq+ng, d]): normalise (if
+ * p->normalize_input), the p->k nearest neighbours of every row once (with
+ * p->precision screening; no camera lists), gcr_dsfp with p->gamma and
+ * p->rounds, then final distances as in gcr_final_distances.  X_final
+ * (float32 [nq+ng, d]) receives the DSFP features if not NULL.  p->alpha,
+ * cross_k, beta_*, rebuild_each_round and symmetric do not apply.
+ * Errors: INVALID, UNSUPPORTED (as gcr_dsfp; K above 120), NOMEM, HIP. */
+gcr_status gcr_rerank_local(gcr_ctx* ctx, const float* X, int64_t nq,
+                            int64_t ng, int32_t d, const gcr_params* p,
+                            float* dist_out, int32_t* topk_idx,
+                            float* topk_dist, float* X_final, void* stream);
 
 /* Tracklet profile vectors (video re-ID, Alg. 2 step 1).
  *   frames: float32 [nf, d]; offsets: int32 [nt+1] (frames of tracklet c are

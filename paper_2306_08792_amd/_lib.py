@@ -24,6 +24,7 @@ EXPORTS = [
     "gcr_profile_vectors", "gcr_set_timing", "gcr_get_timing",
     "gcr_server_config_default", "gcr_server_create", "gcr_server_submit", "gcr_server_wait",
     "gcr_server_get_stats", "gcr_server_last_error", "gcr_server_destroy",
+    "gcr_dsfp", "gcr_rerank_local",
 ]
 NUM_TIMERS = 6
 TIMER_NAMES = ["sim_topk", "refine", "graph", "propagate", "final_dense", "prep"]
@@ -123,6 +124,8 @@ def load(path: str = LIB_PATH):
     L.gcr_server_last_error.argtypes = [vp]
     L.gcr_server_last_error.restype = C.c_char_p
     L.gcr_server_destroy.argtypes = [vp]
+    L.gcr_dsfp.argtypes = [vp, vp, vp, i64, i32, i32, f32, i32, vp, vp]
+    L.gcr_rerank_local.argtypes = [vp, vp, i64, i64, i32, pP, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         fn = getattr(L, name)
         if fn.restype is C.c_int:  # default restype: gcr_status

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -713,6 +714,100 @@ gcr_status gcr_rerank(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_
   }
   run_final(c, fp, xa, nq, ng, d, p, dist_out, topk_idx, topk_dist, st);
   if (X_final) HIP_TRY(c, hipMemcpyAsync(X_final, xa, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+// DSFP (Alg. 1) over given neighbour lists.  The nodes are visited in the
+// locality order of their lists so that workgroups running together on one
+// XCD share most of the rows they gather.
+static hipError_t enqueue_dsfp(gcr_ctx* c, const GraphTmp& gt, const float* X, const int32_t* idx, int64_t n,
+                               int d, int k, float gamma, int rounds, float* Y, hipStream_t st) {
+  if (rounds == 0) return hipMemcpyAsync(Y, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st);
+  const int32_t* order = nullptr;
+  if (k > 0) {
+    launch_locality_order(n, idx, k, gt.label, gt.cnt, gt.blk, gt.order, st);
+    order = gt.order;
+  }
+  TimedScope ts(c, 3, st);
+  launch_dsfp(X, idx, n, d, k, gamma, rounds, order, Y, st);
+  return hipSuccess;
+}
+
+static gcr_status check_dsfp_args(gcr_ctx* c, int64_t n, int32_t d, int32_t k, float gamma, int32_t rounds) {
+  if (n < 1 || d <= 0 || k < 0 || rounds < 0) return fail(c, GCR_ERR_INVALID, "bad n / d / k / rounds");
+  if (!(gamma > 0.f) || !std::isfinite(gamma)) return fail(c, GCR_ERR_INVALID, "gamma must be finite and > 0");
+  if (k > DSFP_K_MAX) return fail(c, GCR_ERR_UNSUPPORTED, "DSFP supports k <= %d", DSFP_K_MAX);
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
+  if (n > (int64_t)INT32_MAX / 2) return fail(c, GCR_ERR_UNSUPPORTED, "n too large");
+  return GCR_OK;
+}
+
+gcr_status gcr_dsfp(gcr_ctx* c, const float* X, const int32_t* idx, int64_t n, int32_t d, int32_t k, float gamma,
+                    int32_t rounds, float* Y, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  gcr_status s = check_dsfp_args(c, n, d, k, gamma, rounds);
+  if (s != GCR_OK) return s;
+  if (!X || !Y || (k > 0 && !idx)) return fail(c, GCR_ERR_INVALID, "X / Y / idx are NULL");
+  const size_t bytes = (size_t)n * d * sizeof(float);
+  const uintptr_t xb = (uintptr_t)X, yb = (uintptr_t)Y;
+  if (xb < yb + bytes && yb < xb + bytes) return fail(c, GCR_ERR_INVALID, "Y overlaps X");
+  HIP_TRY(c, hipSetDevice(c->device));
+  Arena dry;
+  GraphTmp gt;
+  plan_graph_tmp(dry, gt, n);
+  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan_graph_tmp(ar, gt, n);
+  HIP_TRY(c, enqueue_dsfp(c, gt, X, idx, n, d, k, gamma, rounds, Y, (hipStream_t)stream));
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+gcr_status gcr_rerank_local(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_t d, const gcr_params* p,
+                            float* dist_out, int32_t* topk_idx, float* topk_dist, float* X_final, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  gcr_status s = check_params(c, p);
+  if (s != GCR_OK) return s;
+  const int64_t n = nq + ng;
+  if (!X || nq < 1 || ng < 1) return fail(c, GCR_ERR_INVALID, "bad X / nq / ng");
+  if ((s = check_dsfp_args(c, n, d, p->k, p->gamma, p->rounds)) != GCR_OK) return s;
+  if (topk_idx && (!topk_dist || p->topk_out < 1 || p->topk_out > 120))
+    return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int k = p->k;
+  auto plan = [&](Arena& ar, float** xa, float** xb, int32_t** idx, float** dist, KnnPlan& kp, GraphTmp& gt) {
+    *xa = ar.take<float>((size_t)n * d);
+    *xb = ar.take<float>((size_t)n * d);
+    *idx = ar.take<int32_t>((size_t)n * (k > 0 ? k : 1));
+    *dist = ar.take<float>((size_t)n * (k > 0 ? k : 1));
+    plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, k, 0);
+    plan_graph_tmp(ar, gt, n);
+  };
+  float *xa, *xb, *dist;
+  int32_t* idx;
+  KnnPlan kp;
+  GraphTmp gt;
+  FinalPlan fp;
+  const bool dense = dist_out != nullptr, topk = topk_idx != nullptr;
+  Arena dry;
+  plan(dry, &xa, &xb, &idx, &dist, kp, gt);
+  plan_final(dry, fp, p, nq, ng, d, dense, topk);
+  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  Arena ar{(char*)c->ws, 0};
+  plan(ar, &xa, &xb, &idx, &dist, kp, gt);
+  plan_final(ar, fp, p, nq, ng, d, dense, topk);
+
+  if (p->normalize_input) {
+    TimedScope ts(c, 5, st);
+    launch_normalize_rows(X, xa, n, d, st);
+  }
+  else HIP_TRY(c, hipMemcpyAsync(xa, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (k > 0) run_knn(c, kp, xa, d, nullptr, 0, n, 0, n, 1, k, 0, idx, dist, nullptr, nullptr, st);
+  HIP_TRY(c, enqueue_dsfp(c, gt, xa, idx, n, d, k, p->gamma, p->rounds, xb, st));
+  run_final(c, fp, xb, nq, ng, d, p, dist_out, topk_idx, topk_dist, st);
+  if (X_final) HIP_TRY(c, hipMemcpyAsync(X_final, xb, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
   HIP_TRY(c, hipGetLastError());
   return GCR_OK;
 }

@@ -159,6 +159,13 @@ void launch_cand_order(int64_t n, const uint64_t* cand, const int32_t* ccnt, int
                        int32_t* cnt, int32_t* blk, int32_t* order, hipStream_t st);
 
 // ---- propagate.hip
+// DSFP (Alg. 1): one workgroup per node over its local set (the node and
+// its distinct valid list entries).  Requires rounds >= 1, 0 <= k <=
+// DSFP_K_MAX (the local matrices then fit 64 KB of LDS), d <= 2048, Y != X.
+constexpr int DSFP_K_MAX = 59;
+void launch_dsfp(const float* X, const int32_t* idx, int64_t n, int d, int k, float gamma, int rounds,
+                 const int32_t* order, float* Y, hipStream_t st);
+
 struct PropArgs {
   const float* X; float* Y; int64_t n; int d;
   const float* self;

@@ -263,6 +263,45 @@ class Context:
                                      _ptr(o.get("X") if keep_features else None), _stream()), "gcr_rerank")
         return o
 
+    def dsfp(self, X: torch.Tensor, idx: Optional[torch.Tensor], p: Params,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """DSFP (Alg. 1) of X (used as given) over the neighbour lists idx
+        (int32 [n, k], or None with k = 0), with p.gamma and p.rounds."""
+        _check(X, torch.float32, "X", self.device)
+        n, d = X.shape
+        k = 0
+        if idx is not None:
+            _check(idx, torch.int32, "idx", self.device)
+            k = idx.shape[1]
+        Y = out if out is not None else torch.empty_like(X)
+        self._ok(self.lib.gcr_dsfp(self.h, _ptr(X), _ptr(idx), n, d, k, p.gamma, p.rounds, _ptr(Y), _stream()),
+                 "gcr_dsfp")
+        return Y
+
+    def rerank_local(self, X: torch.Tensor, nq: int, p: Params, dense: bool = True, topk: bool = False,
+                     keep_features: bool = False, out: Optional[dict] = None):
+        """GCR_Local re-ranking (kNN once, DSFP, final distances); returns
+        dict(dist, topk_idx, topk_dist, X)."""
+        _check(X, torch.float32, "X", self.device)
+        n, d = X.shape
+        ng = n - nq
+        o = out if out is not None else {}
+        if dense and o.get("dist") is None:
+            o["dist"] = torch.empty((nq, ng), dtype=torch.float32, device=self.device)
+        if topk and o.get("topk_idx") is None:
+            o["topk_idx"] = torch.empty((nq, p.topk_out), dtype=torch.int32, device=self.device)
+            o["topk_dist"] = torch.empty((nq, p.topk_out), dtype=torch.float32, device=self.device)
+        if keep_features and o.get("X") is None:
+            o["X"] = torch.empty_like(X)
+        pc = p.c()
+        self._ok(self.lib.gcr_rerank_local(self.h, _ptr(X), nq, ng, d, C.byref(pc),
+                                           _ptr(o.get("dist") if dense else None),
+                                           _ptr(o.get("topk_idx") if topk else None),
+                                           _ptr(o.get("topk_dist") if topk else None),
+                                           _ptr(o.get("X") if keep_features else None), _stream()),
+                 "gcr_rerank_local")
+        return o
+
     def profile_vectors(self, frames: torch.Tensor, offsets: torch.Tensor, groups: Optional[torch.Tensor] = None,
                         mode: str = "pvg", lam: float = 10.0) -> torch.Tensor:
         """Eq. (16) ("pvg") or Eq. (10) ("mean") profiles, L2-normalised.
