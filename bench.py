@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-agreement", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=192)
-    ap.add_argument("--workload", default="cross_camera", choices=["cross_camera", "serving"],
+    ap.add_argument("--workload", default="cross_camera", choices=["cross_camera", "serving", "local"],
                     help="cross_camera: whole re-ranking steps (default); serving: resident 500,000 x 512 "
                          "gallery and a Poisson request trace")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
@@ -258,6 +258,103 @@ def serving_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def local_bench(args):
+    """GCR_Local (DSFP, Alg. 1) on the cross-camera workload: one step = one
+    gcr_rerank_local call (normalise, kNN once with BF16 screening + exact
+    refine, DSFP with k = 20, gamma = 0.2, T = 3, dense final distances).
+    Roofline of the DSFP kernel: useful FP32 work per node = the local Gram
+    (m (m + 1) / 2 dot products of length d) plus the output combination (m
+    rows of length d), m = k + 1, against the vector FP32 peak."""
+    import torch
+
+    from paper_2306_08792_amd import datagen
+    from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params
+
+    prec = {"fp32": FP32, "bf16": BF16, "fp8": FP8}[args.precision]
+    print("generating the cross-camera workload", file=sys.stderr, flush=True)
+    w = datagen.cross_camera_reid()
+    n, d = w.X.shape
+    k, gamma, rounds = 20, 0.2, 3
+    ctx = Context(0)
+    X = torch.from_numpy(w.X).cuda()
+    p = Params(k=k, gamma=gamma, rounds=rounds, precision=prec)
+    out = {}
+    for _ in range(args.warmup):
+        ctx.rerank_local(X, w.nq, p, dense=True, out=out)
+    torch.cuda.synchronize()
+    ctx.timing()
+    ctx.set_timing(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record()
+        ctx.rerank_local(X, w.nq, p, dense=True, out=out)
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    tim = ctx.timing()
+    step_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    ds_ms, ds_n = tim["propagate"]
+    ds_avg = ds_ms / max(1, ds_n)
+    m = k + 1
+    flops = float(n) * d * (m * (m + 1) + 2 * m)
+    achieved = flops / (ds_avg * 1e-3) / 1e12
+    peak = 157.3
+    res = {
+        "metric": METRIC,
+        "value": round(w.nq * args.steps / wall, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1000.0 / args.steps, 3),
+        "p50_ms": round(float(np.percentile(step_ms, 50)), 3),
+        "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name + "_gcr_local", "queries": w.nq, "gallery": w.ng, "d": d, "k": k,
+                   "gamma": gamma, "rounds": rounds, "propagation": "DSFP (local, Alg. 1)",
+                   "graph": "kNN once", "output": "dense distances",
+                   "screening": args.precision + "+exact refine", "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "dsfp", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "avg_launch_ms": round(ds_avg, 4), "launches": int(ds_n), "flops_per_launch": flops},
+        "stage_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in tim.items()},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import gcr_oracle as O
+
+        print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        Xn = O.row_normalize(w.X)
+        rng = np.random.default_rng(0)
+        rows = np.sort(rng.choice(n, size=min(args.cpu_sample_rows, n), replace=False))
+        t0 = time.perf_counter()
+        idx, _ = O.knn_rows(O.sq_dists(Xn, rows), rows, k)
+        for t, i in enumerate(rows):
+            O.dsfp_node(Xn, O.local_set(int(i), idx[t]), gamma, rounds)
+        t_row = (time.perf_counter() - t0) / len(rows)
+        qrows = rows[rows < w.nq]
+        t1 = time.perf_counter()
+        if len(qrows):
+            O.sq_dists(Xn, qrows)
+        t_q = (time.perf_counter() - t1) / max(1, len(qrows))
+        total = t_row * n + t_q * w.nq
+        res["cpu_baseline"] = {
+            "value": round(w.nq / total, 3), "unit": "queries/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": (f"FP64 oracle steps (distance row, stable sort, DSFP of the node) on {len(rows)} of {n} "
+                       f"rows plus {len(qrows)} final distance rows, scaled linearly to {n} rows and {w.nq} "
+                       f"queries"),
+        }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -269,6 +366,9 @@ def main():
         sys.exit(2)
     if args.workload == "serving":
         serving_bench(args)
+        return
+    if args.workload == "local":
+        local_bench(args)
         return
     import torch
 

@@ -21,25 +21,31 @@ namespace gcr {
 namespace {
 
 constexpr int DS_NT = 256;  // threads per workgroup
-constexpr int DS_DC = 64;   // feature columns per staged chunk
+// Feature columns per staged chunk: 128 when the local set has at most 32
+// members, 64 up to 64 members (the chunk then always fills 4 float4 slots
+// per thread, and the transposed chunk fits the LDS of the Gram partials).
+constexpr int ds_dc(int mp) { return mp <= 32 ? 128 : 64; }
 
 struct DsLayout {
   int mp;       // local size rounded up to a multiple of 4
   float* G;     // [mp][mp] Gram
   float* P;     // [mp][mp] normalised local affinity
   float* C;     // [mp][mp] coefficients of the local rows
-  float* stage; // [DS_DC][mp] transposed feature chunk; later the Gram
-                // partials and the unscaled coefficients of a round
+  float* stage; // [mp][DC + 1] feature chunk (odd row stride: the chunk's
+                // stores and the Gram's column reads spread over the LDS
+                // banks); later the Gram partials and the unscaled
+                // coefficients of a round
 };
 
 __host__ __device__ inline int ds_mp(int k) { return ((k + 1 + 3) / 4) * 4; }
-__host__ __device__ inline int ds_stage_floats(int mp) {
-  const int a = DS_DC * mp, b = DS_NT * 16;
-  return a > b ? a : b;
-}
-__host__ __device__ inline size_t ds_lds_bytes(int k) {
+// LDS floats: G, P, C and the stage, or G and the Gram partials of all 256
+// threads (16 each), whichever is larger.  The partials are placed at the
+// end of the region, over P, C and the stage, which are unused while the
+// partials are summed into G.
+__host__ __device__ inline int ds_lds_floats(int k) {
   const int mp = ds_mp(k);
-  return (size_t)(3 * mp * mp + ds_stage_floats(mp)) * sizeof(float);
+  const int a = 3 * mp * mp + (ds_dc(mp) + 1) * mp, b = mp * mp + DS_NT * 16;
+  return a > b ? a : b;
 }
 
 __device__ __forceinline__ float block_sum(float v, float* red4) {
@@ -52,13 +58,13 @@ __device__ __forceinline__ float block_sum(float v, float* red4) {
   return s;
 }
 
-// Chunk [c0, c0 + DS_DC) of the m local rows, one float4 per slot: slot e
-// covers local row e / (DS_DC / 4), columns c0 + 4 (e % (DS_DC / 4)) + 0..3.
-template <bool VEC>
+// Chunk [c0, c0 + DC) of the m local rows, one float4 per slot: slot e
+// covers local row e / (DC / 4), columns c0 + 4 (e % (DC / 4)) + 0..3.
+template <bool VEC, int DC>
 __device__ __forceinline__ f32x4 load_slot(const float* __restrict__ X, const int* nodes, int m, int d, int c0,
                                            int e) {
   f32x4 v = {0.f, 0.f, 0.f, 0.f};
-  const int u = e / (DS_DC / 4), q = e % (DS_DC / 4);
+  const int u = e / (DC / 4), q = e % (DC / 4);
   const int col = c0 + 4 * q;
   if (u < m && col < d) {
     const float* row = X + (int64_t)nodes[u] * d;
@@ -86,7 +92,7 @@ struct DsfpArgs {
   float gamma;
 };
 
-template <bool VEC>
+template <bool VEC, int DC>
 __global__ __launch_bounds__(DS_NT) void dsfp_kernel(DsfpArgs a) {
   extern __shared__ f32x4 ds_smem4[];  // 16-byte aligned for the float4 reads
   float* ds_smem = (float*)ds_smem4;
@@ -151,40 +157,45 @@ __global__ __launch_bounds__(DS_NT) void dsfp_kernel(DsfpArgs a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[r][s] = 0.f;
 
-  constexpr int SLOTS = 64 * DS_DC / 4 / DS_NT;  // float4 slots per thread for m <= 64
-  const int nslot = ((m + 3) / 4) * 4 * (DS_DC / 4);  // rows padded to nb * 4
+  constexpr int SLOTS = (DC == 128 ? 32 : 64) * DC / 4 / DS_NT;  // float4 slots per thread
+  const int nslot = ((m + 3) / 4) * 4 * (DC / 4);  // rows padded to nb * 4
   f32x4 pre[SLOTS];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int e = tid + s * DS_NT;
-    pre[s] = e < nslot ? load_slot<VEC>(a.X, s_nodes, m, d, 0, e) : f32x4{0.f, 0.f, 0.f, 0.f};
+    pre[s] = e < nslot ? load_slot<VEC, DC>(a.X, s_nodes, m, d, 0, e) : f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  for (int c0 = 0; c0 < d; c0 += DS_DC) {
+  for (int c0 = 0; c0 < d; c0 += DC) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int e = tid + s * DS_NT;
       if (e < nslot) {
-        const int u = e / (DS_DC / 4), q = e % (DS_DC / 4);
-        float* col = L.stage + (4 * q) * mp + u;
-        col[0] = pre[s].x;
-        col[mp] = pre[s].y;
-        col[2 * mp] = pre[s].z;
-        col[3 * mp] = pre[s].w;
+        const int u = e / (DC / 4), q = e % (DC / 4);
+        float* dst = L.stage + u * (DC + 1) + 4 * q;
+        dst[0] = pre[s].x;
+        dst[1] = pre[s].y;
+        dst[2] = pre[s].z;
+        dst[3] = pre[s].w;
       }
     }
     __syncthreads();
-    if (c0 + DS_DC < d) {
+    if (c0 + DC < d) {
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         const int e = tid + s * DS_NT;
-        if (e < nslot) pre[s] = load_slot<VEC>(a.X, s_nodes, m, d, c0 + DS_DC, e);
+        if (e < nslot) pre[s] = load_slot<VEC, DC>(a.X, s_nodes, m, d, c0 + DC, e);
       }
     }
     if (active) {
-      for (int c = grp; c < DS_DC; c += groups) {
-        const f32x4 x = *(const f32x4*)(L.stage + c * mp + 4 * bi);
-        const f32x4 y = *(const f32x4*)(L.stage + c * mp + 4 * bj);
-        const float xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+      const float* xr = L.stage + 4 * bi * (DC + 1);
+      const float* yr = L.stage + 4 * bj * (DC + 1);
+      for (int c = grp; c < DC; c += groups) {
+        float xs[4], ys[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          xs[r] = xr[r * (DC + 1) + c];
+          ys[r] = yr[r * (DC + 1) + c];
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -194,7 +205,7 @@ __global__ __launch_bounds__(DS_NT) void dsfp_kernel(DsfpArgs a) {
     __syncthreads();
   }
   // partials -> G (sum over the column groups in group order)
-  float* part = L.stage;
+  float* part = ds_smem + ds_lds_floats(k) - nblk * groups * 16;
   if (active) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -299,13 +310,22 @@ __global__ __launch_bounds__(DS_NT) void dsfp_kernel(DsfpArgs a) {
       y[q] = f32x4{0.f, 0.f, 0.f, 0.f};
       const int col = 4 * (tid + q * DS_NT);
       if (col < d) {
-        for (int u = 0; u < m; ++u) {
-          const f32x4 x = *(const f32x4*)(a.X + (int64_t)s_nodes[u] * d + col);
-          const float c = s_cf[u];
-          y[q].x = fmaf(c, x.x, y[q].x);
-          y[q].y = fmaf(c, x.y, y[q].y);
-          y[q].z = fmaf(c, x.z, y[q].z);
-          y[q].w = fmaf(c, x.w, y[q].w);
+        // rows in batches of 8 (all loads issued before the sums, which
+        // stay in row order)
+        for (int u0 = 0; u0 < m; u0 += 8) {
+          f32x4 xb[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (u0 + t < m) xb[t] = *(const f32x4*)(a.X + (int64_t)s_nodes[u0 + t] * d + col);
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (u0 + t < m) {
+              const float c = s_cf[u0 + t];
+              y[q].x = fmaf(c, xb[t].x, y[q].x);
+              y[q].y = fmaf(c, xb[t].y, y[q].y);
+              y[q].z = fmaf(c, xb[t].z, y[q].z);
+              y[q].w = fmaf(c, xb[t].w, y[q].w);
+            }
         }
         ss += y[q].x * y[q].x + y[q].y * y[q].y + y[q].z * y[q].z + y[q].w * y[q].w;
       }
@@ -325,7 +345,15 @@ __global__ __launch_bounds__(DS_NT) void dsfp_kernel(DsfpArgs a) {
       y[q] = 0.f;
       const int col = tid + q * DS_NT;
       if (col < d) {
-        for (int u = 0; u < m; ++u) y[q] = fmaf(s_cf[u], a.X[(int64_t)s_nodes[u] * d + col], y[q]);
+        for (int u0 = 0; u0 < m; u0 += 8) {
+          float xb[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (u0 + t < m) xb[t] = a.X[(int64_t)s_nodes[u0 + t] * d + col];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (u0 + t < m) y[q] = fmaf(s_cf[u0 + t], xb[t], y[q]);
+        }
         ss += y[q] * y[q];
       }
     }
@@ -351,12 +379,16 @@ void launch_dsfp(const float* X, const int32_t* idx, int64_t n, int d, int k, fl
   a.k = k;
   a.rounds = rounds;
   a.gamma = gamma;
-  const size_t lds = ds_lds_bytes(k);
+  const size_t lds = (size_t)ds_lds_floats(k) * sizeof(float);
   const bool vec = d % 4 == 0 && ((((uintptr_t)X) | ((uintptr_t)Y)) & 15) == 0;
-  if (vec)
-    hipLaunchKernelGGL(dsfp_kernel<true>, dim3((unsigned)n), dim3(DS_NT), lds, st, a);
-  else
-    hipLaunchKernelGGL(dsfp_kernel<false>, dim3((unsigned)n), dim3(DS_NT), lds, st, a);
+  const dim3 g((unsigned)n), b(DS_NT);
+  if (ds_mp(k) <= 32) {
+    if (vec) hipLaunchKernelGGL((dsfp_kernel<true, 128>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((dsfp_kernel<false, 128>), g, b, lds, st, a);
+  } else {
+    if (vec) hipLaunchKernelGGL((dsfp_kernel<true, 64>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((dsfp_kernel<false, 64>), g, b, lds, st, a);
+  }
 }
 
 }  // namespace gcr
