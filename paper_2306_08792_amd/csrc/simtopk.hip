@@ -128,19 +128,38 @@ __device__ __forceinline__ void mma_chunk(const uint8_t* __restrict__ Rt, const 
             acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[cb][s], vr[rb][s], acc[cb][rb], 0, 0, 0);
     }
   } else if constexpr (PREC == GCR_PREC_BF16) {
+    // fragments of step q + 1 are read while the 8 MFMAs of step q run
+    bf16x8 fr[2][2], fc[2][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      bf16x8 fr[2], fc[4];
+    for (int q = 0; q < 5; ++q) {
+      if (q < 4) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b) fr[b] = *(const bf16x8*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
+        for (int b = 0; b < 2; ++b) fr[q & 1][b] = *(const bf16x8*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) fc[b] = *(const bf16x8*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
+        for (int b = 0; b < 4; ++b) fc[q & 1][b] = *(const bf16x8*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
+      }
+      if (q > 0) {
+        const int p = (q - 1) & 1;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-          acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fc[cb], fr[rb], acc[cb][rb], 0, 0, 0);
+          for (int rb = 0; rb < 2; ++rb)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fc[p][cb], fr[p][rb], acc[cb][rb], 0, 0, 0);
+      }
     }
+    // issue order: the first step's 6 reads, then per step its 8 MFMAs with
+    // the next step's 6 reads interleaved
+    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
   } else {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
