@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-agreement", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=192)
+    ap.add_argument("--cpu-sample-rows", type=int, default=3840)
     ap.add_argument("--workload", default="cross_camera", choices=["cross_camera", "serving", "local"],
                     help="cross_camera: whole re-ranking steps (default); serving: resident 500,000 x 512 "
                          "gallery and a Poisson request trace")
