@@ -169,7 +169,8 @@ def serving_bench(args):
     p = Params(k=20, rounds=2, gamma=0.2, topk_out=100, precision=BF16, rebuild_each_round=False)
     print("building the resident gallery state (BF16 screening)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    srv = Server(ctx, g, p, slots=4, max_batch=512, max_recomputed=65536)
+    n_mut = 1000
+    srv = Server(ctx, g, p, slots=4, max_batch=512, max_recomputed=65536, gallery_capacity=ng + n_mut)
     t_build = time.perf_counter() - t0
 
     agreement = None
@@ -225,6 +226,22 @@ def serving_bench(args):
     for i in range(len(trace)):
         lat[i] = (done_at[i] - (start + arrivals[i])) * 1e3
     span = max(done_at) - start
+
+    # gallery mutations: 1,000 new items (near random centres, like the
+    # queries), then 1,000 random items removed; each call returns once the
+    # lists, graph, gallery rounds and operands are exact again
+    print("gallery mutations", file=sys.stderr, flush=True)
+    mrng = np.random.default_rng(11)
+    rows = datagen._unit_rows_f32(centres[mrng.integers(0, len(centres), n_mut)]
+                                  + 0.6 * mrng.standard_normal((n_mut, d)))
+    t0 = time.perf_counter()
+    srv.insert(rows)
+    t_ins = time.perf_counter() - t0
+    gone = mrng.choice(ng, size=n_mut, replace=False).astype(np.int32)
+    t0 = time.perf_counter()
+    srv.remove(gone)
+    t_rem = time.perf_counter() - t0
+    srv.query(trace[0][1])
     st = srv.stats()
     srv.close()
     ctx.close()
@@ -253,6 +270,8 @@ def serving_bench(args):
                           "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3)},
         "saturated_phase": {"seconds": round(t_sat, 3), "queries_per_s": round(qps_sat, 2)},
         "gallery_build_s": round(t_build, 3),
+        "mutation": {"insert_rows": n_mut, "insert_ms": round(t_ins * 1e3, 2), "remove_rows": n_mut,
+                     "remove_ms": round(t_rem * 1e3, 2), "full_build_ms": round(t_build * 1e3, 1)},
         "server": st,
     }
     print(json.dumps(res), flush=True)

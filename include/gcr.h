@@ -314,6 +314,8 @@ typedef struct {
                              max_batch * k <= 16384)                          */
   int32_t max_recomputed; /* gallery rows recomputed per round and request
                              (default 65536)                                  */
+  int32_t gallery_capacity; /* gallery rows reserved for inserts; 0: the
+                             initial gallery size (default 0)                 */
 } gcr_server_config;
 void gcr_server_config_default(gcr_server_config* cfg);
 
@@ -323,6 +325,8 @@ typedef struct {
   int64_t max_recomputed_rows; /* largest per-round recomputed set seen      */
   int64_t slots, max_batch, max_recomputed;
   int64_t device_bytes;        /* device memory held by the server           */
+  int64_t gallery_size;        /* live gallery items                          */
+  int64_t gallery_capacity;    /* gallery rows reserved                       */
 } gcr_server_stats;
 
 /* Build a server on ctx's device.
@@ -347,7 +351,7 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery,
 gcr_status gcr_server_submit(gcr_server* srv, const float* q_host, int32_t b,
                              uint64_t* ticket);
 /* Wait for a request (timeout_ms < 0: no limit; 0: poll).  On success the
- * HOST arrays idx_host [b, K] int32 (gallery indices, -1 padding) and
+ * HOST arrays idx_host [b, K] int32 (external gallery ids, -1 padding) and
  * dist_host [b, K] float32 receive the result (either may be NULL) and the
  * ticket is released.  Returns TIMEOUT (ticket kept) if not done in time;
  * UNSUPPORTED if the request needed more than max_recomputed rows in a
@@ -357,6 +361,44 @@ gcr_status gcr_server_wait(gcr_server* srv, uint64_t ticket, int32_t* idx_host,
 gcr_status gcr_server_get_stats(gcr_server* srv, gcr_server_stats* out);
 /* Message of the last failed server call (never NULL). */
 const char* gcr_server_last_error(const gcr_server* srv);
+/* Mutable gallery.  Every gallery item has an external id: the initial
+ * items get 0..ng-1 and inserted items the next unused ids, in order.
+ * Results of gcr_server_wait are external ids.  A mutation waits for the
+ * requests on the device, holds back new ones while it runs, and leaves the
+ * server exactly as a server created on the resulting gallery (items in id
+ * order) would be: the gallery's kNN lists are maintained exactly (inserted
+ * rows are searched against the whole gallery and merged into the lists they
+ * enter; lists that lose a removed item are searched again), and the graph,
+ * degrees, gallery-only rounds and screening operands are recomputed from
+ * the lists.  The precomputed database graph of Sec. IV-F thereby follows a
+ * changing database without a full rebuild.  Requests submitted before a
+ * mutation call returns may run before or after it.  After a HIP error the
+ * server must be destroyed.
+ *
+ * gcr_server_insert: rows_host is a HOST array [m, d] float32, used as
+ *   supplied (as the gallery at creation); ids_out (HOST [m] or NULL)
+ *   receives the new ids.  Errors: INVALID, UNSUPPORTED (beyond
+ *   cfg.gallery_capacity), HIP.
+ * gcr_server_remove: ids_host is a HOST array [m] of external ids (repeats
+ *   allowed).  Errors: INVALID (an id not in the gallery, or fewer than 2
+ *   items would remain; nothing is changed), HIP.
+ * gcr_server_gallery_ids: the live ids in increasing order (the gallery's
+ *   row order) into ids_host (HOST, capacity entries; NULL: count only);
+ *   *count receives their number.
+ * gcr_server_save / gcr_server_load: the resident state that is expensive to
+ *   rebuild (parameters, ids, level-0 features, kNN lists) to / from a file;
+ *   load recomputes the rest and starts a server with configuration cfg.
+ *   Errors: INVALID (unreadable file or not a saved state), NOMEM, HIP. */
+gcr_status gcr_server_insert(gcr_server* srv, const float* rows_host, int32_t m,
+                             int32_t* ids_out);
+gcr_status gcr_server_remove(gcr_server* srv, const int32_t* ids_host,
+                             int32_t m);
+gcr_status gcr_server_gallery_ids(gcr_server* srv, int32_t* ids_host,
+                                  int64_t capacity, int64_t* count);
+gcr_status gcr_server_save(gcr_server* srv, const char* path);
+gcr_status gcr_server_load(gcr_ctx* ctx, const char* path,
+                           const gcr_server_config* cfg, gcr_server** out);
+
 /* Finish the requests in flight, fail the queued ones, free everything. */
 gcr_status gcr_server_destroy(gcr_server* srv);
 

@@ -25,6 +25,7 @@ EXPORTS = [
     "gcr_server_config_default", "gcr_server_create", "gcr_server_submit", "gcr_server_wait",
     "gcr_server_get_stats", "gcr_server_last_error", "gcr_server_destroy",
     "gcr_dsfp", "gcr_rerank_local",
+    "gcr_server_insert", "gcr_server_remove", "gcr_server_gallery_ids", "gcr_server_save", "gcr_server_load",
 ]
 NUM_TIMERS = 6
 TIMER_NAMES = ["sim_topk", "refine", "graph", "propagate", "final_dense", "prep"]
@@ -66,13 +67,15 @@ class GcrGraph(C.Structure):
 
 
 class GcrServerConfig(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("max_batch", C.c_int32), ("max_recomputed", C.c_int32)]
+    _fields_ = [("slots", C.c_int32), ("max_batch", C.c_int32), ("max_recomputed", C.c_int32),
+                ("gallery_capacity", C.c_int32)]
 
 
 class GcrServerStats(C.Structure):
     _fields_ = [("requests_done", C.c_int64), ("queries_done", C.c_int64),
                 ("max_recomputed_rows", C.c_int64), ("slots", C.c_int64), ("max_batch", C.c_int64),
-                ("max_recomputed", C.c_int64), ("device_bytes", C.c_int64)]
+                ("max_recomputed", C.c_int64), ("device_bytes", C.c_int64), ("gallery_size", C.c_int64),
+                ("gallery_capacity", C.c_int64)]
 
 
 _lib = None
@@ -125,6 +128,11 @@ def load(path: str = LIB_PATH):
     L.gcr_server_last_error.restype = C.c_char_p
     L.gcr_server_destroy.argtypes = [vp]
     L.gcr_dsfp.argtypes = [vp, vp, vp, i64, i32, i32, f32, i32, vp, vp]
+    L.gcr_server_insert.argtypes = [vp, vp, i32, vp]
+    L.gcr_server_remove.argtypes = [vp, vp, i32]
+    L.gcr_server_gallery_ids.argtypes = [vp, vp, i64, C.POINTER(i64)]
+    L.gcr_server_save.argtypes = [vp, C.c_char_p]
+    L.gcr_server_load.argtypes = [vp, C.c_char_p, C.POINTER(GcrServerConfig), C.POINTER(vp)]
     L.gcr_rerank_local.argtypes = [vp, vp, i64, i64, i32, pP, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         fn = getattr(L, name)

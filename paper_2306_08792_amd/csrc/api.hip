@@ -382,6 +382,14 @@ void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, cons
             cross ? g->cr_idx : nullptr, cross ? g->cr_dist : nullptr, st,
             seed_from_previous ? g->idx : nullptr, seed_from_previous && cross ? g->cr_idx : nullptr,
             seed_from_previous && g->k > 0 ? gt.order : nullptr);
+  enqueue_graph_from_lists(c, gt, n, cam, p, g, st);
+}
+
+// Affinities, reverse lists, degrees, normalised values, self coefficients
+// and the locality order from the forward lists already in g.
+void enqueue_graph_from_lists(gcr_ctx* c, const GraphTmp& gt, int64_t n, const int* cam, const gcr_params* p,
+                              const gcr_graph* g, hipStream_t st) {
+  const bool cross = g->has_cross != 0;
   const float alpha = cross ? p->alpha : 1.0f;
   TimedScope ts(c, 2, st);
   build_one(g, false, n, cam, p, alpha, gt, st, false);

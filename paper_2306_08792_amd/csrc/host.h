@@ -88,6 +88,8 @@ void plan_graph_tmp(Arena& ar, GraphTmp& t, int64_t n);
 void enqueue_build_graph(gcr_ctx* c, const KnnPlan& kp, const GraphTmp& gt, const float* X, int64_t n, int d,
                          const int* cam, const gcr_params* p, const gcr_graph* g, hipStream_t st,
                          bool seed_from_previous = false);
+void enqueue_graph_from_lists(gcr_ctx* c, const GraphTmp& gt, int64_t n, const int* cam, const gcr_params* p,
+                              const gcr_graph* g, hipStream_t st);
 void enqueue_propagate(gcr_ctx* c, const gcr_graph* g, const float* Xin, float* Xout, int64_t n, int d,
                        hipStream_t st, const int32_t* order);
 

@@ -227,6 +227,22 @@ struct ServePropArgs {
 void launch_serve_propagate(const ServePropArgs& a, hipStream_t st);
 void launch_serve_merge(int b, int K, const int32_t* ia, const float* da, const int32_t* ib, const float* db,
                         const int32_t* list, int32_t* oi, float* od, hipStream_t st);
+// Gallery list maintenance (exact under inserts and removals).
+// Merge each of `rows` lists [rows, k] with its m nearest appended items
+// (indices + col_offset), keeping the k smallest by (distance, index).
+void launch_merge_appended(int64_t rows, int k, int32_t* idx, float* dist, int m, const int32_t* nidx,
+                           const float* ndist, int32_t col_offset, hipStream_t st);
+// Lists of the surviving rows renumbered by new_of_old (-1: removed) into
+// distinct buffers; rows that lost a neighbour are appended to repair.
+void launch_relabel_lists(int64_t rows_old, int k, const int32_t* new_of_old, const int32_t* idx_old,
+                          const float* dist_old, int32_t* idx_new, float* dist_new, int32_t* repair,
+                          int* repair_count, hipStream_t st);
+// dst[r] = src[src_row[r]] (float rows of width d; dst distinct from src).
+void launch_gather_rows(const float* src, float* dst, const int32_t* src_row, int64_t rows, int d, hipStream_t st);
+// k + 1 nearest items of row self_row[t] (itself included) -> its k nearest
+// other items, written to row self_row[t] of idx_out / dist_out.
+void launch_drop_self(int64_t rows, int k, const int32_t* self_row, const int32_t* idx_in, const float* dist_in,
+                      int32_t* idx_out, float* dist_out, hipStream_t st);
 void launch_bf16_to_f32(const uint16_t* in, float* out, int64_t n, hipStream_t st);
 void launch_copy_u32(const unsigned* src, unsigned* dst, int n, hipStream_t st);
 

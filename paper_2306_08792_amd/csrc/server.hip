@@ -6,6 +6,12 @@
 // others run overlap on the device.  Each request is computed exactly over
 // the node set gallery + its queries (see serve.hip), independently of the
 // other requests in flight.
+//
+// The gallery is mutable: rows are appended or removed between requests and
+// its kNN lists are maintained exactly (gallery.hip), after which the graph,
+// degrees, gallery-only rounds and screening operands are recomputed from
+// the lists.  Items carry external ids; the device gallery stays dense.
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -166,7 +172,20 @@ struct Slot {
 struct gcr_server {
   int device = 0;
   gcr_params p;
-  int64_t G = 0;
+  int64_t G = 0;      // live gallery rows (dense, rows [0, G))
+  int64_t Gcap = 0;   // gallery capacity (rows reserved)
+  gcr_ctx* mctx = nullptr;         // private context for gallery maintenance
+  hipStream_t mst = nullptr;       // its stream
+  std::vector<int32_t> ext;        // external id of every gallery row, increasing
+  int64_t next_id = 0;
+  bool paused = false;             // no new request starts while set
+  std::mutex mut_mu;               // one gallery mutation at a time
+  int32_t* tmp_idx = nullptr;      // [Gcap, k + 1] list scratch
+  float* tmp_dist = nullptr;
+  int32_t* map_a = nullptr;        // [Gcap] row maps
+  int32_t* map_b = nullptr;
+  int32_t* repair = nullptr;       // [Gcap] rows whose lists are searched again
+  int* mcount = nullptr;           // [64] device counters
   int d = 0, k = 0, L = 0, K = 0, S = 0, Rq = 0, Rc = 0, P = 0, prec = 0;
   int64_t rows_total = 0;
   void* mem = nullptr;
@@ -281,6 +300,8 @@ void collect(gcr_server* s, Slot& sl) {
   Request& r = *sl.req;
   const size_t m = (size_t)r.b * s->K;
   r.idx.assign(sl.h_idx, sl.h_idx + m);
+  for (int32_t& v : r.idx)
+    if (v >= 0) v = s->ext[v];
   r.dist.assign(sl.h_dist, sl.h_dist + m);
   int worst = 0;
   for (int t = 1; t <= s->L; ++t) worst = std::max(worst, sl.h_counts[t]);
@@ -301,7 +322,7 @@ void worker_main(gcr_server* s) {
   for (;;) {
     bool busy = false;
     for (Slot& sl : s->slots) {
-      if (!sl.req && !s->pending.empty() && !s->stop) {
+      if (!sl.req && !s->pending.empty() && !s->stop && !s->paused) {
         Request* r = s->pending.front();
         s->pending.pop_front();
         sl.req = r;
@@ -331,7 +352,7 @@ void worker_main(gcr_server* s) {
       if (!busy) break;
     }
     if (!busy) {
-      s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+      s->cv_work.wait(lk, [&] { return s->stop || (!s->pending.empty() && !s->paused); });
       continue;
     }
     lk.unlock();
@@ -377,11 +398,18 @@ void plan_server(Arena& ar, gcr_server* s) {
   else s->opL = s->op0;
   s->max0 = ar.take<unsigned>(64);
   s->maxLg = ar.take<unsigned>(64);
-  void* gbuf = ar.take<char>(gcr_graph_bytes(s->G, s->k, 0, 0));
-  if (gbuf) gcr_graph_bind(&s->g, gbuf, s->G, s->k, 0, 0);
+  // graph arrays sized for the capacity; kernels run on the first G rows
+  void* gbuf = ar.take<char>(gcr_graph_bytes(s->Gcap, s->k, 0, 0));
+  if (gbuf) gcr_graph_bind(&s->g, gbuf, s->Gcap, s->k, 0, 0);
+  s->tmp_idx = ar.take<int32_t>((size_t)s->Gcap * (s->k + 1));
+  s->tmp_dist = ar.take<float>((size_t)s->Gcap * (s->k + 1));
+  s->map_a = ar.take<int32_t>((size_t)s->Gcap);
+  s->map_b = ar.take<int32_t>((size_t)s->Gcap);
+  s->repair = ar.take<int32_t>((size_t)s->Gcap);
+  s->mcount = ar.take<int>(64);
   for (Slot& sl : s->slots) {
-    plan_scratch(ar, sl.kn0, s->Rq, s->G, s->k);
-    plan_scratch(ar, sl.knA, s->Rq, s->G, s->K);
+    plan_scratch(ar, sl.kn0, s->Rq, s->Gcap, s->k);
+    plan_scratch(ar, sl.knA, s->Rq, s->Gcap, s->K);
     plan_scratch(ar, sl.knB, s->Rq, s->Rc, s->K);
     const int64_t qk = (int64_t)s->Rq * s->k;
     sl.q_idx = ar.take<int32_t>((size_t)qk);
@@ -389,18 +417,18 @@ void plan_server(Arena& ar, gcr_server* s) {
     sl.q_w = ar.take<float>((size_t)s->P);
     sl.Dq = ar.take<float>((size_t)s->Rq);
     sl.keys = ar.take<uint64_t>((size_t)s->P);
-    sl.touched = ar.take<uint32_t>((size_t)s->G);
-    sl.dD = ar.take<float>((size_t)s->G);
-    sl.seg_start = ar.take<int32_t>((size_t)s->G);
-    sl.seg_len = ar.take<int32_t>((size_t)s->G);
+    sl.touched = ar.take<uint32_t>((size_t)s->Gcap);
+    sl.dD = ar.take<float>((size_t)s->Gcap);
+    sl.seg_start = ar.take<int32_t>((size_t)s->Gcap);
+    sl.seg_len = ar.take<int32_t>((size_t)s->Gcap);
     sl.T_list = ar.take<int32_t>((size_t)qk);
     sl.counts = ar.take<int>(64);
     sl.mark.assign(s->L + 1, nullptr);
     sl.pos.assign(s->L + 1, nullptr);
     sl.list.assign(s->L + 1, nullptr);
     for (int t = 1; t <= s->L; ++t) {
-      sl.mark[t] = ar.take<uint32_t>((size_t)s->G);
-      sl.pos[t] = ar.take<int32_t>((size_t)s->G);
+      sl.mark[t] = ar.take<uint32_t>((size_t)s->Gcap);
+      sl.pos[t] = ar.take<int32_t>((size_t)s->Gcap);
       sl.list[t] = ar.take<int32_t>((size_t)s->Rc);
     }
     const int64_t qK = (int64_t)s->Rq * s->K;
@@ -421,31 +449,25 @@ void release(gcr_server* s) {
     if (sl.h_dist) (void)hipHostFree(sl.h_dist);
     if (sl.h_counts) (void)hipHostFree(sl.h_counts);
   }
+  if (s->mst) (void)hipStreamDestroy(s->mst);
   if (s->mem) (void)hipFree(s->mem);
+  if (s->mctx) (void)gcr_destroy(s->mctx);
   delete s;
 }
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-void gcr_server_config_default(gcr_server_config* c) {
-  if (!c) return;
-  c->slots = 4;
-  c->max_batch = 512;
-  c->max_recomputed = 65536;
-}
-
-gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_dtype, int64_t ng, int32_t d,
-                             const gcr_params* p, const gcr_server_config* cfg, gcr_server** out) {
-  if (!ctx || !out) return GCR_ERR_INVALID;
+// Validation, sizes and the one device allocation of a server over an
+// initial gallery of ng rows (nothing computed yet).
+gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config* cfg, int64_t ng, int32_t d,
+                      gcr_server** out) {
   *out = nullptr;
   const gcr_status pst = check_params(ctx, p);
   if (pst != GCR_OK) return pst;
-  if (!gallery || ng < 2 || d <= 0) return fail(ctx, GCR_ERR_INVALID, "bad gallery / ng / d");
-  if (gallery_dtype != 0 && gallery_dtype != 1) return fail(ctx, GCR_ERR_INVALID, "gallery_dtype must be 0 or 1");
+  if (ng < 2 || d <= 0) return fail(ctx, GCR_ERR_INVALID, "bad gallery size / d");
   if (d > 2048) return fail(ctx, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
-  if (ng > (int64_t)1 << 30) return fail(ctx, GCR_ERR_UNSUPPORTED, "galleries above 2^30 items are not supported");
   if (p->k < 1) return fail(ctx, GCR_ERR_INVALID, "serving needs k >= 1");
   if (p->topk_out < 1 || p->topk_out > 120) return fail(ctx, GCR_ERR_UNSUPPORTED, "top-K output must be in 1..120");
   if (p->rebuild_each_round) return fail(ctx, GCR_ERR_INVALID, "serving keeps the gallery graph fixed "
@@ -456,12 +478,16 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_
   if (cfg) c = *cfg;
   if (c.slots < 1 || c.slots > 16) return fail(ctx, GCR_ERR_INVALID, "slots must be in 1..16");
   if (c.max_batch < 1 || c.max_recomputed < 1) return fail(ctx, GCR_ERR_INVALID, "bad slot capacities");
+  const int64_t cap = c.gallery_capacity > 0 ? c.gallery_capacity : ng;
+  if (cap < ng) return fail(ctx, GCR_ERR_INVALID, "gallery_capacity is below the gallery size");
+  if (cap > (int64_t)1 << 30) return fail(ctx, GCR_ERR_UNSUPPORTED, "galleries above 2^30 items are not supported");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
 
   gcr_server* s = new gcr_server();
   s->device = ctx->device;
   s->p = *p;
   s->G = ng;
+  s->Gcap = cap;
   s->d = d;
   s->k = p->k;
   s->L = p->rounds;
@@ -469,14 +495,17 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_
   s->prec = p->precision;
   s->S = c.slots;
   s->Rq = std::min(c.max_batch, 16384 / p->k);
-  s->Rc = (int)std::min<int64_t>(c.max_recomputed, ng);
+  s->Rc = (int)std::min<int64_t>(c.max_recomputed, cap);
   s->P = pow2_at_least(s->Rq * p->k);
-  s->rows_total = ng + (int64_t)s->S * (s->Rq + s->Rc);
+  s->rows_total = cap + (int64_t)s->S * (s->Rq + s->Rc);
   s->slots.resize(s->S);
   for (int i = 0; i < s->S; ++i) {
-    s->slots[i].qbase = ng + (int64_t)i * (s->Rq + s->Rc);
+    s->slots[i].qbase = cap + (int64_t)i * (s->Rq + s->Rc);
     s->slots[i].pbase = s->slots[i].qbase + s->Rq;
   }
+  s->ext.resize(ng);
+  for (int64_t i = 0; i < ng; ++i) s->ext[i] = (int32_t)i;
+  s->next_id = ng;
   memset(&s->stats, 0, sizeof s->stats);
   s->stats.slots = s->S;
   s->stats.max_batch = s->Rq;
@@ -493,78 +522,356 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_
   }
   Arena ar{(char*)s->mem, 0};
   plan_server(ar, s);
-
-  hipStream_t st = nullptr;
-  auto bail = [&](gcr_status code, const char* what, hipError_t e) {
-    if (st) (void)hipStreamDestroy(st);
+  hipError_t e = hipStreamCreateWithFlags(&s->mst, hipStreamNonBlocking);
+  if (e == hipSuccess && gcr_create(&s->mctx, ctx->device) != GCR_OK) e = hipErrorOutOfMemory;
+  if (e != hipSuccess) {
     release(s);
-    return fail(ctx, code, "%s: %s", what, hipGetErrorString(e));
-  };
-  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e != hipSuccess) return bail(GCR_ERR_HIP, "stream", e);
-  // resident gallery: level-0 features as given (float32, or BF16 widened)
-  if (gallery_dtype == 0)
-    e = hipMemcpyAsync(s->X[0], gallery, (size_t)ng * d * sizeof(float), hipMemcpyDeviceToDevice, st);
-  else
-    launch_bf16_to_f32((const uint16_t*)gallery, s->X[0], ng * d, st);
-  if (e != hipSuccess) return bail(GCR_ERR_HIP, "gallery copy", e);
-  // frozen gallery graph (fixed mode, one list, no camera weighting)
-  gcr_params gp = *p;
+    return fail(ctx, GCR_ERR_HIP, "server set-up: %s", hipGetErrorString(e));
+  }
+  // rows past the live gallery stay zero (they are screened as padding)
+  fill_u32((unsigned*)s->X[0] + ng * d, 0u, (cap - ng) * d, s->mst);
+  for (const Operand* o : {&s->op0, &s->opL}) fill_u32(o->Xs + ng * o->ld, 0u, (o->npad - ng) * o->ld / 4, s->mst);
+  *out = s;
+  return GCR_OK;
+}
+
+// Workspace of the private context for a plan of `bytes`.
+std::string mctx_ws(gcr_server* s, size_t bytes) {
+  if (ensure_ws(s->mctx, bytes) != GCR_OK) return std::string("maintenance workspace: ") + gcr_last_error(s->mctx);
+  return "";
+}
+
+// Exact k nearest other items of gallery rows [r0, r1) among columns
+// [c0, c1) (run on the private context; kk <= k + 1 entries per row).
+std::string gallery_knn(gcr_server* s, int64_t n_prep, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int excl,
+                        int kk, int32_t* idx, float* dist) {
+  Arena dry;
+  KnnPlan kp;
+  plan_knn(dry, kp, s->prec, n_prep, s->d, r0, r1, c0, c1, kk, 0);
+  std::string e = mctx_ws(s, dry.off);
+  if (!e.empty()) return e;
+  Arena a1{(char*)s->mctx->ws, 0};
+  plan_knn(a1, kp, s->prec, n_prep, s->d, r0, r1, c0, c1, kk, 0);
+  run_knn(s->mctx, kp, s->X[0], s->d, nullptr, r0, r1, c0, c1, excl, kk, 0, idx, dist, nullptr, nullptr, s->mst);
+  return "";
+}
+
+// Graph, degrees, gallery-only rounds and screening operands of the live
+// gallery, from its lists.
+std::string refresh_gallery(gcr_server* s) {
+  const hipStream_t st = s->mst;
+  gcr_params gp = s->p;
   gp.alpha = 1.0f;
   gp.beta_same = gp.beta_cross = 1.0f;
-  {
-    Arena d1;
-    KnnPlan kp;
-    GraphTmp gt;
-    plan_knn(d1, kp, gp.precision, ng, d, 0, ng, 0, ng, gp.k, 0);
-    plan_graph_tmp(d1, gt, ng);
-    if (ensure_ws(ctx, d1.off) != GCR_OK) {
-      (void)hipStreamDestroy(st);
-      release(s);
-      return GCR_ERR_NOMEM;
-    }
-    Arena a1{(char*)ctx->ws, 0};
-    plan_knn(a1, kp, gp.precision, ng, d, 0, ng, 0, ng, gp.k, 0);
-    plan_graph_tmp(a1, gt, ng);
-    enqueue_build_graph(ctx, kp, gt, s->X[0], ng, d, nullptr, &gp, &s->g, st, false);
-    for (int t = 1; t <= s->L; ++t) enqueue_propagate(ctx, &s->g, s->X[t - 1], s->X[t], ng, d, st, gt.order);
-    fill_u32(s->max0, 0u, 2, st);
-    launch_screen_prep_rows(s->prec, s->X[0], 0, ng, nullptr, d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
-                            s->op0.rn, s->max0, st);
-    if (s->L > 0) {
-      fill_u32(s->maxLg, 0u, 2, st);
-      launch_screen_prep_rows(s->prec, s->X[s->L], 0, ng, nullptr, d, s->opL.Xs, s->opL.ld, s->opL.n2,
-                              s->opL.scale, s->opL.rn, s->maxLg, st);
-    }
-    // marks start clear; positions start in range, so a row marked in a
-    // request whose set overflowed still reads inside the slot (that
-    // request is reported as failed)
-    for (Slot& sl : s->slots) {
-      fill_u32(sl.touched, 0u, ng, st);
-      for (int t = 1; t <= s->L; ++t) {
-        fill_u32(sl.mark[t], 0u, ng, st);
-        fill_u32(sl.pos[t], 0u, ng, st);
-      }
-    }
-    e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e != hipSuccess) return bail(GCR_ERR_HIP, "gallery preparation", e);
+  Arena dry;
+  GraphTmp gt;
+  plan_graph_tmp(dry, gt, s->G);
+  std::string e = mctx_ws(s, dry.off);
+  if (!e.empty()) return e;
+  Arena a1{(char*)s->mctx->ws, 0};
+  plan_graph_tmp(a1, gt, s->G);
+  enqueue_graph_from_lists(s->mctx, gt, s->G, nullptr, &gp, &s->g, st);
+  for (int t = 1; t <= s->L; ++t) enqueue_propagate(s->mctx, &s->g, s->X[t - 1], s->X[t], s->G, s->d, st, gt.order);
+  fill_u32(s->max0, 0u, 2, st);
+  launch_screen_prep_rows(s->prec, s->X[0], 0, s->G, nullptr, s->d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
+                          s->op0.rn, s->max0, st);
+  if (s->L > 0) {
+    fill_u32(s->maxLg, 0u, 2, st);
+    launch_screen_prep_rows(s->prec, s->X[s->L], 0, s->G, nullptr, s->d, s->opL.Xs, s->opL.ld, s->opL.n2,
+                            s->opL.scale, s->opL.rn, s->maxLg, st);
   }
-  (void)hipStreamDestroy(st);
-  st = nullptr;
+  SRV_HIP(hipStreamSynchronize(st));
+  SRV_HIP(hipGetLastError());
+  return "";
+}
+
+// Slot state, streams and the worker thread (after the gallery is ready).
+std::string server_start(gcr_server* s) {
+  // marks start clear; positions start in range, so a row marked in a
+  // request whose set overflowed still reads inside the slot (that request
+  // is reported as failed)
   for (Slot& sl : s->slots) {
-    e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_q, (size_t)s->Rq * d * sizeof(float), hipHostMallocDefault);
-    if (e == hipSuccess)
-      e = hipHostMalloc((void**)&sl.h_idx, (size_t)s->Rq * s->K * sizeof(int32_t), hipHostMallocDefault);
-    if (e == hipSuccess)
-      e = hipHostMalloc((void**)&sl.h_dist, (size_t)s->Rq * s->K * sizeof(float), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_counts, 64 * sizeof(int), hipHostMallocDefault);
-    if (e != hipSuccess) return bail(GCR_ERR_HIP, "slot set-up", e);
+    fill_u32(sl.touched, 0u, s->Gcap, s->mst);
+    for (int t = 1; t <= s->L; ++t) {
+      fill_u32(sl.mark[t], 0u, s->Gcap, s->mst);
+      fill_u32(sl.pos[t], 0u, s->Gcap, s->mst);
+    }
+  }
+  std::string e = refresh_gallery(s);
+  if (!e.empty()) return e;
+  for (Slot& sl : s->slots) {
+    SRV_HIP(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+    SRV_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    SRV_HIP(hipHostMalloc((void**)&sl.h_q, (size_t)s->Rq * s->d * sizeof(float), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&sl.h_idx, (size_t)s->Rq * s->K * sizeof(int32_t), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&sl.h_dist, (size_t)s->Rq * s->K * sizeof(float), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&sl.h_counts, 64 * sizeof(int), hipHostMallocDefault));
     memset(sl.h_counts, 0, 64 * sizeof(int));
   }
   s->worker = std::thread(worker_main, s);
+  return "";
+}
+
+// Stop admitting requests and wait for the ones on the device.
+void pause_and_drain(gcr_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->paused = true;
+  s->cv_done.wait(lk, [&] {
+    for (const Slot& sl : s->slots)
+      if (sl.req) return false;
+    return true;
+  });
+}
+
+void resume(gcr_server* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->paused = false;
+  }
+  s->cv_work.notify_all();
+}
+
+std::string insert_rows(gcr_server* s, const float* rows, int32_t m) {
+  const hipStream_t st = s->mst;
+  const int64_t G0 = s->G, G1 = G0 + m;
+  const int k = s->k, d = s->d;
+  SRV_HIP(hipMemcpyAsync(s->X[0] + G0 * d, rows, (size_t)m * d * sizeof(float), hipMemcpyHostToDevice, st));
+  // the appended rows' lists over the whole gallery
+  std::string e = gallery_knn(s, G1, G0, G1, 0, G1, 1, k, s->g.idx + G0 * k, s->g.dist + G0 * k);
+  if (!e.empty()) return e;
+  // the old rows' nearest appended items, merged into their lists
+  const int km = (int)std::min<int64_t>(k, m);
+  e = gallery_knn(s, G1, 0, G0, G0, G1, 0, km, s->tmp_idx, s->tmp_dist);
+  if (!e.empty()) return e;
+  launch_merge_appended(G0, k, s->g.idx, s->g.dist, km, s->tmp_idx, s->tmp_dist, (int32_t)G0, st);
+  SRV_HIP(hipGetLastError());
+  s->G = G1;
+  return refresh_gallery(s);
+}
+
+std::string remove_rows(gcr_server* s, const std::vector<int32_t>& new_of_old, const std::vector<int32_t>& old_of_new) {
+  const hipStream_t st = s->mst;
+  const int64_t G0 = s->G, G1 = (int64_t)old_of_new.size();
+  const int k = s->k, d = s->d;
+  SRV_HIP(hipMemcpyAsync(s->map_a, new_of_old.data(), (size_t)G0 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  SRV_HIP(hipMemcpyAsync(s->map_b, old_of_new.data(), (size_t)G1 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  // lists renumbered (order kept: the renumbering is monotone)
+  fill_u32((unsigned*)s->mcount, 0u, 1, st);
+  launch_relabel_lists(G0, k, s->map_a, s->g.idx, s->g.dist, s->tmp_idx, s->tmp_dist, s->repair, s->mcount, st);
+  SRV_HIP(hipMemcpyAsync(s->g.idx, s->tmp_idx, (size_t)G1 * k * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  SRV_HIP(hipMemcpyAsync(s->g.dist, s->tmp_dist, (size_t)G1 * k * sizeof(float), hipMemcpyDeviceToDevice, st));
+  // features compacted through a staging copy past the gallery capacity
+  // (rows [Gcap, rows_total) belong to the idle slots), in pieces
+  const int64_t stage_rows = s->rows_total - s->Gcap;
+  for (int64_t r = 0; r < G1; r += stage_rows) {
+    const int64_t b = std::min<int64_t>(stage_rows, G1 - r);
+    launch_gather_rows(s->X[0], s->X[0] + s->Gcap * d, s->map_b + r, b, d, st);
+    SRV_HIP(hipMemcpyAsync(s->X[0] + r * d, s->X[0] + s->Gcap * d, (size_t)b * d * sizeof(float),
+                           hipMemcpyDeviceToDevice, st));
+  }
+  fill_u32((unsigned*)s->X[0] + G1 * d, 0u, (G0 - G1) * d, st);
+  int nrep = 0;
+  SRV_HIP(hipMemcpyAsync(&nrep, s->mcount, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRV_HIP(hipStreamSynchronize(st));
+  s->G = G1;
+  // lists that lost a neighbour: k + 1 nearest of a staged copy of the row
+  // (the copy finds the row itself), then the row itself dropped
+  for (int64_t r = 0; r < nrep; r += stage_rows) {
+    const int64_t b = std::min<int64_t>(stage_rows, nrep - r);
+    launch_gather_rows(s->X[0], s->X[0] + s->Gcap * d, s->repair + r, b, d, st);
+    std::string e = gallery_knn(s, s->Gcap + b, s->Gcap, s->Gcap + b, 0, G1, 0, k + 1, s->tmp_idx, s->tmp_dist);
+    if (!e.empty()) return e;
+    launch_drop_self(b, k, s->repair + r, s->tmp_idx, s->tmp_dist, s->g.idx, s->g.dist, st);
+    SRV_HIP(hipGetLastError());
+  }
+  fill_u32((unsigned*)s->X[0] + s->Gcap * d, 0u, std::min<int64_t>(stage_rows, std::max<int64_t>(G1, nrep)) * d, st);
+  return refresh_gallery(s);
+}
+
+const char kMagic[8] = {'G', 'C', 'R', 'S', 'R', 'V', '0', '1'};
+
+}  // namespace
+
+extern "C" {
+
+void gcr_server_config_default(gcr_server_config* c) {
+  if (!c) return;
+  c->slots = 4;
+  c->max_batch = 512;
+  c->max_recomputed = 65536;
+  c->gallery_capacity = 0;
+}
+
+gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_dtype, int64_t ng, int32_t d,
+                             const gcr_params* p, const gcr_server_config* cfg, gcr_server** out) {
+  if (!ctx || !out || !p) return GCR_ERR_INVALID;
+  *out = nullptr;
+  if (!gallery) return fail(ctx, GCR_ERR_INVALID, "gallery is NULL");
+  if (gallery_dtype != 0 && gallery_dtype != 1) return fail(ctx, GCR_ERR_INVALID, "gallery_dtype must be 0 or 1");
+  gcr_server* s = nullptr;
+  gcr_status st = server_new(ctx, p, cfg, ng, d, &s);
+  if (st != GCR_OK) return st;
+  // resident gallery: level-0 features as given (float32, or BF16 widened)
+  hipError_t e = hipSuccess;
+  if (gallery_dtype == 0)
+    e = hipMemcpyAsync(s->X[0], gallery, (size_t)ng * d * sizeof(float), hipMemcpyDeviceToDevice, s->mst);
+  else
+    launch_bf16_to_f32((const uint16_t*)gallery, s->X[0], ng * d, s->mst);
+  std::string err = e == hipSuccess ? "" : std::string("gallery copy: ") + hipGetErrorString(e);
+  // the gallery's kNN lists (fixed mode, one list, no camera weighting)
+  if (err.empty()) err = gallery_knn(s, ng, 0, ng, 0, ng, 1, s->k, s->g.idx, s->g.dist);
+  if (err.empty()) err = server_start(s);
+  if (!err.empty()) {
+    if (s->worker.joinable()) gcr_server_destroy(s);
+    else release(s);
+    return fail(ctx, GCR_ERR_HIP, "%s", err.c_str());
+  }
+  *out = s;
+  return GCR_OK;
+}
+
+gcr_status gcr_server_insert(gcr_server* s, const float* rows_host, int32_t m, int32_t* ids_out) {
+  if (!s) return GCR_ERR_INVALID;
+  if (!rows_host || m < 1) return sfail(s, GCR_ERR_INVALID, "rows must be a host array of m >= 1 rows");
+  std::lock_guard<std::mutex> mg(s->mut_mu);
+  if (s->G + m > s->Gcap)
+    return sfail(s, GCR_ERR_UNSUPPORTED, "inserting " + std::to_string(m) + " rows exceeds the gallery capacity of " +
+                                             std::to_string(s->Gcap));
+  if (s->next_id + m > (int64_t)INT32_MAX) return sfail(s, GCR_ERR_UNSUPPORTED, "external ids exhausted");
+  pause_and_drain(s);
+  (void)hipSetDevice(s->device);
+  const std::string e = insert_rows(s, rows_host, m);
+  if (e.empty()) {
+    for (int32_t t = 0; t < m; ++t) {
+      s->ext.push_back((int32_t)s->next_id);
+      if (ids_out) ids_out[t] = (int32_t)s->next_id;
+      ++s->next_id;
+    }
+  }
+  resume(s);
+  return e.empty() ? GCR_OK : sfail(s, GCR_ERR_HIP, e);
+}
+
+gcr_status gcr_server_remove(gcr_server* s, const int32_t* ids_host, int32_t m) {
+  if (!s) return GCR_ERR_INVALID;
+  if (!ids_host || m < 1) return sfail(s, GCR_ERR_INVALID, "ids must be a host array of m >= 1 ids");
+  std::lock_guard<std::mutex> mg(s->mut_mu);
+  const int64_t G0 = s->G;
+  std::vector<int32_t> new_of_old(G0, 0);
+  for (int32_t t = 0; t < m; ++t) {
+    auto it = std::lower_bound(s->ext.begin(), s->ext.end(), ids_host[t]);
+    if (it == s->ext.end() || *it != ids_host[t])
+      return sfail(s, GCR_ERR_INVALID, "id " + std::to_string(ids_host[t]) + " is not in the gallery");
+    new_of_old[it - s->ext.begin()] = -1;
+  }
+  std::vector<int32_t> old_of_new;
+  old_of_new.reserve(G0);
+  for (int64_t i = 0; i < G0; ++i)
+    if (new_of_old[i] == 0) {
+      new_of_old[i] = (int32_t)old_of_new.size();
+      old_of_new.push_back((int32_t)i);
+    }
+  if (old_of_new.size() < 2) return sfail(s, GCR_ERR_INVALID, "a gallery keeps at least 2 items");
+  pause_and_drain(s);
+  (void)hipSetDevice(s->device);
+  const std::string e = remove_rows(s, new_of_old, old_of_new);
+  if (e.empty()) {
+    std::vector<int32_t> ext;
+    ext.reserve(old_of_new.size());
+    for (int32_t o : old_of_new) ext.push_back(s->ext[o]);
+    s->ext.swap(ext);
+  }
+  resume(s);
+  return e.empty() ? GCR_OK : sfail(s, GCR_ERR_HIP, e);
+}
+
+gcr_status gcr_server_gallery_ids(gcr_server* s, int32_t* ids_host, int64_t capacity, int64_t* count) {
+  if (!s || !count) return GCR_ERR_INVALID;
+  std::lock_guard<std::mutex> mg(s->mut_mu);
+  *count = (int64_t)s->ext.size();
+  if (ids_host) {
+    if (capacity < *count) return sfail(s, GCR_ERR_INVALID, "ids buffer too small");
+    memcpy(ids_host, s->ext.data(), s->ext.size() * sizeof(int32_t));
+  }
+  return GCR_OK;
+}
+
+gcr_status gcr_server_save(gcr_server* s, const char* path) {
+  if (!s) return GCR_ERR_INVALID;
+  if (!path) return sfail(s, GCR_ERR_INVALID, "path is NULL");
+  std::lock_guard<std::mutex> mg(s->mut_mu);
+  pause_and_drain(s);
+  (void)hipSetDevice(s->device);
+  const int64_t G = s->G;
+  const int k = s->k, d = s->d;
+  std::vector<float> X((size_t)G * d), dist((size_t)G * k);
+  std::vector<int32_t> idx((size_t)G * k);
+  hipError_t e = hipMemcpy(X.data(), s->X[0], X.size() * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(idx.data(), s->g.idx, idx.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(dist.data(), s->g.dist, dist.size() * sizeof(float), hipMemcpyDeviceToHost);
+  resume(s);
+  if (e != hipSuccess) return sfail(s, GCR_ERR_HIP, std::string("save: ") + hipGetErrorString(e));
+  FILE* f = fopen(path, "wb");
+  if (!f) return sfail(s, GCR_ERR_INVALID, std::string("cannot open ") + path + " for writing");
+  const int32_t hdr[4] = {1, d, k, 0};
+  const int64_t sizes[2] = {G, s->next_id};
+  bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+            fwrite(sizes, sizeof sizes, 1, f) == 1 && fwrite(&s->p, sizeof s->p, 1, f) == 1 &&
+            fwrite(s->ext.data(), sizeof(int32_t), (size_t)G, f) == (size_t)G &&
+            fwrite(X.data(), sizeof(float), X.size(), f) == X.size() &&
+            fwrite(idx.data(), sizeof(int32_t), idx.size(), f) == idx.size() &&
+            fwrite(dist.data(), sizeof(float), dist.size(), f) == dist.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? GCR_OK : sfail(s, GCR_ERR_INVALID, std::string("write to ") + path + " failed");
+}
+
+gcr_status gcr_server_load(gcr_ctx* ctx, const char* path, const gcr_server_config* cfg, gcr_server** out) {
+  if (!ctx || !out) return GCR_ERR_INVALID;
+  *out = nullptr;
+  if (!path) return fail(ctx, GCR_ERR_INVALID, "path is NULL");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(ctx, GCR_ERR_INVALID, "cannot open %s", path);
+  char magic[8];
+  int32_t hdr[4];
+  int64_t sizes[2];
+  gcr_params p;
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMagic, 8) == 0 && fread(hdr, sizeof hdr, 1, f) == 1 &&
+            hdr[0] == 1 && fread(sizes, sizeof sizes, 1, f) == 1 && fread(&p, sizeof p, 1, f) == 1;
+  const int d = ok ? hdr[1] : 0, k = ok ? hdr[2] : 0;
+  const int64_t G = ok ? sizes[0] : 0;
+  ok = ok && d > 0 && d <= 2048 && k == p.k && G >= 2 && G <= ((int64_t)1 << 30) && sizes[1] >= G &&
+       sizes[1] <= (int64_t)INT32_MAX;
+  std::vector<int32_t> ext, idx;
+  std::vector<float> X, dist;
+  if (ok) {
+    ext.resize((size_t)G);
+    X.resize((size_t)G * d);
+    idx.resize((size_t)G * k);
+    dist.resize((size_t)G * k);
+    ok = fread(ext.data(), sizeof(int32_t), ext.size(), f) == ext.size() &&
+         fread(X.data(), sizeof(float), X.size(), f) == X.size() &&
+         fread(idx.data(), sizeof(int32_t), idx.size(), f) == idx.size() &&
+         fread(dist.data(), sizeof(float), dist.size(), f) == dist.size();
+  }
+  fclose(f);
+  for (size_t i = 1; ok && i < ext.size(); ++i) ok = ext[i] > ext[i - 1];
+  for (size_t i = 0; ok && i < idx.size(); ++i) ok = idx[i] >= -1 && idx[i] < G;
+  if (!ok) return fail(ctx, GCR_ERR_INVALID, "%s is not a saved server state", path);
+  gcr_server* s = nullptr;
+  gcr_status st = server_new(ctx, &p, cfg, G, d, &s);
+  if (st != GCR_OK) return st;
+  s->ext = ext;
+  s->next_id = sizes[1];
+  hipError_t e = hipMemcpy(s->X[0], X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->g.idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->g.dist, dist.data(), dist.size() * sizeof(float), hipMemcpyHostToDevice);
+  std::string err = e == hipSuccess ? "" : std::string("load: ") + hipGetErrorString(e);
+  if (err.empty()) err = server_start(s);
+  if (!err.empty()) {
+    if (s->worker.joinable()) gcr_server_destroy(s);
+    else release(s);
+    return fail(ctx, GCR_ERR_HIP, "%s", err.c_str());
+  }
   *out = s;
   return GCR_OK;
 }
@@ -620,6 +927,8 @@ gcr_status gcr_server_get_stats(gcr_server* s, gcr_server_stats* out) {
   if (!s || !out) return GCR_ERR_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->stats;
+  out->gallery_size = s->G;
+  out->gallery_capacity = s->Gcap;
   return GCR_OK;
 }
 

@@ -340,10 +340,22 @@ class Server:
     wait() returns (indices int32 [b, K], distances float32 [b, K]).
     """
 
-    def __init__(self, ctx: Context, gallery: torch.Tensor, p: Params, slots: int = 4, max_batch: int = 512,
-                 max_recomputed: int = 65536):
+    def __init__(self, ctx: Context, gallery: Optional[torch.Tensor], p: Optional[Params], slots: int = 4,
+                 max_batch: int = 512, max_recomputed: int = 65536, gallery_capacity: int = 0,
+                 _load_path: Optional[str] = None):
         self.ctx = ctx
         self.lib = ctx.lib
+        cfg = L.GcrServerConfig(slots, max_batch, max_recomputed, gallery_capacity)
+        if _load_path is not None:
+            h = C.c_void_p()
+            st = self.lib.gcr_server_load(ctx.h, _load_path.encode(), C.byref(cfg), C.byref(h))
+            if st != L.GCR_OK:
+                raise GcrError(f"gcr_server_load failed ({L.STATUS_NAMES.get(st, st)}): "
+                               f"{self.lib.gcr_last_error(ctx.h).decode()}")
+            self.h = h
+            self._b = {}
+            self._read_shape(_load_path)
+            return
         if gallery.device != ctx.device or not gallery.is_contiguous():
             raise ValueError("gallery must be a contiguous tensor on the context's device")
         if gallery.dtype == torch.float32:
@@ -354,7 +366,6 @@ class Server:
             raise TypeError("gallery must be float32 or BF16")
         ng, d = gallery.shape
         self.d, self.K = d, p.topk_out
-        cfg = L.GcrServerConfig(slots, max_batch, max_recomputed)
         h = C.c_void_p()
         pc = p.c()
         st = self.lib.gcr_server_create(ctx.h, _ptr(gallery), dtype, ng, d, C.byref(pc), C.byref(cfg), C.byref(h))
@@ -397,6 +408,59 @@ class Server:
 
     def query(self, q):
         return self.wait(self.submit(q))
+
+    @classmethod
+    def load(cls, ctx: Context, path: str, slots: int = 4, max_batch: int = 512, max_recomputed: int = 65536,
+             gallery_capacity: int = 0) -> "Server":
+        """A server started from a state written by save()."""
+        return cls(ctx, None, None, slots, max_batch, max_recomputed, gallery_capacity, _load_path=path)
+
+    def _read_shape(self, path: str):
+        import struct
+
+        with open(path, "rb") as f:
+            head = f.read(8 + 16 + 16 + C.sizeof(L.GcrParams))
+        _, d, _, _ = struct.unpack_from("<4i", head, 8)
+        pr = L.GcrParams.from_buffer_copy(head[8 + 16 + 16:])
+        self.d, self.K = d, pr.topk_out
+
+    def insert(self, rows):
+        """Append host float32 rows [m, d]; returns their ids (int32 [m])."""
+        import numpy as np
+
+        rows = np.ascontiguousarray(rows, dtype=np.float32)
+        if rows.ndim != 2 or rows.shape[1] != self.d:
+            raise ValueError(f"rows must be [m, {self.d}]")
+        ids = np.empty(rows.shape[0], dtype=np.int32)
+        st = self.lib.gcr_server_insert(self.h, rows.ctypes.data, rows.shape[0], ids.ctypes.data)
+        if st != L.GCR_OK:
+            raise GcrError(f"gcr_server_insert failed ({L.STATUS_NAMES.get(st, st)}): {self._err()}")
+        return ids
+
+    def remove(self, ids):
+        import numpy as np
+
+        ids = np.ascontiguousarray(ids, dtype=np.int32).ravel()
+        st = self.lib.gcr_server_remove(self.h, ids.ctypes.data, ids.shape[0])
+        if st != L.GCR_OK:
+            raise GcrError(f"gcr_server_remove failed ({L.STATUS_NAMES.get(st, st)}): {self._err()}")
+
+    def ids(self):
+        """Live gallery ids in row order (increasing)."""
+        import numpy as np
+
+        n = C.c_int64()
+        self.lib.gcr_server_gallery_ids(self.h, None, 0, C.byref(n))
+        out = np.empty(n.value, dtype=np.int32)
+        st = self.lib.gcr_server_gallery_ids(self.h, out.ctypes.data, n.value, C.byref(n))
+        if st != L.GCR_OK:
+            raise GcrError(f"gcr_server_gallery_ids failed: {self._err()}")
+        return out
+
+    def save(self, path: str):
+        st = self.lib.gcr_server_save(self.h, path.encode())
+        if st != L.GCR_OK:
+            raise GcrError(f"gcr_server_save failed ({L.STATUS_NAMES.get(st, st)}): {self._err()}")
 
     def stats(self) -> dict:
         s = L.GcrServerStats()

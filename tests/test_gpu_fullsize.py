@@ -131,13 +131,31 @@ def test_serving_full_size():
     gi, gd = host(gidx), host(gdist)
     rows = sample(vals.shape[0], 16, 7)
     check_knn_rows(gi[rows], gd[rows], vals, rows, 20)
-    srv = Server(ctx, g, p, slots=2, max_batch=512, max_recomputed=65536)
+    srv = Server(ctx, g, p, slots=2, max_batch=512, max_recomputed=65536, gallery_capacity=vals.shape[0] + 500)
     trace = datagen.serving_trace(centres, 3, 1000.0, seed=11)
     op = O.Params(k=20, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
     try:
         for _, Q, _ in trace:
             ri, rd = srv.query(Q)
             check_request(ri, rd, vals, gi.astype(np.int64), gd.astype(np.float64), Q, op, 100)
+        # 500 items in, 500 out: the same answers as a server built on the
+        # resulting gallery
+        rng = np.random.default_rng(12)
+        new = datagen._unit_rows_f32(centres[rng.integers(0, len(centres), 500)]
+                                     + 0.6 * rng.standard_normal((500, vals.shape[1])))
+        srv.insert(new)
+        srv.remove(rng.choice(vals.shape[0], 500, replace=False))
+        live = srv.ids()
+        Xlive = np.concatenate([vals, new])[live]
+        fresh = Server(ctx, dev(Xlive), p, slots=1, max_batch=512, max_recomputed=65536)
+        try:
+            for _, Q, _ in trace[:2]:
+                a_i, a_d = srv.query(Q)
+                b_i, b_d = fresh.query(Q)
+                assert np.array_equal(a_i, np.where(b_i >= 0, live[np.maximum(b_i, 0)], -1))
+                assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
+        finally:
+            fresh.close()
     finally:
         srv.close()
     ctx.close()

@@ -1,0 +1,156 @@
+"""Mutable serving gallery: after inserts and removals a server answers
+bitwise like a server created on the resulting gallery (items in id order),
+and both match the FP64 oracle's serving semantics; saved state reloads to
+the same answers."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gcr_oracle as O
+from paper_2306_08792_amd import datagen
+from paper_2306_08792_amd.gcr import BF16, FP32, Context, GcrError, Params, Server
+
+from test_gpu_serving import check_request, gallery_and_queries, oracle_gallery_lists
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def same_answers(srv, ref, ref_ids, reqs):
+    """srv's results equal ref's with ref's row indices mapped to ids."""
+    for Q in reqs:
+        a_i, a_d = srv.query(Q)
+        b_i, b_d = ref.query(Q)
+        mapped = np.where(b_i >= 0, ref_ids[np.maximum(b_i, 0)], -1)
+        assert np.array_equal(a_i, mapped)
+        assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
+
+
+@pytest.mark.parametrize("prec", [BF16, FP32])
+def test_insert_remove_equals_fresh_server(ctx, prec):
+    print(f"mutable gallery prec={prec}", flush=True)
+    Xall, reqs = gallery_and_queries(seed=7, n_ids=160, per=20, nreq=4, sizes=(1, 9, 33, 64))
+    rng = np.random.default_rng(7)
+    k, K = 8, 10
+    p = Params(k=k, rounds=2, gamma=0.2, topk_out=K, precision=prec, rebuild_each_round=False)
+    srv = Server(ctx, torch.from_numpy(Xall[:2500]).cuda(), p, slots=2, max_batch=64, max_recomputed=3200,
+                 gallery_capacity=3200)
+    try:
+        ids1 = srv.insert(Xall[2500:2700])
+        assert np.array_equal(ids1, np.arange(2500, 2700))
+        gone = np.concatenate([rng.choice(2500, 120, replace=False), rng.choice(np.arange(2500, 2700), 30,
+                                                                                  replace=False)])
+        srv.remove(np.concatenate([gone, gone[:5]]))  # repeats are allowed
+        ids2 = srv.insert(Xall[2700:2900])
+        assert np.array_equal(ids2, np.arange(2700, 2900))
+        live = srv.ids()
+        assert np.array_equal(live, np.setdiff1d(np.arange(2900), gone))
+        st = srv.stats()
+        assert st["gallery_size"] == len(live) and st["gallery_capacity"] == 3200
+        Xlive = np.ascontiguousarray(Xall[live])
+        fresh = Server(ctx, torch.from_numpy(Xlive).cuda(), p, slots=2, max_batch=64, max_recomputed=3200)
+        try:
+            same_answers(srv, fresh, live, reqs)
+        finally:
+            fresh.close()
+        # and the oracle's serving semantics on the live gallery
+        op = O.Params(k=k, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
+        g_idx, g_dist = oracle_gallery_lists(Xlive, k)
+        for Q in reqs[:2]:
+            gi, gd = srv.query(Q)
+            pos = np.searchsorted(live, gi)
+            check_request(np.where(gi >= 0, pos, -1), gd, Xlive, g_idx, g_dist, Q, op, K)
+    finally:
+        srv.close()
+
+
+def test_remove_everything_a_row_knows(ctx):
+    """Removing all neighbours of some rows (lists that empty out entirely)
+    and a whole cluster, then inserting it back under new ids."""
+    print("mutable gallery: heavy removal", flush=True)
+    Xall, reqs = gallery_and_queries(seed=8, n_ids=60, per=25, nreq=3, sizes=(4, 16, 40))
+    k = 6
+    p = Params(k=k, rounds=1, gamma=0.2, topk_out=12, precision=BF16, rebuild_each_round=False)
+    n = Xall.shape[0]
+    srv = Server(ctx, torch.from_numpy(Xall).cuda(), p, slots=2, max_batch=64, max_recomputed=n, gallery_capacity=n)
+    try:
+        g_idx, _ = oracle_gallery_lists(Xall, k)
+        gone = np.unique(np.concatenate([g_idx[5], g_idx[77], np.arange(100, 125)]))
+        srv.remove(gone)
+        back = srv.insert(Xall[100:125])
+        live = srv.ids()
+        Xmap = {int(i): Xall[i] for i in range(n)}
+        for j, i in enumerate(back):
+            Xmap[int(i)] = Xall[100 + j]
+        Xlive = np.stack([Xmap[int(i)] for i in live])
+        fresh = Server(ctx, torch.from_numpy(Xlive).cuda(), p, slots=2, max_batch=64, max_recomputed=n)
+        try:
+            same_answers(srv, fresh, live, reqs)
+        finally:
+            fresh.close()
+    finally:
+        srv.close()
+
+
+def test_save_load_roundtrip(ctx):
+    print("mutable gallery: save / load", flush=True)
+    Xall, reqs = gallery_and_queries(seed=9, n_ids=100, per=20, nreq=3, sizes=(3, 20, 50))
+    p = Params(k=8, rounds=2, gamma=0.2, topk_out=10, precision=BF16, rebuild_each_round=False)
+    srv = Server(ctx, torch.from_numpy(Xall[:1800]).cuda(), p, slots=2, max_batch=64, max_recomputed=2000,
+                 gallery_capacity=2000)
+    try:
+        srv.insert(Xall[1800:1900])
+        srv.remove(np.arange(0, 1800, 7))
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "gallery.gcr")
+            srv.save(path)
+            two = Server.load(ctx, path, slots=3, max_batch=64, max_recomputed=2000, gallery_capacity=2000)
+            try:
+                assert np.array_equal(two.ids(), srv.ids())
+                for Q in reqs:
+                    a = srv.query(Q)
+                    b = two.query(Q)
+                    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+                # the loaded server keeps growing from the next unused id
+                assert np.array_equal(two.insert(Xall[1900:1910]), np.arange(1900, 1910))
+            finally:
+                two.close()
+            with open(os.path.join(td, "junk.gcr"), "wb") as f:
+                f.write(b"not a saved server")
+            with pytest.raises(GcrError, match="INVALID"):
+                Server.load(ctx, os.path.join(td, "junk.gcr"))
+    finally:
+        srv.close()
+
+
+def test_mutation_errors_and_inflight_requests(ctx):
+    print("mutable gallery: errors", flush=True)
+    Xall, reqs = gallery_and_queries(seed=10, n_ids=50, per=20, nreq=3, sizes=(5, 30, 60))
+    p = Params(k=8, rounds=2, gamma=0.2, topk_out=10, precision=BF16, rebuild_each_round=False)
+    with pytest.raises(GcrError, match="INVALID"):
+        Server(ctx, torch.from_numpy(Xall[:900]).cuda(), p, gallery_capacity=800)
+    srv = Server(ctx, torch.from_numpy(Xall[:900]).cuda(), p, slots=2, max_batch=64, max_recomputed=1000,
+                 gallery_capacity=950)
+    try:
+        with pytest.raises(GcrError, match="UNSUPPORTED"):
+            srv.insert(Xall[900:1000])
+        with pytest.raises(GcrError, match="INVALID"):
+            srv.remove([3, 5000])
+        assert len(srv.ids()) == 900  # nothing changed
+        tickets = [srv.submit(Q) for Q in reqs]
+        srv.insert(Xall[900:950])
+        for t in tickets:
+            ri, rd = srv.wait(t)
+            assert np.all((ri >= 0) & (ri < 950))
+        assert srv.stats()["gallery_size"] == 950
+    finally:
+        srv.close()
