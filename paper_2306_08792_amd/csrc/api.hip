@@ -243,8 +243,12 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   }
   if (prev0 && r0 == 0 && c0 == 0 && r1 == c1 && (k1 == 0 || prev1)) {
     TimedScope ts(c, 1, st);
-    launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, kp.rn, (const float*)kp.maxn2,
-                           sa.eps_s, sa.eps_n, kp.seed, order, st);
+    if (kp.prec == GCR_PREC_BF16 && (kp.ld == 1024 || kp.ld == 2048 || kp.ld == 4096))
+      launch_seed_thresholds_bf16(kp.Xs, kp.ld, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, kp.rn,
+                                  (const float*)kp.maxn2, sa.eps_s, sa.eps_n, kp.seed, order, st);
+    else
+      launch_seed_thresholds(X, d, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, kp.rn, (const float*)kp.maxn2,
+                             sa.eps_s, sa.eps_n, kp.seed, order, st);
     sa.thr_init = kp.seed;
   }
   {

@@ -76,6 +76,11 @@ void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx
                             int k1, const float* n2, const float* rn, const float* maxn2, float eps_s,
                             float eps_n, float* out, const int32_t* order, hipStream_t st);
 int sim_topk_tile_cols();
+// The same bounds from a BF16 screening operand with ld in {1024, 2048,
+// 4096} bytes (its rows zero past d).
+void launch_seed_thresholds_bf16(const uint8_t* Xs, int64_t ld, int64_t n, const int32_t* idx0, int k0,
+                                 const int32_t* idx1, int k1, const float* n2, const float* rn, const float* maxn2,
+                                 float eps_s, float eps_n, float* out, const int32_t* order, hipStream_t st);
 void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st);
 
 // ---- refine.hip : union of split candidates, exact re-score, selection

@@ -1047,6 +1047,90 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
   out[w] = res;
 }
 
+// The same bound from the BF16 screening operand (half the bytes of the
+// float32 rows): every member's screened key n2_j - 2 x~_i.x~_j lies within
+// E of its exact key (screen_margin holds for any float32 summation order),
+// so the largest member key is at most the largest screened key + E, and a
+// true neighbour's screened key in the sweep is at most that + E again.
+// NV: 16-byte operand parts per lane (ld = 1024 NV bytes).
+template <int NV>
+__global__ __launch_bounds__(256) void seed_thresholds_bf16_kernel(const uint8_t* __restrict__ Xs, int64_t ld,
+                                                                   int64_t n, const int32_t* __restrict__ idx0,
+                                                                   int k0, const int32_t* __restrict__ idx1, int k1,
+                                                                   const float* __restrict__ n2,
+                                                                   const float* __restrict__ rn,
+                                                                   const float* __restrict__ maxn2, float eps_s,
+                                                                   float eps_n, float* __restrict__ out,
+                                                                   const int32_t* __restrict__ order) {
+  const int nl = idx1 ? 2 : 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t p = xcd_position(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (p >= n * nl) return;
+  const int64_t prow = p / nl;
+  const int L = (int)(p - prow * nl);
+  const int64_t row = order ? (int64_t)order[prow] : prow;
+  const int kk = L == 0 ? k0 : k1;
+  const int32_t* lst = (L == 0 ? idx0 : idx1) + row * kk;
+  typedef uint32_t __attribute__((ext_vector_type(4))) u32x4;
+  u32x4 xr[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) xr[q] = *(const u32x4*)(Xs + row * ld + (q * 64 + lane) * 16);
+  auto dot = [&](const u32x4 (&y)[NV]) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint32_t a = xr[q][c], b = y[q][c];
+        s = fmaf(__uint_as_float(a << 16), __uint_as_float(b << 16), s);
+        s = fmaf(__uint_as_float(a & 0xffff0000u), __uint_as_float(b & 0xffff0000u), s);
+      }
+    }
+    return wave_sum(s);
+  };
+  float kmax = -INFINITY;
+  int valid = 0;
+  for (int t = 0; t < kk; t += 2) {
+    const int32_t ja = lst[t];
+    if (ja < 0) break;
+    const int32_t jb0 = t + 1 < kk ? lst[t + 1] : -1;
+    const int32_t jb = jb0 >= 0 ? jb0 : ja;
+    u32x4 ya[NV], yb[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      ya[q] = *(const u32x4*)(Xs + (int64_t)ja * ld + (q * 64 + lane) * 16);
+      yb[q] = *(const u32x4*)(Xs + (int64_t)jb * ld + (q * 64 + lane) * 16);
+    }
+    kmax = fmaxf(kmax, n2[ja] - 2.0f * dot(ya));
+    ++valid;
+    if (jb0 < 0) break;
+    kmax = fmaxf(kmax, n2[jb] - 2.0f * dot(yb));
+    ++valid;
+  }
+  if (lane != 0) return;
+  float res = INFINITY;
+  if (kk > 0 && valid == kk) {
+    const float mx = *maxn2, n2r = n2[row];
+    const float E = screen_margin(n2r, rn[row], mx, maxn2[1], eps_s, eps_n);
+    res = kmax + 3.0f * E + 4e-7f * (fabsf(kmax) + n2r + 1.0f);
+  }
+  out[row * nl + L] = res;
+}
+
+void launch_seed_thresholds_bf16(const uint8_t* Xs, int64_t ld, int64_t n, const int32_t* idx0, int k0,
+                                 const int32_t* idx1, int k1, const float* n2, const float* rn, const float* maxn2,
+                                 float eps_s, float eps_n, float* out, const int32_t* order, hipStream_t st) {
+  const int nl = idx1 ? 2 : 1;
+  const int64_t waves = n * nl;
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define GCR_SEED16(V) hipLaunchKernelGGL(seed_thresholds_bf16_kernel<V>, grid, block, 0, st, Xs, ld, n, idx0, k0, \
+                                         idx1, k1, n2, rn, maxn2, eps_s, eps_n, out, order)
+  if (ld == 4096) GCR_SEED16(4);
+  else if (ld == 2048) GCR_SEED16(2);
+  else GCR_SEED16(1);
+#undef GCR_SEED16
+}
+
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,
                             int k1, const float* n2, const float* rn, const float* maxn2, float eps_s,
                             float eps_n, float* out, const int32_t* order, hipStream_t st) {
