@@ -257,8 +257,9 @@ __device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk,
 template <int PREC, int NL, int E>
 __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ float col_n2[BN], col_sc[BN];
-  __shared__ int col_cam[BN];
+  __shared__ __align__(16) float col_n2[BN];
+  __shared__ __align__(16) float col_sc[BN];
+  __shared__ __align__(16) int col_cam[BN];
   __shared__ float row_thr[NL][BM];
   __shared__ int row_cnt[NL][BM];
   __shared__ float row_twoE[BM], row_sc[BM];
@@ -421,32 +422,49 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     // per row and list, the mask of entries under the admission threshold:
     // bit cb * 16 + i of pend[rb2][L]
     uint64_t pend[2][NL];
+    float t0r[2], t1r[2], rsr[2];
+    int rcr[2], selfr[2];
+    bool rvr[2];
 #pragma unroll
     for (int rb2 = 0; rb2 < 2; ++rb2) {
       const int lr = wr + 32 * rb2 + l32;
-      const float t0 = row_thr[0][lr];
-      const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
-      const float rs = row_sc[lr];
-      const int rc = row_cam[lr];
-      const bool rvalid = row0 + lr < a.r1;
+      t0r[rb2] = row_thr[0][lr];
+      t1r[rb2] = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
+      rsr[rb2] = row_sc[lr];
+      rcr[rb2] = row_cam[lr];
+      rvr[rb2] = row0 + lr < a.r1;
       // column offset (within the tile) of this row's own column, if any
       const int64_t selfc = row0 + lr - ct0;
-      const int selfoff = (a.exclude_self && selfc >= 0 && selfc < BN) ? (int)selfc : -1;
+      selfr[rb2] = (a.exclude_self && selfc >= 0 && selfc < BN) ? (int)selfc : -1;
 #pragma unroll
       for (int L = 0; L < NL; ++L) pend[rb2][L] = 0ull;
+    }
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < 4; ++cb) {
+      // the block's 16 columns of this lane are four runs of four: read
+      // them as vectors once for both row blocks
+      f32x4 n2v[4], scv[4];
+      i32x4 camv[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int c4 = lcol + 32 * cb + 8 * g;
+        n2v[g] = *(const f32x4*)&col_n2[c4];
+        if (NL > 1) camv[g] = *(const i32x4*)&col_cam[c4];
+        if (PREC == GCR_PREC_FP8) scv[g] = *(const f32x4*)&col_sc[c4];
+      }
+#pragma unroll
+      for (int rb2 = 0; rb2 < 2; ++rb2) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int lc = lcol + 32 * cb + 8 * (i >> 2) + (i & 3);
           float sv = acc[cb][rb2][i];
-          if (PREC == GCR_PREC_FP8) sv = sv * (rs * col_sc[lc]);
-          const bool valid = rvalid && lc != selfoff;
-          const float key = valid ? col_n2[lc] - 2.0f * sv : INFINITY;
+          if (PREC == GCR_PREC_FP8) sv = sv * (rsr[rb2] * scv[i >> 2][i & 3]);
+          const bool valid = rvr[rb2] && lc != selfr[rb2];
+          const float key = valid ? n2v[i >> 2][i & 3] - 2.0f * sv : INFINITY;
           acc[cb][rb2][i] = key;
           const uint64_t bit = 1ull << (cb * 16 + i);
-          if (key <= t0) pend[rb2][0] |= bit;
-          if (NL > 1 && col_cam[lc] != rc && key <= t1) pend[rb2][NL - 1] |= bit;
+          if (key <= t0r[rb2]) pend[rb2][0] |= bit;
+          if (NL > 1 && camv[i >> 2][i & 3] != rcr[rb2] && key <= t1r[rb2]) pend[rb2][NL - 1] |= bit;
         }
       }
     }
