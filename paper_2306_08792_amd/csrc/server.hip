@@ -684,7 +684,6 @@ std::string remove_rows(gcr_server* s, const std::vector<int32_t>& new_of_old, c
     launch_drop_self(b, k, s->repair + r, s->tmp_idx, s->tmp_dist, s->g.idx, s->g.dist, st);
     SRV_HIP(hipGetLastError());
   }
-  fill_u32((unsigned*)s->X[0] + s->Gcap * d, 0u, std::min<int64_t>(stage_rows, std::max<int64_t>(G1, nrep)) * d, st);
   return refresh_gallery(s);
 }
 
