@@ -137,7 +137,7 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   if (tid == 0) s_M = 0;
   __syncthreads();
   int mine = 0;
-  for (int t = tid; t < T; t += RT) mine += cand_key(U[t]) <= th ? 1 : 0;
+  for (int t = tid; t < T; t += RT) mine += (cand_key(U[t]) <= th && cand_key(U[t]) < INFINITY) ? 1 : 0;
   if (mine) atomicAdd(&s_M, mine);
   __syncthreads();
   const int M = s_M;  // a prefix of the sorted union
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
   for (int e0 = 0; e0 < T; e0 += 64) {
     const int e = e0 + lane;
     const uint64_t v = e < T ? U[e] : GCR_EMPTY;
-    const bool keep = e < T && (uint32_t)(v >> 32) <= tho;
+    const bool keep = e < T && (uint32_t)(v >> 32) <= tho && cand_key(v) < INFINITY;
     const uint64_t bal = __ballot(keep);
     const int pos = M + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
     if (keep && pos < WR_MAX) Mc[pos] = cand_col(v);
@@ -839,7 +839,7 @@ __global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
     const float e32 = screen_margin(a.n2[row], 0.f, a.maxn2[0], 0.f, a.eps32, a.eps_n);
     const float th = (T >= kk && kk > 0) ? cand_key(U[kk - 1]) + 2.0f * e32 : INFINITY;
     int mine = 0;
-    for (int t = tid; t < T; t += RT) mine += cand_key(U[t]) <= th ? 1 : 0;
+    for (int t = tid; t < T; t += RT) mine += (cand_key(U[t]) <= th && cand_key(U[t]) < INFINITY) ? 1 : 0;
     if (mine) atomicAdd(&s_M, mine);
     __syncthreads();
     const int M = s_M;

@@ -428,8 +428,11 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
 #pragma unroll
     for (int rb2 = 0; rb2 < 2; ++rb2) {
       const int lr = wr + 32 * rb2 + l32;
-      t0r[rb2] = row_thr[0][lr];
-      t1r[rb2] = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
+      // thresholds clamped to the largest finite float: ineligible entries
+      // (padding columns, the row itself) carry an infinite key and are
+      // never admitted, not even under an infinite threshold
+      t0r[rb2] = fminf(row_thr[0][lr], 3.40282347e38f);
+      t1r[rb2] = NL > 1 ? fminf(row_thr[NL - 1][lr], 3.40282347e38f) : -INFINITY;
       rsr[rb2] = row_sc[lr];
       rcr[rb2] = row_cam[lr];
       rvr[rb2] = row0 + lr < a.r1;

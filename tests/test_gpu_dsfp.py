@@ -159,3 +159,30 @@ def test_dsfp_errors(ctx):
         ctx.dsfp(X, idx[:, :4].contiguous(), Params(k=4), out=X)
     with pytest.raises(GcrError, match="UNSUPPORTED"):
         ctx.rerank_local(X, 5, Params(k=60))
+
+
+def test_dsfp_on_padded_library_lists(ctx):
+    """Fewer rows than k + 1: the library's lists carry -1 padding, which adds
+    nothing to the local sets (every node's local set is the whole set)."""
+    print("dsfp padded lists", flush=True)
+    X = datagen.random_unit(9, 40, seed=31)
+    p = Params(k=12, gamma=0.4, rounds=2, precision=FP32)
+    Xd = dev(X)
+    idx, _ = ctx.knn(Xd, p)
+    assert np.all(host(idx)[:, 8:] == -1)
+    Y = ctx.dsfp(Xd, idx, p)
+    Yo = O.dsfp(X, O.Params(k=12, gamma=0.4, rounds=2, normalize_input=False), host(idx))
+    check_features(host(Y), Yo, what="padded lists")
+    # every local set is the complete set: global GCR with a fixed graph
+    ref = O.gcr(X, O.Params(k=8, gamma=0.4, rounds=2, rebuild_each_round=False))["X"][-1]
+    check_features(host(Y), ref, what="complete local sets")
+
+
+def test_rerank_local_single_query(ctx):
+    print("rerank_local single query", flush=True)
+    X, _ = datagen.clustered(20, 10, 96, 0.5, seed=32)
+    p = Params(k=6, gamma=0.3, rounds=1, precision=BF16, topk_out=5)
+    out = ctx.rerank_local(dev(X), 1, p, dense=True, topk=True, keep_features=True)
+    Do, XTo = O.gcr_local(X, 1, O.Params(k=6, gamma=0.3, rounds=1))
+    check_distances(host(out["dist"]), Do, what="single query")
+    assert host(out["topk_idx"]).shape == (1, 5)

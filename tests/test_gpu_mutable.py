@@ -154,3 +154,32 @@ def test_mutation_errors_and_inflight_requests(ctx):
         assert srv.stats()["gallery_size"] == 950
     finally:
         srv.close()
+
+
+def test_zero_rounds_and_near_empty_gallery(ctx):
+    """rounds = 0 (final search over the level-0 gallery only), and removing
+    all but two items."""
+    print("mutable gallery: rounds 0, two items left", flush=True)
+    Xall, reqs = gallery_and_queries(seed=11, n_ids=20, per=10, nreq=2, sizes=(3, 7))
+    p = Params(k=4, rounds=0, gamma=0.2, topk_out=6, precision=BF16, rebuild_each_round=False)
+    srv = Server(ctx, torch.from_numpy(Xall[:150]).cuda(), p, slots=1, max_batch=16, max_recomputed=200,
+                 gallery_capacity=200)
+    try:
+        srv.insert(Xall[150:200])
+        srv.remove(np.arange(0, 200, 3))
+        live = srv.ids()
+        fresh = Server(ctx, torch.from_numpy(np.ascontiguousarray(Xall[live])).cuda(), p, slots=1, max_batch=16,
+                       max_recomputed=200)
+        try:
+            same_answers(srv, fresh, live, reqs)
+        finally:
+            fresh.close()
+        with pytest.raises(GcrError, match="INVALID"):
+            srv.remove(live[1:])  # one item would remain
+        srv.remove(live[2:])
+        assert len(srv.ids()) == 2
+        gi, gd = srv.query(reqs[0])
+        assert set(np.unique(gi[gi >= 0]).tolist()) <= set(live[:2].tolist())
+        assert np.all(gi[:, 2:] == -1)
+    finally:
+        srv.close()

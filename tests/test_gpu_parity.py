@@ -370,3 +370,23 @@ def test_knn_exact_ties_exhaustive_paths(ctx, prec, npts):
     assert np.all(host(dist) == 0.0)
     assert st["knn_fallback_rows"] == n
     assert st["knn_exhaustive_rows"] == n, st
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16, FP8])
+def test_knn_fewer_eligible_than_k(ctx, prec):
+    """Rows with fewer eligible items than k: 9 rows with k = 12 (global
+    lists), and a cross-camera list where 35 of 40 rows share a camera
+    (those rows have 5 other-camera items for cross_k = 8).  The lists hold
+    every eligible item and -1 padding, never a column outside the set."""
+    print(f"knn fewer eligible than k prec={prec}", flush=True)
+    X = datagen.random_unit(9, 40, seed=41)
+    idx, dist = ctx.knn(dev(X), Params(k=12, precision=prec))
+    check_knn_rows(host(idx), host(dist), X.astype(np.float64), np.arange(9), 12)
+    X2 = datagen.random_unit(40, 72, seed=42)
+    cams = np.zeros(40, dtype=np.int32)
+    cams[35:] = np.arange(1, 6)
+    p = Params(k=6, cross_k=8, alpha=0.5, precision=prec)
+    i0, d0, i1, d1 = ctx.knn(dev(X2), p, dev(cams, torch.int32), cross=True)
+    X2d = X2.astype(np.float64)
+    check_knn_rows(host(i0), host(d0), X2d, np.arange(40), 6)
+    check_knn_rows(host(i1), host(d1), X2d, np.arange(40), 8, cam=cams, cross=True, what="cross")
