@@ -435,12 +435,12 @@ def serve_request(XG0: np.ndarray, g_idx: np.ndarray, g_dist: np.ndarray,
     nr = np.sum(XG0 * XG0, axis=1)
     qn = np.sum(Q * Q, axis=1)
     Dq = np.maximum(qn[:, None] + nr[None, :] - 2.0 * (Q @ XG0.T), 0.0)
-    q_idx = np.zeros((b, p.k), dtype=np.int64)
-    q_dist = np.zeros((b, p.k))
+    q_idx = np.full((b, p.k), -1, dtype=np.int64)
+    q_dist = np.full((b, p.k), np.inf)
     for t in range(b):
-        order = np.argsort(Dq[t], kind="stable")[: p.k]
-        q_idx[t] = order
-        q_dist[t] = Dq[t, order]
+        order = np.argsort(Dq[t], kind="stable")[: p.k]  # all of them if the gallery is smaller than k
+        q_idx[t, : len(order)] = order
+        q_dist[t, : len(order)] = Dq[t, order]
     idx = np.concatenate([g_idx, q_idx], axis=0)
     dist = np.concatenate([g_dist, q_dist], axis=0)
     for _ in range(p.rounds):

@@ -153,3 +153,21 @@ def test_serving_errors(ctx):
             srv.wait(t)  # five queries touch more than 20 rows
     finally:
         srv.close()
+
+
+def test_serving_gallery_smaller_than_k(ctx):
+    """Six gallery items with k = 8: every list (gallery and query) holds all
+    eligible items and -1 padding."""
+    print("serving tiny gallery", flush=True)
+    X, reqs = gallery_and_queries(seed=12, n_ids=3, per=2, nreq=2, sizes=(1, 4))
+    k, K = 8, 5
+    p = Params(k=k, rounds=2, gamma=0.2, topk_out=K, precision=BF16, rebuild_each_round=False)
+    op = O.Params(k=k, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
+    g_idx, g_dist = oracle_gallery_lists(X, k)
+    srv = Server(ctx, torch.from_numpy(X).cuda(), p, slots=1, max_batch=8, max_recomputed=6)
+    try:
+        for Q in reqs:
+            gi, gd = srv.query(Q)
+            check_request(gi, gd, X, g_idx, g_dist, Q, op, K)
+    finally:
+        srv.close()
