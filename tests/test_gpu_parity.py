@@ -390,3 +390,25 @@ def test_knn_fewer_eligible_than_k(ctx, prec):
     X2d = X2.astype(np.float64)
     check_knn_rows(host(i0), host(d0), X2d, np.arange(40), 6)
     check_knn_rows(host(i1), host(d1), X2d, np.arange(40), 8, cam=cams, cross=True, what="cross")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_short_lists_in_final_topk_and_rerank(ctx, prec):
+    """Top-K with K above the gallery size (padding), and a whole re-ranking
+    of 1 query + 2 gallery items with k above n - 1."""
+    print(f"short lists prec={prec}", flush=True)
+    nq, ng, d = 5, 10, 24
+    X = case(nq + ng, d, 43)
+    p = Params(topk_out=25, precision=prec)
+    D, ti, td = ctx.final_distances(dev(X), nq, p, dense=True, topk=True)
+    check_distances(host(D), O.final_distances(X, nq))
+    check_knn_rows(host(ti), host(td), X, np.arange(nq), 25, cols=np.arange(nq, nq + ng),
+                   exclude_self=False, what="final top-K")
+    X3 = case(3, 16, 44, clustered=False)
+    p3 = Params(k=5, gamma=0.5, rounds=2, precision=prec, topk_out=4)
+    out = ctx.rerank(dev(X3), 1, p3, dense=True, topk=True, keep_features=True)
+    ref = O.gcr(X3, O.Params(k=5, gamma=0.5, rounds=2))
+    check_features(host(out["X"]), ref["X"][-1], what="tiny rerank")
+    check_distances(host(out["dist"]), O.final_distances(ref["X"][-1], 1), what="tiny rerank distances")
+    ti = host(out["topk_idx"])
+    assert np.all(ti[0, 2:] == -1) and sorted(ti[0, :2].tolist()) == [0, 1]
