@@ -266,7 +266,9 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ int row_cam[BM];
   __shared__ int any_flag[2];
 
-  const int id = blockIdx.x;
+  // balanced mode: consecutive pieces (mostly the same row block) go to the
+  // same XCD, so its L2 serves the row tile to both workgroups sweeping it
+  const int id = a.balanced ? (int)xcd_position(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float maxn2 = a.maxn2[0];
   const int64_t cend = a.filt.count ? min(a.c1, a.c0 + (int64_t)*a.filt.count) : a.c1;
