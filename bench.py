@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-agreement", action="store_true")
+    ap.add_argument("--fp32-steps", type=int, default=3,
+                    help="steps timed with float32 screening for comparison (0: skip)")
     ap.add_argument("--cpu-sample-rows", type=int, default=3840)
     ap.add_argument("--workload", default="cross_camera", choices=["cross_camera", "serving", "local"],
                     help="cross_camera: whole re-ranking steps (default); serving: resident 500,000 x 512 "
@@ -174,10 +176,11 @@ def serving_bench(args):
     t_build = time.perf_counter() - t0
 
     agreement = None
+    fp32 = None
     if not args.no_agreement:
         print("checking top-100 agreement against FP32 screening", file=sys.stderr, flush=True)
         p32 = Params(**{**p.__dict__, "precision": FP32})
-        s32 = Server(ctx, g, p32, slots=1, max_batch=512, max_recomputed=65536)
+        s32 = Server(ctx, g, p32, slots=4, max_batch=512, max_recomputed=65536)
         same = 0
         tot = 0
         for _, q, _ in trace[:8]:
@@ -185,8 +188,18 @@ def serving_bench(args):
             b = s32.query(q)
             same += int(np.sum(np.all(a[0] == b[0], axis=1)))
             tot += q.shape[0]
-        s32.close()
         agreement = {"final_top100": same / max(1, tot), "queries_checked": tot}
+        # saturated throughput of the same server with float32 screening
+        sub = trace[:min(100, len(trace))]
+        nq_sub = sum(q.shape[0] for _, q, _ in sub)
+        print("timing float32 screening (saturated)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        tk = [s32.submit(q) for _, q, _ in sub]
+        for t in tk:
+            s32.wait(t)
+        t32 = time.perf_counter() - t0
+        s32.close()
+        fp32 = {"queries_per_s": round(nq_sub / t32, 2), "requests": len(sub)}
 
     for _, q, _ in trace[:4]:  # warm-up
         srv.query(q)
@@ -197,6 +210,16 @@ def serving_bench(args):
         srv.wait(t)
     t_sat = time.perf_counter() - t0
     qps_sat = nq_total / t_sat
+    if fp32 is not None:
+        # the BF16 server on the same request subset as the float32 timing
+        sub = trace[:fp32["requests"]]
+        t0 = time.perf_counter()
+        tk = [srv.submit(q) for _, q, _ in sub]
+        for t in tk:
+            srv.wait(t)
+        qps_sub = sum(q.shape[0] for _, q, _ in sub) / (time.perf_counter() - t0)
+        fp32["bf16_queries_per_s_same_requests"] = round(qps_sub, 2)
+        fp32["bf16_speedup"] = round(qps_sub / fp32["queries_per_s"], 3)
 
     rate = args.load * qps_sat / (nq_total / len(trace))  # requests per second
     rng = np.random.default_rng(7)
@@ -265,6 +288,7 @@ def serving_bench(args):
                    "k": 20, "rounds": 2, "top_k": 100, "batch": "log-uniform 1..512",
                    "requests": len(trace), "queries": nq_total, "slots": 4, "parallelism": "single GPU"},
         "top_k_agreement": agreement,
+        "fp32_screening_same_gpu": fp32,
         "poisson_phase": {"offered_load": args.load, "requests_per_s": round(rate, 2),
                           "queries_per_s": round(nq_total / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                           "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3)},
@@ -449,6 +473,25 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     value = w.nq * args.steps / wall
 
+    # the same steps with plain float32 screening on this GPU (identical
+    # results; the comparison the BF16 + exact refine path is meant to win)
+    fp32 = None
+    if args.fp32_steps > 0 and args.precision != "fp32":
+        print("timing float32 screening", file=sys.stderr, flush=True)
+        pf = Params(**{**p.__dict__, "precision": FP32})
+        o32 = {}
+        ctx.rerank(X, w.nq, pf, cam, dense=True, out=o32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp32_steps):
+            ctx.rerank(X, w.nq, pf, cam, dense=True, out=o32)
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t0
+        fp32 = {"value": round(w.nq * args.fp32_steps / w32, 2), "ms_per_step": round(w32 * 1e3 / args.fp32_steps, 3),
+                "steps": args.fp32_steps, "speedup_of_this_line": round((w.nq * args.steps / wall) /
+                                                                         (w.nq * args.fp32_steps / w32), 3)}
+        del o32
+
     sim_ms, sim_n = tim["sim_topk"]
     sim_avg = sim_ms / max(1, sim_n)
     flops = 2.0 * n * n * d  # one similarity sweep of all rows against all columns
@@ -474,6 +517,7 @@ def main():
                    "alpha": P["alpha"], "graph": "rebuilt each round", "output": "dense distances",
                    "screening": args.precision + "+exact refine", "parallelism": "single GPU"},
         "top_k_agreement": agreement,
+        "fp32_screening_same_gpu": fp32,
         "roofline": {"bound": "mfma", "kernel": "sim_topk", "achieved": round(achieved, 2),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic(),
                      "avg_launch_ms": round(sim_avg, 4), "launches": int(sim_n),
