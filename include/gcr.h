@@ -64,7 +64,7 @@ typedef enum {
 } gcr_status;
 
 /* Precision of the similarity screening.  Every mode re-scores the screened
- * candidates exactly (compensated float32 arithmetic), so the neighbour lists
+ * candidates exactly (float64 sums of squared float64 differences), so the neighbour lists
  * and distances are the same in all modes; only speed differs. */
 typedef enum {
   GCR_FP32 = 0,  /* float32 MFMA screening                                   */

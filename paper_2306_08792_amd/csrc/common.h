@@ -32,36 +32,24 @@ __device__ __forceinline__ uint32_t cand_col(uint64_t e) { return (uint32_t)e; }
 #define GCR_EMPTY (~0ull)
 
 // ---------------------------------------------------------------------------
-// Error-free float transformations (Knuth two-sum, FMA two-product).  The
-// library is built with -ffp-contract=off so that these stay exact.
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
+// Exact re-scoring arithmetic.  The difference of two float32 values is
+// formed in float64 (exact unless their exponents differ by more than 29,
+// else rounded once with relative error <= 2^-53), its square is taken
+// exactly inside the float64 FMA, and the sum of d non-negative terms then
+// carries a relative error below (d + 8) 2^-53 (about 2^-42 at d = 2048),
+// far below the float32 rounding of the reported distance.
+__device__ __forceinline__ double sqdiff_acc(double acc, float a, float b) {
+  const double t = (double)a - (double)b;
+  return fma(t, t, acc);
 }
-__device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  e = b - (s - a);
+// Order-preserving map double -> uint64 (total order for non-NaN values).
+__device__ __forceinline__ uint64_t ord_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
-// float-float accumulate (hi, lo) += (a_hi, a_lo)
-__device__ __forceinline__ void ff_add(float& hi, float& lo, float ahi, float alo) {
-  float s, e;
-  two_sum(hi, ahi, s, e);
-  e += lo + alo;
-  fast_two_sum(s, e, hi, lo);
-}
-// (hi, lo) += (a - b)^2 with the difference and square kept exact to
-// float-float precision.
-__device__ __forceinline__ void ff_acc_sqdiff(float& hi, float& lo, float a, float b) {
-  float dh, dl;
-  two_sum(a, -b, dh, dl);              // dh + dl = a - b exactly
-  float p = dh * dh;
-  float pe = fmaf(dh, dh, -p);         // p + pe = dh^2 exactly
-  pe = fmaf(2.0f * dh, dl, pe);        // + 2 dh dl (dl^2 is below float-float)
-  float s, e;
-  two_sum(hi, p, s, e);
-  lo += e + pe;
-  hi = s;
+__device__ __forceinline__ double unord_f64(uint64_t o) {
+  const uint64_t b = (o & 0x8000000000000000ull) ? (o & 0x7fffffffffffffffull) : ~o;
+  return __longlong_as_double((long long)b);
 }
 
 // ---------------------------------------------------------------------------
@@ -71,13 +59,10 @@ __device__ __forceinline__ float wave_sum(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ __forceinline__ void wave_ff_sum(float& hi, float& lo) {
+__device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    float oh = __shfl_xor(hi, o, 64);
-    float ol = __shfl_xor(lo, o, 64);
-    ff_add(hi, lo, oh, ol);
-  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);

@@ -5,8 +5,8 @@
 // screened key over all splits, E = screening margin): this superset holds
 // the exact top-k as long as every split kept all of its items up to that
 // cut (each split reports the threshold up to which its buffer is whole).  Its members are re-scored with the squared distance
-// ||x_i - x_j||^2 evaluated in float-float arithmetic (error-free
-// differences and products, compensated sums), then ordered by
+// ||x_i - x_j||^2 accumulated in float64 from exactly squared float64
+// differences (relative error about 2^-42 at d = 2048), then ordered by
 // (distance, index), the order of Eq. (4)'s neighbour sets, and the first k
 // are written.  Rows whose buffer overflowed are queued for the exhaustive
 // path, which scores every column exactly and extracts the k smallest.
@@ -20,33 +20,30 @@ constexpr int UMAX = 2048;    // max union size (S * C)
 constexpr int FB_CW = 2048;   // columns per exhaustive work item
 }  // namespace
 
-// float-float squared distance of two float32 rows by one wave; the result
-// is a packed key (ord(hi) << 32 | ord(lo)) whose unsigned order is the
-// order of the exact values.
+// Exact squared distance of two float32 rows by one wave (float64
+// accumulation of exact squared differences, sqdiff_acc); the result is the
+// sum's order-preserving 64-bit key.
 __device__ __forceinline__ uint64_t wave_exact_sqdist(const float* __restrict__ xa,
                                                       const float* __restrict__ xb, int d) {
   const int lane = threadIdx.x & 63;
-  float hi = 0.f, lo = 0.f;
+  double s = 0.0;
   if ((d & 3) == 0 && ((((uintptr_t)xa) | ((uintptr_t)xb)) & 15) == 0) {
     const int d4 = d >> 2;
     for (int e = lane; e < d4; e += 64) {
       const f32x4 a = ((const f32x4*)xa)[e], b = ((const f32x4*)xb)[e];
-      ff_acc_sqdiff(hi, lo, a.x, b.x);
-      ff_acc_sqdiff(hi, lo, a.y, b.y);
-      ff_acc_sqdiff(hi, lo, a.z, b.z);
-      ff_acc_sqdiff(hi, lo, a.w, b.w);
+      s = sqdiff_acc(s, a.x, b.x);
+      s = sqdiff_acc(s, a.y, b.y);
+      s = sqdiff_acc(s, a.z, b.z);
+      s = sqdiff_acc(s, a.w, b.w);
     }
   } else {
-    for (int e = lane; e < d; e += 64) ff_acc_sqdiff(hi, lo, xa[e], xb[e]);
+    for (int e = lane; e < d; e += 64) s = sqdiff_acc(s, xa[e], xb[e]);
   }
-  float h, l;
-  fast_two_sum(hi, lo, h, l);
-  wave_ff_sum(h, l);
-  fast_two_sum(h, l, hi, lo);
-  return ((uint64_t)ord_f32(hi) << 32) | (uint64_t)ord_f32(lo);
+  return ord_f64(wave_sum_f64(s));
 }
 
-__device__ __forceinline__ float exact_hi(uint64_t k) { return unord_f32((uint32_t)(k >> 32)); }
+// The exact squared distance of a key, rounded to float32.
+__device__ __forceinline__ float exact_dist(uint64_t k) { return (float)unord_f64(k); }
 
 // LDS bitonic sort of n (power of two) entries ordered by (key, aux).
 __device__ void block_sort_pairs(uint64_t* key, uint32_t* aux, int n) {
@@ -158,7 +155,7 @@ __global__ __launch_bounds__(RT) void refine_kernel(RefineArgs a) {
   for (int t = tid; t < kk; t += RT) {
     if (t < M) {
       oidx[t] = (int32_t)ec[t];
-      odist[t] = exact_hi(ek[t]);
+      odist[t] = exact_dist(ek[t]);
     } else {
       oidx[t] = -1;
       odist[t] = INFINITY;
@@ -189,29 +186,22 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
-// float-float squared distances of the register-held row to two rows
+// Exact squared distances of the register-held row to two rows
 __device__ __forceinline__ void wave_exact_sqdist2_reg(const float (&xr)[32], const float* __restrict__ xa,
                                                        const float* __restrict__ xb, int d, uint64_t& ka,
                                                        uint64_t& kb) {
   const int lane = threadIdx.x & 63;
-  float ha = 0.f, la = 0.f, hb = 0.f, lb = 0.f;
+  double sa = 0.0, sb = 0.0;
 #pragma unroll
   for (int t = 0; t < 32; ++t) {
     const int e = lane + 64 * t;
     if (e < d) {
-      ff_acc_sqdiff(ha, la, xr[t], xa[e]);
-      ff_acc_sqdiff(hb, lb, xr[t], xb[e]);
+      sa = sqdiff_acc(sa, xr[t], xa[e]);
+      sb = sqdiff_acc(sb, xr[t], xb[e]);
     }
   }
-  float h, l;
-  fast_two_sum(ha, la, h, l);
-  wave_ff_sum(h, l);
-  fast_two_sum(h, l, ha, la);
-  fast_two_sum(hb, lb, h, l);
-  wave_ff_sum(h, l);
-  fast_two_sum(h, l, hb, lb);
-  ka = ((uint64_t)ord_f32(ha) << 32) | (uint64_t)ord_f32(la);
-  kb = ((uint64_t)ord_f32(hb) << 32) | (uint64_t)ord_f32(lb);
+  ka = ord_f64(wave_sum_f64(sa));
+  kb = ord_f64(wave_sum_f64(sb));
 }
 
 // The same with 16-byte loads when d is a multiple of 256 (lane l holds
@@ -226,27 +216,20 @@ __device__ __forceinline__ void wave_exact_sqdist2_vec(const f32x4 (&xr4)[V], co
     va[t] = ((const f32x4*)xa)[t * 64 + lane];
     vb[t] = ((const f32x4*)xb)[t * 64 + lane];
   }
-  float ha = 0.f, la = 0.f, hb = 0.f, lb = 0.f;
+  double sa = 0.0, sb = 0.0;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    ff_acc_sqdiff(ha, la, xr4[t].x, va[t].x);
-    ff_acc_sqdiff(ha, la, xr4[t].y, va[t].y);
-    ff_acc_sqdiff(ha, la, xr4[t].z, va[t].z);
-    ff_acc_sqdiff(ha, la, xr4[t].w, va[t].w);
-    ff_acc_sqdiff(hb, lb, xr4[t].x, vb[t].x);
-    ff_acc_sqdiff(hb, lb, xr4[t].y, vb[t].y);
-    ff_acc_sqdiff(hb, lb, xr4[t].z, vb[t].z);
-    ff_acc_sqdiff(hb, lb, xr4[t].w, vb[t].w);
+    sa = sqdiff_acc(sa, xr4[t].x, va[t].x);
+    sa = sqdiff_acc(sa, xr4[t].y, va[t].y);
+    sa = sqdiff_acc(sa, xr4[t].z, va[t].z);
+    sa = sqdiff_acc(sa, xr4[t].w, va[t].w);
+    sb = sqdiff_acc(sb, xr4[t].x, vb[t].x);
+    sb = sqdiff_acc(sb, xr4[t].y, vb[t].y);
+    sb = sqdiff_acc(sb, xr4[t].z, vb[t].z);
+    sb = sqdiff_acc(sb, xr4[t].w, vb[t].w);
   }
-  float h, l;
-  fast_two_sum(ha, la, h, l);
-  wave_ff_sum(h, l);
-  fast_two_sum(h, l, ha, la);
-  fast_two_sum(hb, lb, h, l);
-  wave_ff_sum(h, l);
-  fast_two_sum(h, l, hb, lb);
-  ka = ((uint64_t)ord_f32(ha) << 32) | (uint64_t)ord_f32(la);
-  kb = ((uint64_t)ord_f32(hb) << 32) | (uint64_t)ord_f32(lb);
+  ka = ord_f64(wave_sum_f64(sa));
+  kb = ord_f64(wave_sum_f64(sb));
 }
 
 // ascending bitonic sort of 64 EX (key, index) pairs, EX per lane
@@ -429,7 +412,7 @@ __global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
     if (t < kk) {
       if (t < M) {
         oidx[t] = (int32_t)ec[j];
-        odist[t] = exact_hi(ek[j]);
+        odist[t] = exact_dist(ek[j]);
       } else {
         oidx[t] = -1;
         odist[t] = INFINITY;
@@ -442,22 +425,18 @@ __global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
 // Exhaustive exact path for (row, list) pairs whose cut reached past a
 // split's threshold.  One block per pair (grid-stride); the row's slice of
 // the feature vector stays in registers (d <= 2048), each wave scores one
-// column at a time in float-float arithmetic, then k rounds of "smallest
+// column at a time in float64 arithmetic, then k rounds of "smallest
 // (distance, column) above the previous one" extract the list in order.
 __device__ __forceinline__ uint64_t wave_exact_sqdist_reg(const float (&xr)[32], const float* __restrict__ xb,
                                                           int d) {
   const int lane = threadIdx.x & 63;
-  float hi = 0.f, lo = 0.f;
+  double s = 0.0;
 #pragma unroll
   for (int t = 0; t < 32; ++t) {
     const int e = lane + 64 * t;
-    if (e < d) ff_acc_sqdiff(hi, lo, xr[t], xb[e]);
+    if (e < d) s = sqdiff_acc(s, xr[t], xb[e]);
   }
-  float h, l;
-  fast_two_sum(hi, lo, h, l);
-  wave_ff_sum(h, l);
-  fast_two_sum(h, l, hi, lo);
-  return ((uint64_t)ord_f32(hi) << 32) | (uint64_t)ord_f32(lo);
+  return ord_f64(wave_sum_f64(s));
 }
 
 // Column-parallel exhaustive path for the first fb_max queued pairs: each
@@ -581,7 +560,7 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(RefineArgs a) {
       block_min_pair(bkey, bcol, rk, rc);
       if (tid == 0) {
         if (bkey == GCR_EMPTY) { oidx[t] = -1; odist[t] = INFINITY; }
-        else { oidx[t] = (int32_t)bcol; odist[t] = exact_hi(bkey); }
+        else { oidx[t] = (int32_t)bcol; odist[t] = exact_dist(bkey); }
       }
       prevk = bkey; prevc = bcol; have = true;
     }
@@ -652,7 +631,7 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
           if (rk[q] < b || (rk[q] == b && rc[q] < c)) { b = rk[q]; c = rc[q]; }
         bk = b; bc = c;
         if (b == GCR_EMPTY) { oidx[t] = -1; odist[t] = INFINITY; }
-        else { oidx[t] = (int32_t)c; odist[t] = exact_hi(b); }
+        else { oidx[t] = (int32_t)c; odist[t] = exact_dist(b); }
       }
       __syncthreads();
       pk = bk; pc = bc; have_prev = true;
@@ -857,7 +836,7 @@ __global__ __launch_bounds__(RT) void band_select_kernel(RefineArgs a) {
     for (int t = tid; t < kk; t += RT) {
       if (t < M) {
         oidx[t] = (int32_t)ec[t];
-        odist[t] = exact_hi(ek[t]);
+        odist[t] = exact_dist(ek[t]);
       } else {
         oidx[t] = -1;
         odist[t] = INFINITY;
@@ -1030,10 +1009,10 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
     const float* pb = X + (int64_t)jb * d;
     if constexpr (V > 0) wave_exact_sqdist2_vec<V>(xr4, pa, pb, ka, kb);
     else wave_exact_sqdist2_reg(xr, pa, pb, d, ka, kb);
-    umax = fmaxf(umax, exact_hi(ka));
+    umax = fmaxf(umax, exact_dist(ka));
     ++valid;
     if (jb0 < 0) break;
-    umax = fmaxf(umax, exact_hi(kb));
+    umax = fmaxf(umax, exact_dist(kb));
     ++valid;
   }
   if (lane != 0) return;
