@@ -219,14 +219,20 @@ __device__ __forceinline__ void wave_exact_sqdist2_vec(const f32x4 (&xr4)[V], co
   double sa = 0.0, sb = 0.0;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
-    sa = sqdiff_acc(sa, xr4[t].x, va[t].x);
-    sa = sqdiff_acc(sa, xr4[t].y, va[t].y);
-    sa = sqdiff_acc(sa, xr4[t].z, va[t].z);
-    sa = sqdiff_acc(sa, xr4[t].w, va[t].w);
-    sb = sqdiff_acc(sb, xr4[t].x, vb[t].x);
-    sb = sqdiff_acc(sb, xr4[t].y, vb[t].y);
-    sb = sqdiff_acc(sb, xr4[t].z, vb[t].z);
-    sb = sqdiff_acc(sb, xr4[t].w, vb[t].w);
+    // The empty asm makes the row slice look fresh on every call, so the
+    // compiler keeps it in float32 registers instead of hoisting its float64
+    // conversion out of the caller's loop (twice the registers, one wave per
+    // SIMD fewer).
+    f32x4 r = xr4[t];
+    asm volatile("" : "+v"(r));
+    sa = sqdiff_acc(sa, r.x, va[t].x);
+    sa = sqdiff_acc(sa, r.y, va[t].y);
+    sa = sqdiff_acc(sa, r.z, va[t].z);
+    sa = sqdiff_acc(sa, r.w, va[t].w);
+    sb = sqdiff_acc(sb, r.x, vb[t].x);
+    sb = sqdiff_acc(sb, r.y, vb[t].y);
+    sb = sqdiff_acc(sb, r.z, vb[t].z);
+    sb = sqdiff_acc(sb, r.w, vb[t].w);
   }
   ka = ord_f64(wave_sum_f64(sa));
   kb = ord_f64(wave_sum_f64(sb));
@@ -273,8 +279,10 @@ __device__ __forceinline__ void wave_sort_pairs(uint64_t (&k)[EX], uint32_t (&c)
 }
 
 // V > 0: d == 256 V with 16-byte aligned rows; V == 0: any d <= 2048.
+// At most 168 VGPRs (three waves per SIMD): the re-score loop is bound by
+// the latency of its row gathers, and the third wave hides 15 % of it.
 template <int V>
-__global__ __launch_bounds__(256) void refine_wave_kernel(RefineArgs a) {
+__global__ __launch_bounds__(256, 3) void refine_wave_kernel(RefineArgs a) {
   extern __shared__ uint64_t wsm[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int UW = a.S * a.C;
