@@ -205,7 +205,9 @@ gcr_status gcr_propagate(gcr_ctx* ctx, const gcr_graph* g, const float* X_in,
 
 /* Distances between the first nq rows (queries) and the next ng rows
  * (gallery) of X (float32 [nq+ng, d]):
- *   dist_out: float32 [nq, ng] dense squared distances, or NULL;
+ *   dist_out: float32 [nq, ng] dense squared distances, or NULL (inner
+ *     products from a 16-bit-mantissa split of every feature, hi + lo in
+ *     bfloat16, |x - hi - lo| <= 2^-16 |x|, accumulated in float32);
  *   topk_idx / topk_dist: int32 / float32 [nq, K] with K = p->topk_out: the
  *     K nearest gallery items (gallery index 0..ng-1) by (distance, index),
  *     or NULL.

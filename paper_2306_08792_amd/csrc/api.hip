@@ -646,6 +646,7 @@ static void run_final(gcr_ctx* c, const FinalPlan& fp, const float* X, int64_t n
     {
       TimedScope ts(c, 5, st);
       launch_screen_prep(GCR_PREC_FP32, X, n, d, kd.npad, kd.Xs, kd.ld, kd.n2, kd.scale, kd.rn, kd.maxn2, st);
+      launch_split_bf16(kd.Xs, kd.npad, kd.ld, st);
     }
     TimedScope ts(c, 4, st);
     launch_dense_dist(kd.Xs, kd.ld, kd.kch, kd.n2, 0, nq, nq, ng, dist_out, st);

@@ -31,6 +31,14 @@ __device__ __forceinline__ float cand_key(uint64_t e) { return unord_f32((uint32
 __device__ __forceinline__ uint32_t cand_col(uint64_t e) { return (uint32_t)e; }
 #define GCR_EMPTY (~0ull)
 
+// bfloat16 with round-to-nearest-even (finite inputs) and back.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 // ---------------------------------------------------------------------------
 // Exact re-scoring arithmetic.  The difference of two float32 values is
 // formed in float64 (exact unless their exponents differ by more than 29,

@@ -183,6 +183,10 @@ struct PropArgs {
 void launch_propagate(const PropArgs& a, hipStream_t st);
 
 // ---- final.hip : dense squared distances between two row ranges
+// Rewrites the float32 screening operand (rows x ld_bytes, ld_bytes a
+// multiple of 128) in place into the split-bfloat16 form launch_dense_dist
+// reads.
+void launch_split_bf16(uint8_t* Xs, int64_t rows, int64_t ld_bytes, hipStream_t st);
 void launch_dense_dist(const uint8_t* Xs, int64_t ld_bytes, int kchunks, const float* n2,
                        int64_t q0, int64_t nq, int64_t g0, int64_t ng, float* out,
                        hipStream_t st);

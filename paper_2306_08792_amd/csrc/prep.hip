@@ -21,14 +21,6 @@ __global__ __launch_bounds__(256) void normalize_rows_kernel(const float* __rest
   for (int e = lane; e < d; e += 64) y[e] = x[e] * inv;
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
 // value of an E4M3 code written by f32_to_e4m3_rne
 __device__ __forceinline__ float e4m3_to_f32(uint8_t c) {
   const int E = (c >> 3) & 15, m = c & 7;
