@@ -218,6 +218,25 @@ def test_final_distances_dense_and_topk(ctx, prec):
                    exclude_self=False, what="final top-K")
 
 
+@pytest.mark.parametrize("d,scale", [(2048, 1e-3), (512, 1e-5), (100, 0.0)])
+def test_final_distances_near_duplicates(ctx, d, scale):
+    """Gallery rows that are the queries plus tiny perturbations (and exact
+    copies): distances near zero, where the absolute tolerance binds and the
+    split-bfloat16 inner products must cancel against the float32 norms."""
+    print(f"final near-duplicates d={d} scale={scale}", flush=True)
+    rng = np.random.default_rng(d)
+    nq = 130
+    Q = rng.standard_normal((nq, d))
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    G = np.concatenate([Q + scale * rng.standard_normal((nq, d)), Q, rng.standard_normal((200, d)) * 0.05])
+    X = np.concatenate([Q, G]).astype(np.float32)
+    D, _, _ = ctx.final_distances(dev(X), nq, Params(), dense=True)
+    Dg, Do = host(D), O.final_distances(X, nq)
+    check_distances(Dg, Do, what="near-duplicate distances")
+    # exact copies: the distance of a row to itself
+    np.testing.assert_allclose(Dg[np.arange(nq), nq + np.arange(nq)], 0.0, atol=1e-5)
+
+
 def _stagewise_rerank(ctx, X, nq, p, op, cam=None, prec=FP32):
     """Run the rounds one at a time through the C ABI and check each stage
     against the oracle fed with the GPU's previous features."""
