@@ -340,7 +340,6 @@ size_t layout_graph(Arena& ar, gcr_graph* g, int64_t n, int k, int ck, int has_c
 
 void plan_graph_tmp(Arena& ar, GraphTmp& t, int64_t n) {
   t.cnt = ar.take<int32_t>((size_t)n + 1);
-  t.fsum = ar.take<float>((size_t)n + 1);
   t.blk = ar.take<int32_t>((size_t)(n / 1024 + 2));
   t.label = ar.take<int32_t>((size_t)n);
   t.order = ar.take<int32_t>((size_t)n);
@@ -367,7 +366,7 @@ void build_one(const gcr_graph* g, bool cross, int64_t n, const int* cam, const 
   a.pf = cross ? g->cr_pf : g->pf;
   a.pr = cross ? g->cr_pr : g->pr;
   a.coef = coef;
-  a.tmp_cnt = t.cnt; a.tmp_fsum = t.fsum; a.tmp_blk = t.blk;
+  a.tmp_cnt = t.cnt; a.tmp_blk = t.blk;
   a.asym = p->symmetric ? 0 : 1;
   a.deg_c = cross ? t.dc_cr : t.dc;
   if (!finish) launch_graph_build(a, st);

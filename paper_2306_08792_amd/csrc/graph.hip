@@ -19,24 +19,19 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// One thread per forward edge: its weight, and one more entry in the
+// reverse row of its target.
 __global__ void edge_weight_kernel(GraphBuildArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int ci = (a.use_beta && a.cam) ? a.cam[i] : 0;
-  float fs = 0.f;
-  for (int s = 0; s < a.k; ++s) {
-    const int64_t e = i * a.k + s;
-    const int j = a.idx[e];
-    float wv = 0.f;
-    if (j >= 0) {
-      wv = expf(-a.dist[e] / a.gamma);
-      if (a.use_beta && a.cam) wv *= (a.cam[j] == ci) ? a.beta_same : a.beta_cross;
-      atomicAdd(&a.tmp_cnt[j], 1);
-    }
-    a.w[e] = wv;
-    fs += wv;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n * a.k) return;
+  const int j = a.idx[e];
+  float wv = 0.f;
+  if (j >= 0) {
+    wv = expf(-a.dist[e] / a.gamma);
+    if (a.use_beta && a.cam) wv *= (a.cam[j] == a.cam[e / a.k]) ? a.beta_same : a.beta_cross;
+    atomicAdd(&a.tmp_cnt[j], 1);
   }
-  a.tmp_fsum[i] = fs;
+  a.w[e] = wv;
 }
 
 // exclusive scan of tmp_cnt into rev_ptr (n+1 entries): block-local scans of
@@ -95,53 +90,100 @@ __global__ void rev_scatter_kernel(GraphBuildArgs a) {
   a.rev_w[pos] = a.w[e];
 }
 
-// Sort each reverse row by source (one thread per row; rows are short) and
-// compute the degree.
-__global__ void rev_sort_degree_kernel(GraphBuildArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Sort each reverse row by source and compute the degree: one wave per row.
+// The sources of a row are distinct (each forward list names an item once),
+// so an entry's slot is the number of entries with a smaller source (ties,
+// which well-formed lists never have, go by position); rows
+// of up to RS_MAX entries are staged in LDS, ranked, written to their
+// sorted slots and summed in sorted order (lane-strided partial sums, then a
+// fixed butterfly), so the degree does not depend on the order in which the
+// scatter's atomics filled the row.  Longer rows (rare hubs) are sorted by
+// one lane.
+namespace {
+constexpr int RS_MAX = 512;
+__device__ __forceinline__ void wave_lds_sync_g() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void rev_sort_degree_kernel(GraphBuildArgs a) {
+  __shared__ int32_t ssrc[4][RS_MAX];
+  __shared__ float sw[4][RS_MAX], sorted_w[4][RS_MAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   if (i >= a.n) return;
-  const int b = a.rev_ptr[i], e = a.rev_ptr[i + 1];
-  for (int p = b + 1; p < e; ++p) {
-    const int32_t s = a.rev_src[p];
-    const float wv = a.rev_w[p];
-    int q = p - 1;
-    while (q >= b && a.rev_src[q] > s) {
-      a.rev_src[q + 1] = a.rev_src[q];
-      a.rev_w[q + 1] = a.rev_w[q];
-      --q;
-    }
-    a.rev_src[q + 1] = s;
-    a.rev_w[q + 1] = wv;
-  }
+  const int b = a.rev_ptr[i], e = a.rev_ptr[i + 1], m = e - b;
   float rs = 0.f;
-  for (int p = b; p < e; ++p) rs += a.rev_w[p];
-  if (a.asym) {
-    a.deg[i] = 1.0f + a.tmp_fsum[i];  // row degree D_r
-    a.deg_c[i] = 1.0f + rs;           // column degree D_c
+  if (m <= RS_MAX) {
+    for (int p = lane; p < m; p += 64) {
+      ssrc[wave][p] = a.rev_src[b + p];
+      sw[wave][p] = a.rev_w[b + p];
+    }
+    wave_lds_sync_g();
+    for (int p = lane; p < m; p += 64) {
+      const int32_t s = ssrc[wave][p];
+      int r = 0;
+      for (int q = 0; q < m; ++q) r += ssrc[wave][q] < s || (ssrc[wave][q] == s && q < p);
+      a.rev_src[b + r] = s;
+      a.rev_w[b + r] = sw[wave][p];
+      sorted_w[wave][r] = sw[wave][p];
+    }
+    wave_lds_sync_g();
+    for (int p = lane; p < m; p += 64) rs += sorted_w[wave][p];
   } else {
-    a.deg[i] = 1.0f + 0.5f * a.tmp_fsum[i] + 0.5f * rs;
+    if (lane == 0) {
+      for (int p = b + 1; p < e; ++p) {
+        const int32_t s = a.rev_src[p];
+        const float wv = a.rev_w[p];
+        int q = p - 1;
+        while (q >= b && a.rev_src[q] > s) {
+          a.rev_src[q + 1] = a.rev_src[q];
+          a.rev_w[q + 1] = a.rev_w[q];
+          --q;
+        }
+        a.rev_src[q + 1] = s;
+        a.rev_w[q + 1] = wv;
+      }
+      for (int p = b; p < e; ++p) rs += a.rev_w[p];  // lane 0 alone; the others add zeros
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) rs += __shfl_xor(rs, o, 64);
+  if (lane == 0) {
+    float fs = 0.f;  // forward weights of the row, in list order
+    for (int s = 0; s < a.k; ++s) fs += a.w[i * a.k + s];
+    if (a.asym) {
+      a.deg[i] = 1.0f + fs;  // row degree D_r
+      a.deg_c[i] = 1.0f + rs;  // column degree D_c
+    } else {
+      a.deg[i] = 1.0f + 0.5f * fs + 0.5f * rs;
+    }
   }
 }
 
-__global__ void values_kernel(GraphBuildArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Normalised values of one row per wave: forward entries, then (symmetric
+// graphs) reverse entries.
+__global__ __launch_bounds__(256) void values_kernel(GraphBuildArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.n) return;
   const float di = a.deg[i];
   if (a.asym) {
-    for (int s = 0; s < a.k; ++s) {
+    for (int s = lane; s < a.k; s += 64) {
       const int64_t e = i * a.k + s;
       const int j = a.idx[e];
       a.pf[e] = j >= 0 ? a.coef * a.w[e] / sqrtf(di * a.deg_c[j]) : 0.f;
     }
     return;  // no reverse terms
   }
-  for (int s = 0; s < a.k; ++s) {
+  for (int s = lane; s < a.k; s += 64) {
     const int64_t e = i * a.k + s;
     const int j = a.idx[e];
     a.pf[e] = j >= 0 ? a.coef * 0.5f * a.w[e] / sqrtf(di * a.deg[j]) : 0.f;
   }
   const int b = a.rev_ptr[i], en = a.rev_ptr[i + 1];
-  for (int p = b; p < en; ++p) a.pr[p] = a.coef * 0.5f * a.rev_w[p] / sqrtf(di * a.deg[a.rev_src[p]]);
+  for (int p = b + lane; p < en; p += 64) a.pr[p] = a.coef * 0.5f * a.rev_w[p] / sqrtf(di * a.deg[a.rev_src[p]]);
 }
 
 // deg_c / cr_deg_c: column degrees of asymmetric graphs (nullptr: symmetric)
@@ -159,7 +201,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 void launch_graph_build(const GraphBuildArgs& a, hipStream_t st) {
   const int64_t n = a.n;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a.tmp_cnt, n);
-  hipLaunchKernelGGL(edge_weight_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a);
+  if (n * a.k > 0) hipLaunchKernelGGL(edge_weight_kernel, dim3(nblk(n * a.k, 256)), dim3(256), 0, st, a);
   const int ntiles = (int)((n + 1023) / 1024);
   hipLaunchKernelGGL(scan_tiles_kernel, dim3(ntiles), dim3(1024), 0, st, a.tmp_cnt, a.rev_ptr, n, a.tmp_blk);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, a.tmp_blk, ntiles, a.rev_ptr + n);
@@ -167,11 +209,11 @@ void launch_graph_build(const GraphBuildArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a.tmp_cnt, n);
   if (n * a.k > 0)
     hipLaunchKernelGGL(rev_scatter_kernel, dim3(nblk(n * a.k, 256)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(rev_sort_degree_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(rev_sort_degree_kernel, dim3(nblk(n, 4)), dim3(256), 0, st, a);
 }
 
 void launch_finish_values(const GraphBuildArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(values_kernel, dim3(nblk(a.n, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(values_kernel, dim3(nblk(a.n, 4)), dim3(256), 0, st, a);
 }
 
 void launch_self_coef(int64_t n, const float* deg, const float* deg_c, const float* cr_deg, const float* cr_deg_c,

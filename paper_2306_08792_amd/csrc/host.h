@@ -61,7 +61,7 @@ struct KnnPlan {
 };
 
 struct GraphTmp {
-  int32_t* cnt; float* fsum; int32_t* blk;
+  int32_t* cnt; int32_t* blk;
   int32_t* label; int32_t* order;  // locality order of the last graph built
   float* dc; float* dc_cr;         // column degrees of asymmetric graphs
 };

@@ -144,7 +144,6 @@ struct GraphBuildArgs {
   float* pf; float* pr;
   float coef;          // alpha or 1 - alpha
   int32_t* tmp_cnt;    // [n]
-  float* tmp_fsum;     // [n]
   int32_t* tmp_blk;    // scan block sums
   int asym = 0;        // asymmetric normalisation: deg = row degrees, deg_c = column degrees
   float* deg_c = nullptr;
