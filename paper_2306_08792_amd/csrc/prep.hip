@@ -6,19 +6,37 @@
 
 namespace gcr {
 
-// One wave per row: Y[i] = X[i] / max(||X[i]||, 1e-12).
+// One wave per row: Y[i] = X[i] / max(||X[i]||, 1e-12).  VEC: d % 4 == 0
+// and 16-byte aligned rows, read and written 16 bytes per lane.
+template <bool VEC>
 __global__ __launch_bounds__(256) void normalize_rows_kernel(const float* __restrict__ X,
                                                              float* Y, int64_t n, int d) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const float* x = X + row * d;
-  float s = 0.f;
-  for (int e = lane; e < d; e += 64) s = fmaf(x[e], x[e], s);
-  s = wave_sum(s);
-  const float inv = 1.0f / fmaxf(sqrtf(s), 1e-12f);
   float* y = Y + row * d;
-  for (int e = lane; e < d; e += 64) y[e] = x[e] * inv;
+  float s = 0.f;
+  if constexpr (VEC) {
+    const f32x4* x4 = (const f32x4*)x;
+    const int d4 = d >> 2;
+    for (int e = lane; e < d4; e += 64) {
+      const f32x4 v = x4[e];
+      s = fmaf(v.x, v.x, s); s = fmaf(v.y, v.y, s); s = fmaf(v.z, v.z, s); s = fmaf(v.w, v.w, s);
+    }
+    s = wave_sum(s);
+    const float inv = 1.0f / fmaxf(sqrtf(s), 1e-12f);
+    for (int e = lane; e < d4; e += 64) {
+      f32x4 v = x4[e];
+      v.x *= inv; v.y *= inv; v.z *= inv; v.w *= inv;
+      ((f32x4*)y)[e] = v;
+    }
+  } else {
+    for (int e = lane; e < d; e += 64) s = fmaf(x[e], x[e], s);
+    s = wave_sum(s);
+    const float inv = 1.0f / fmaxf(sqrtf(s), 1e-12f);
+    for (int e = lane; e < d; e += 64) y[e] = x[e] * inv;
+  }
 }
 
 // value of an E4M3 code written by f32_to_e4m3_rne
@@ -235,7 +253,11 @@ __global__ __launch_bounds__(256) void screen_prep_rows_kernel(const float* __re
 
 void launch_normalize_rows(const float* X, float* Y, int64_t n, int d, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(normalize_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, Y, n, d);
+  const bool vec = d % 4 == 0 && ((((uintptr_t)X) | ((uintptr_t)Y)) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(normalize_rows_kernel<true>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, Y, n, d);
+  else
+    hipLaunchKernelGGL(normalize_rows_kernel<false>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, Y, n, d);
 }
 
 void launch_screen_prep_rows(int prec, const float* X, int64_t r0, int64_t nmax, const int* count, int d, void* Xs,
