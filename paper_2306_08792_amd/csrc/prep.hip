@@ -128,35 +128,22 @@ __device__ __forceinline__ void prep_row(const float* __restrict__ x, int d, uin
 }
 
 // prep_row for d % 4 == 0 and 16-byte aligned rows: 16-byte loads, the
-// operand written 4 elements per store, the padding past d zeroed.
+// operand written 4 elements per store, the padding past d zeroed.  Float32
+// and bfloat16 copies are written in the same pass that sums the squares;
+// FP8 needs the row's amax for its scale first and reads the row twice.
 template <int PREC>
 __device__ __forceinline__ void prep_row_vec(const float* __restrict__ x, int d, uint8_t* out, int64_t ld_bytes,
                                              float* n2o, float* scaleo, float* rno, unsigned (&maxbits)[2],
                                              int lane) {
   const f32x4* x4 = (const f32x4*)x;
   const int d4 = d >> 2;
-  float s = 0.f, amax = 0.f;
+  float s = 0.f, amax = 0.f, r2 = 0.f;
   for (int e = lane; e < d4; e += 64) {
     const f32x4 v = x4[e];
     s = fmaf(v.x, v.x, s); s = fmaf(v.y, v.y, s); s = fmaf(v.z, v.z, s); s = fmaf(v.w, v.w, s);
-    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-  }
-  s = wave_sum(s);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-  if (lane == 0) {
-    *n2o = s;
-    maxbits[0] = max(maxbits[0], __float_as_uint(s));
-  }
-  constexpr int ES = PREC == GCR_PREC_FP32 ? 4 : (PREC == GCR_PREC_BF16 ? 2 : 1);
-  float r2 = 0.f;
-  const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
-  if (PREC == GCR_PREC_FP8 && lane == 0) *scaleo = sc;
-  for (int e = lane; e < d4; e += 64) {
-    const f32x4 v = x4[e];
-    if (PREC == GCR_PREC_FP32) {
+    if constexpr (PREC == GCR_PREC_FP32) {
       ((f32x4*)out)[e] = v;
-    } else if (PREC == GCR_PREC_BF16) {
+    } else if constexpr (PREC == GCR_PREC_BF16) {
       const uint16_t h0 = f32_to_bf16_rne(v.x), h1 = f32_to_bf16_rne(v.y);
       const uint16_t h2 = f32_to_bf16_rne(v.z), h3 = f32_to_bf16_rne(v.w);
       const float r0 = v.x - bf16_to_f32(h0), r1 = v.y - bf16_to_f32(h1);
@@ -167,6 +154,22 @@ __device__ __forceinline__ void prep_row_vec(const float* __restrict__ x, int d,
       w.y = (uint32_t)h2 | ((uint32_t)h3 << 16);
       ((uint2*)out)[e] = w;
     } else {
+      amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    *n2o = s;
+    maxbits[0] = max(maxbits[0], __float_as_uint(s));
+  }
+  constexpr int ES = PREC == GCR_PREC_FP32 ? 4 : (PREC == GCR_PREC_BF16 ? 2 : 1);
+  if constexpr (PREC == GCR_PREC_FP8) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
+    if (lane == 0) *scaleo = sc;
+    for (int e = lane; e < d4; e += 64) {
+      const f32x4 v = x4[e];
       const uint8_t c0 = f32_to_e4m3_rne(v.x / sc), c1 = f32_to_e4m3_rne(v.y / sc);
       const uint8_t c2 = f32_to_e4m3_rne(v.z / sc), c3 = f32_to_e4m3_rne(v.w / sc);
       const float r0 = v.x - e4m3_to_f32(c0) * sc, r1 = v.y - e4m3_to_f32(c1) * sc;
