@@ -185,6 +185,36 @@ def test_build_graph_values(ctx, prec):
     assert rp[-1] == n * 9
 
 
+def test_build_graph_hub_rows(ctx):
+    """A hub that nearly every row lists as a neighbour: its reverse row holds
+    more than the 512 entries the wave-per-row sort stages in LDS, so the
+    one-lane path sorts it; degrees, sorted reverse rows and the normalised
+    matrix against the oracle."""
+    print("graph hub rows", flush=True)
+    rng = np.random.default_rng(77)
+    d, m = 32, 1100
+    S = rng.standard_normal((m, d))
+    S /= np.linalg.norm(S, axis=1, keepdims=True)
+    far = 5.0 + rng.standard_normal((99, d))
+    X = np.concatenate([np.zeros((1, d)), S, far]).astype(np.float32)
+    n, k = X.shape[0], 9
+    g = ctx.build_graph(dev(X), Params(k=k, gamma=0.5, precision=FP32))
+    idx = host(g.field("idx")).astype(np.int64)
+    check_knn_rows(idx, host(g.field("dist")), X, np.arange(n), k)
+    rp, rs, pr = host(g.field("rev_ptr")), host(g.field("rev_src")), host(g.field("pr"))
+    assert rp[1] - rp[0] > 512, "the hub's reverse row should exceed the LDS-staged size"
+    P, Dg = _oracle_graph_values(X, O.Params(k=k, gamma=0.5), idx)
+    np.testing.assert_allclose(host(g.field("deg")), Dg, rtol=2e-6)
+    pf, selfv = host(g.field("pf")), host(g.field("self"))
+    dense = np.zeros((n, n))
+    for i in range(n):
+        dense[i, idx[i]] += pf[i]
+        assert np.all(np.diff(rs[rp[i]:rp[i + 1]]) > 0), "reverse row not sorted by source"
+        dense[i, rs[rp[i]:rp[i + 1]]] += pr[rp[i]:rp[i + 1]]
+        dense[i, i] += selfv[i]
+    np.testing.assert_allclose(dense, P, atol=2e-6)
+
+
 @pytest.mark.parametrize("d", [3, 64, 256, 512, 700])
 def test_propagate_one_round(ctx, d):
     print(f"propagate d={d}", flush=True)
