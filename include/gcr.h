@@ -59,7 +59,7 @@ typedef enum {
   GCR_ERR_INVALID = -1,     /* bad argument (shape, NULL, range)            */
   GCR_ERR_NOMEM = -2,       /* device allocation failed                     */
   GCR_ERR_HIP = -3,         /* a HIP runtime call failed                    */
-  GCR_ERR_UNSUPPORTED = -4, /* valid but not supported by this build        */
+  GCR_ERR_UNSUPPORTED = -4, /* valid but not supported by the library      */
   GCR_ERR_TIMEOUT = -5      /* gcr_server_wait: the request is not done yet */
 } gcr_status;
 
