@@ -1075,24 +1075,31 @@ __global__ __launch_bounds__(256) void seed_thresholds_bf16_kernel(const uint8_t
     }
     return wave_sum(s);
   };
+  // the list's members up to the first padding entry, 64 at a time in the
+  // lanes, four rows gathered per step
   float kmax = -INFINITY;
   int valid = 0;
-  for (int t = 0; t < kk; t += 2) {
-    const int32_t ja = lst[t];
-    if (ja < 0) break;
-    const int32_t jb0 = t + 1 < kk ? lst[t + 1] : -1;
-    const int32_t jb = jb0 >= 0 ? jb0 : ja;
-    u32x4 ya[NV], yb[NV];
+  for (int base = 0; base < kk; base += 64) {
+    const int m = min(64, kk - base);
+    const int32_t jl = lane < m ? lst[base + lane] : -1;
+    const uint64_t okb = __ballot(jl >= 0);
+    // members before the first -1 of this chunk (all m if there is none)
+    const int run = ~okb ? min(m, (int)__builtin_ctzll(~okb)) : m;
+    for (int t = 0; t < run; t += 4) {
+      int32_t j[4];
+      u32x4 y[4][NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      ya[q] = *(const u32x4*)(Xs + (int64_t)ja * ld + (q * 64 + lane) * 16);
-      yb[q] = *(const u32x4*)(Xs + (int64_t)jb * ld + (q * 64 + lane) * 16);
+      for (int u = 0; u < 4; ++u) {
+        j[u] = __shfl(jl, min(t + u, run - 1), 64);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) y[u][q] = *(const u32x4*)(Xs + (int64_t)j[u] * ld + (q * 64 + lane) * 16);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t + u < run) kmax = fmaxf(kmax, n2[j[u]] - 2.0f * dot(y[u]));
     }
-    kmax = fmaxf(kmax, n2[ja] - 2.0f * dot(ya));
-    ++valid;
-    if (jb0 < 0) break;
-    kmax = fmaxf(kmax, n2[jb] - 2.0f * dot(yb));
-    ++valid;
+    valid += run;
+    if (run < m) break;
   }
   if (lane != 0) return;
   float res = INFINITY;
