@@ -20,6 +20,29 @@ __global__ __launch_bounds__(256) void normalize_rows_kernel(const float* __rest
   if constexpr (VEC) {
     const f32x4* x4 = (const f32x4*)x;
     const int d4 = d >> 2;
+    if (d4 <= 8 * 64) {
+      // the row stays in registers between the norm and the scaling
+      f32x4 r[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = q * 64 + lane;
+        r[q] = e < d4 ? x4[e] : f32x4{0.f, 0.f, 0.f, 0.f};
+        s = fmaf(r[q].x, r[q].x, s); s = fmaf(r[q].y, r[q].y, s);
+        s = fmaf(r[q].z, r[q].z, s); s = fmaf(r[q].w, r[q].w, s);
+      }
+      s = wave_sum(s);
+      const float inv = 1.0f / fmaxf(sqrtf(s), 1e-12f);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = q * 64 + lane;
+        if (e < d4) {
+          f32x4 v = r[q];
+          v.x *= inv; v.y *= inv; v.z *= inv; v.w *= inv;
+          ((f32x4*)y)[e] = v;
+        }
+      }
+      return;
+    }
     for (int e = lane; e < d4; e += 64) {
       const f32x4 v = x4[e];
       s = fmaf(v.x, v.x, s); s = fmaf(v.y, v.y, s); s = fmaf(v.z, v.z, s); s = fmaf(v.w, v.w, s);
