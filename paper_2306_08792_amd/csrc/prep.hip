@@ -6,10 +6,11 @@
 
 namespace gcr {
 
-// One wave per row: Y[i] = X[i] / max(||X[i]||, 1e-12).  VEC: d % 4 == 0
+// One wave per row: Y[i] = X[i] / max(||X[i]||, 1e-12); X and Y may be the
+// same buffer (each lane writes only elements it has read).  VEC: d % 4 == 0
 // and 16-byte aligned rows, read and written 16 bytes per lane.
 template <bool VEC>
-__global__ __launch_bounds__(256) void normalize_rows_kernel(const float* __restrict__ X,
+__global__ __launch_bounds__(256) void normalize_rows_kernel(const float* X,
                                                              float* Y, int64_t n, int d) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);

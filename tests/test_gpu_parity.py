@@ -155,6 +155,25 @@ def _oracle_graph_values(X, p, idx, cam=None, cr_idx=None):
     return P, Dg
 
 
+@pytest.mark.parametrize("d", [3, 101, 256, 2048, 2052, 3000])
+def test_normalize_rows_widths(ctx, d):
+    """Row normalisation on every path: scalar (d % 4 != 0), 16-byte with the
+    row held in registers (d <= 2048), 16-byte two-pass (d > 2048); a zero
+    row stays zero; in place gives the same result."""
+    print(f"normalize d={d}", flush=True)
+    rng = np.random.default_rng(d)
+    X = (rng.standard_normal((37, d)) * rng.uniform(0.01, 50.0, (37, 1))).astype(np.float32)
+    X[5] = 0.0
+    Y = host(ctx.normalize_rows(dev(X)))
+    X64 = X.astype(np.float64)
+    ref = X64 / np.maximum(np.linalg.norm(X64, axis=1, keepdims=True), 1e-12)
+    np.testing.assert_allclose(Y, ref, rtol=0, atol=2e-6)
+    assert np.all(Y[5] == 0.0)
+    Xd = dev(X)
+    Z = host(ctx.normalize_rows(Xd, out=Xd))
+    assert np.array_equal(Z.view(np.uint32), Y.view(np.uint32))
+
+
 @pytest.mark.parametrize("prec", [FP32, BF16])
 def test_build_graph_values(ctx, prec):
     print(f"graph prec={prec}", flush=True)
