@@ -331,6 +331,23 @@ def test_rerank_small_plain(ctx, prec, rebuild):
     check_distances(host(out["dist"]), O.final_distances(ref["X"][-1], nq), what="end-to-end distances")
 
 
+def test_rerank_seeded_lists_longer_than_a_wave(ctx):
+    """k = 70 > 64: from the second round on the screening thresholds are
+    seeded from the previous lists, which the seeding reads 64 entries at a
+    time.  BF16 (seeded from the BF16 operand) and FP32 screening give the
+    same features bit for bit, and both match the FP64 oracle."""
+    print("rerank k=70 seeded", flush=True)
+    X, _ = datagen.clustered(30, 14, 512, 0.6, 61)
+    nq = 60
+    outs = {}
+    for prec in (BF16, FP32):
+        p = Params(k=70, gamma=0.3, rounds=3, precision=prec)
+        outs[prec] = host(ctx.rerank(dev(X), nq, p, dense=True, keep_features=True)["X"])
+    assert np.array_equal(outs[BF16].view(np.uint32), outs[FP32].view(np.uint32))
+    ref = O.gcr(X, O.Params(k=70, gamma=0.3, rounds=3))
+    check_features(outs[BF16], ref["X"][-1], what="k = 70 features")
+
+
 @pytest.mark.parametrize("alpha,beta", [(0.5, (1.0, 1.0)), (0.7, (1.0, 1.0)), (1.0, (0.5, 1.0))])
 def test_rerank_cross_camera(ctx, alpha, beta):
     print(f"rerank cross alpha={alpha} beta={beta}", flush=True)
