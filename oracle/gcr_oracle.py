@@ -27,8 +27,8 @@ Retrieval, Sec. III):
   * Alg. 1   DSFP ("GCR_Local"): per node, a dense local affinity over the
              node and its k neighbours, local degrees, T local rounds
   * Alg. 2   GCRV: profile vectors, then T rounds on the profile vectors
-  * Sec. IV-E (efficiency analysis): gallery graphs may be computed in
-    advance (used by the serving reading)
+  * Sec. IV-F (experimental analysis, efficiency): gallery graphs may be
+    computed in advance (used by the serving reading)
 
 Readings where the paper is silent or ambiguous (each is implemented here and
 listed with its reason in the design notes):
@@ -72,7 +72,6 @@ __all__ = [
     "propagation_round",
     "gcr",
     "final_distances",
-    "rank_gallery",
     "profile_vectors",
     "sparse_round_from_lists",
     "degrees_from_lists",
@@ -89,7 +88,7 @@ NORM_FLOOR = 1e-12
 @dataclasses.dataclass
 class Params:
     """Hyper-parameters.  Paper defaults: gamma 0.2, k 15, T 3, lambda 10
-    (Sec. IV-B) and alpha 0.7 (Sec. IV-E, ablation)."""
+    (Sec. IV-B) and alpha 0.7 (Sec. IV-F, ablation study)."""
 
     k: int = 15
     gamma: float = 0.2
@@ -293,14 +292,6 @@ def final_distances(X: np.ndarray, nq: int) -> np.ndarray:
     return sq_dists(X, np.arange(nq))[:, nq:]
 
 
-def rank_gallery(dq: np.ndarray, topk: Optional[int] = None):
-    """Per-query gallery order by (distance, gallery index), stable sort."""
-    order = np.argsort(dq, axis=1, kind="stable")
-    if topk is not None:
-        order = order[:, :topk]
-    return order
-
-
 # ----------------------------------------------------------------------------
 # sparse evaluation of one round from given kNN lists (same nonzeros as the
 # dense matrices above; used where N x N does not fit)
@@ -418,7 +409,7 @@ def gcrv(frames, offsets, groups, nq: int, p: Params, mode: str = "pvg",
 def serve_request(XG0: np.ndarray, g_idx: np.ndarray, g_dist: np.ndarray,
                   Q: np.ndarray, p: Params, topk: int):
     """One request against a resident gallery (precomputed graphs, Sec.
-    IV-E efficiency analysis).
+    IV-F, efficiency analysis).
 
     Node set = gallery then the request's queries.  Gallery rows keep their
     precomputed kNN lists (built on the gallery alone, frozen); query rows

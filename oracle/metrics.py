@@ -23,7 +23,3 @@ def mean_average_precision(dq: np.ndarray, qids: np.ndarray, gids: np.ndarray) -
         aps.append(float((prec * rel).sum() / nrel))
     return float(np.mean(aps)) if aps else 0.0
 
-
-def rank1(dq: np.ndarray, qids: np.ndarray, gids: np.ndarray) -> float:
-    best = np.argmin(dq, axis=1)
-    return float(np.mean(gids[best] == qids))

@@ -570,3 +570,180 @@ def test_dsfp_node_depends_on_its_local_set_only():
         sub = X[[i] + [int(j) for j in idx[i]]]
         ref = O.gcr(sub, O.Params(k=k, gamma=0.5, rounds=2, rebuild_each_round=False))["X"][-1][0]
         np.testing.assert_allclose(got[i], ref, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# pins for the camera factors, the profile mode of GCRV, the zero-row floor,
+# the serving tie order and the retrieval metric
+
+
+def _fsum_d(a, b):
+    return math.fsum((float(x) - float(y)) ** 2 for x, y in zip(a, b))
+
+
+def _hand_sym_round(X, lists, weights):
+    """One symmetric round by hand: A~ from explicit (i, j, w) edges plus the
+    unit diagonal, A = (A~ + A~^T) / 2, D = row sums, y_i = sum_j A_ij x_j /
+    sqrt(D_i D_j), then y_i / ||y_i||.  Pure Python scalars."""
+    n = len(X)
+    At = [[1.0 if i == j else 0.0 for j in range(n)] for i in range(n)]
+    for i in range(n):
+        for j, w in zip(lists[i], weights[i]):
+            At[i][j] = w
+    A = [[0.5 * (At[i][j] + At[j][i]) for j in range(n)] for i in range(n)]
+    D = [math.fsum(A[i]) for i in range(n)]
+    out = []
+    for i in range(n):
+        y = [math.fsum(A[i][j] * X[j][c] / math.sqrt(D[i] * D[j]) for j in range(n)) for c in range(len(X[0]))]
+        nrm = math.sqrt(math.fsum(v * v for v in y))
+        out.append([v / nrm for v in y])
+    return out
+
+
+def _hand_knn(X, k):
+    lists, dists = [], []
+    for i in range(len(X)):
+        c = sorted((_fsum_d(X[i], X[j]), j) for j in range(len(X)) if j != i)[:k]
+        lists.append([j for _, j in c])
+        dists.append([d for d, _ in c])
+    return lists, dists
+
+
+def test_beta_same_and_cross_are_not_interchangeable():
+    # three unit vectors at 0, 30 and 100 degrees; cameras (0, 0, 1); k = 2
+    # makes both other points neighbours of every point.  Same-camera edges
+    # (0-1) carry beta_same, the others beta_cross; the factors differ, so a
+    # swapped assignment changes every off-diagonal entry.
+    X = np.array([unit_at(0.0), unit_at(30.0), unit_at(100.0)])
+    cam = np.array([0, 0, 1])
+    bs, bc = 0.25, 3.0
+    p = O.Params(k=2, gamma=1.0, rounds=1, alpha=1.0, beta_same=bs, beta_cross=bc)
+    g = O.build_graphs(X, p, cam)
+    ang = [0.0, 30.0, 100.0]
+    for i in range(3):
+        for j in range(3):
+            if i == j:
+                assert g["At"][i, j] == 1.0
+                continue
+            f = bs if cam[i] == cam[j] else bc
+            assert abs(g["At"][i, j] - f * E(-d_angle(ang[i], ang[j]))) < 1e-15
+    # the round that follows uses these weights (dense and sparse forms)
+    lists, dists = _hand_knn(X.tolist(), 2)
+    wts = [[(bs if cam[i] == cam[j] else bc) * E(-d) for j, d in zip(lists[i], dists[i])] for i in range(3)]
+    ref = _hand_sym_round(X.tolist(), lists, wts)
+    np.testing.assert_allclose(O.gcr(X, p, cam)["X"][1], ref, rtol=0, atol=1e-14)
+    sp, _, _ = O.sparse_round_from_lists(X, p, g["idx"], g["dist"], cam)
+    np.testing.assert_allclose(sp, ref, rtol=0, atol=1e-14)
+
+
+def _pvg_case():
+    # three tracklets of two unit frames each in R^3
+    F = [[1.0, 0.0, 0.0], [0.8, 0.6, 0.0],
+         [0.0, 1.0, 0.0], [0.0, 0.6, 0.8],
+         [0.0, 0.0, 1.0], [0.6, 0.0, 0.8]]
+    return F, [0, 2, 4, 6]
+
+
+def test_gcrv_uses_the_requested_profile_mode():
+    """Alg. 2 on the three-tracklet case: W by Cramer's rule from Eq. (16)
+    (lambda = 2, one group, n = 6) or the mean profile of Eq. (10), then one
+    fixed-graph round with k = 1 worked by hand.  A GCRV that ignored its
+    mode would give the other profile."""
+    F, offs = _pvg_case()
+    lam, n = 2.0, 6
+    M = [[math.fsum(f[a] * f[b] for f in F) + (lam * n if a == b else 0.0) for b in range(3)] for a in range(3)]
+    mu = [math.fsum(f[a] for f in F) / n for a in range(3)]
+    w_pvg, w_mean = [], []
+    for c in range(3):
+        muc = [math.fsum(F[r][a] for r in range(offs[c], offs[c + 1])) / 2.0 for a in range(3)]
+        w = _cramer3(M, [muc[a] - mu[a] for a in range(3)])
+        nw, nm = math.sqrt(math.fsum(v * v for v in w)), math.sqrt(math.fsum(v * v for v in muc))
+        w_pvg.append([v / nw for v in w])
+        w_mean.append([v / nm for v in muc])
+    p = O.Params(k=1, gamma=1.0, rounds=1, lam=lam, rebuild_each_round=False)
+    for mode, W in (("pvg", w_pvg), ("mean", w_mean)):
+        out = O.gcrv(np.array(F), np.array(offs), None, 1, p, mode=mode)
+        np.testing.assert_allclose(out["W"], W, rtol=0, atol=1e-14)
+        lists, dists = _hand_knn(W, 1)
+        ref = _hand_sym_round(W, lists, [[E(-d) for d in ds] for ds in dists])
+        np.testing.assert_allclose(out["X"][1], ref, rtol=0, atol=1e-13)
+    # the two profiles really differ here
+    assert np.abs(np.array(w_pvg) - np.array(w_mean)).max() > 0.1
+
+
+def test_row_normalize_zero_row_stays_zero():
+    Y = O.row_normalize(np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 4.0], [0.0, 0.0, 0.0]]))
+    assert np.all(np.isfinite(Y))
+    np.testing.assert_array_equal(Y[0], 0.0)
+    np.testing.assert_array_equal(Y[2], 0.0)
+    np.testing.assert_allclose(Y[1], [0.6, 0.0, 0.8], rtol=0, atol=1e-16)
+    # a round whose blended row vanishes keeps it at zero (the 1e-12 floor)
+    tiny = O.row_normalize(np.array([[1e-13, 0.0]]))
+    np.testing.assert_allclose(tiny, [[0.1, 0.0]], rtol=1e-12)
+
+
+def _hand_serve(XG, gi, gd, Q, k, gamma, rounds, topk):
+    """S1 by hand: node order gallery then queries; query rows list their k
+    nearest gallery items by (distance, index); fixed graph, `rounds` rounds."""
+    ng, b = len(XG), len(Q)
+    X = [list(map(float, r)) for r in XG] + [list(map(float, r)) for r in Q]
+    lists = [list(map(int, gi[i])) for i in range(ng)]
+    wts = [[E(-float(d) / gamma) for d in gd[i]] for i in range(ng)]
+    for q in range(b):
+        c = sorted((_fsum_d(Q[q], XG[j]), j) for j in range(ng))[:k]
+        lists.append([j for _, j in c])
+        wts.append([E(-d / gamma) for d, _ in c])
+    for _ in range(rounds):
+        X = _hand_sym_round(X, lists, wts)
+    res = []
+    for q in range(b):
+        res.append(sorted((_fsum_d(X[ng + q], X[j]), j) for j in range(ng))[:topk])
+    return res
+
+
+def test_serve_request_ties_resolve_by_gallery_index():
+    rng = np.random.default_rng(12)
+    XG = O.row_normalize(rng.standard_normal((12, 5)))
+    XG[7] = XG[3]   # exact copies: equal distances to every query
+    XG[10] = XG[1]
+    # each query sits next to one copied pair, so with k = 1 its only
+    # neighbour is decided by the index tie-break
+    Q = O.row_normalize(np.array([XG[3] + 0.05 * rng.standard_normal(5), XG[1] + 0.05 * rng.standard_normal(5)]))
+    gi, gd = O.knn_lists(O.sq_dists(XG), 1)
+    assert gi[3, 0] == 7 and gi[7, 0] == 3
+    for rounds in (0, 1, 2):
+        p = O.Params(k=1, gamma=0.5, rounds=rounds, rebuild_each_round=False)
+        top, dist = O.serve_request(XG, gi, gd, Q, p, topk=6)
+        ref = _hand_serve(XG, gi, gd, Q, 1, 0.5, rounds, 6)
+        for q in range(2):
+            assert top[q].tolist() == [j for _, j in ref[q]], (rounds, q)
+            np.testing.assert_allclose(dist[q], [d for d, _ in ref[q]], rtol=0, atol=1e-13)
+    # with no rounds the copies tie exactly and appear in index order
+    top0, d0 = O.serve_request(XG, gi, gd, Q, O.Params(k=1, rounds=0, rebuild_each_round=False), topk=2)
+    assert top0[0].tolist() == [3, 7] and d0[0, 0] == d0[0, 1]
+    assert top0[1].tolist() == [1, 10] and d0[1, 0] == d0[1, 1]
+
+
+def test_mean_average_precision_hand_computed():
+    # query 0 (id 5): ranking by distance is g2, g0, g3, g1 (g0 and g3 tie at
+    # 0.4 and keep index order); relevant g0, g1 -> hits at ranks 2 and 4:
+    #   AP = (1/2 + 2/4) / 2 = 0.5
+    # query 1 (id 7): ranking g3, g1, g0, g2; relevant g3, g2 -> ranks 1, 4:
+    #   AP = (1/1 + 2/4) / 2 = 0.75
+    # query 2 (id 9): no relevant item, skipped
+    dq = np.array([[0.4, 0.9, 0.1, 0.4],
+                   [0.5, 0.3, 0.8, 0.2],
+                   [0.1, 0.2, 0.3, 0.4]])
+    qids = np.array([5, 7, 9])
+    gids = np.array([5, 5, 7, 7])
+    gids_q0 = np.array([5, 5, 6, 6])
+    assert mean_average_precision(dq[:1], qids[:1], gids_q0) == pytest.approx(0.5, abs=1e-15)
+    gids_q1 = np.array([6, 6, 7, 7])
+    assert mean_average_precision(dq[1:2], qids[1:2], gids_q1) == pytest.approx(0.75, abs=1e-15)
+    # together, with the per-query gallery ids folded into one labelling
+    dq2 = np.array([[0.4, 0.9, 0.1, 0.4, 0.95, 0.96], [0.97, 0.98, 0.8, 0.2, 0.5, 0.3]])
+    gids2 = np.array([5, 5, 6, 7, 6, 6])
+    # q0 (5): order g2, g0, g3, g1, g4, g5 -> hits at 2, 4: (1/2 + 2/4)/2 = 0.5
+    # q1 (7): order g3, g5, g4, g2, g0, g1 -> hit at 1: 1.0
+    assert mean_average_precision(dq2, np.array([5, 7]), gids2) == pytest.approx(0.75, abs=1e-15)
+    assert mean_average_precision(dq[2:], qids[2:], gids) == 0.0
