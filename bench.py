@@ -2,15 +2,19 @@
 
 One step = one gcr_rerank call on device-resident input: normalisation,
 L rounds of {kNN graph (MFMA similarity + streaming top-k + exact refine),
-affinities / reverse lists / degrees, propagation}, then the dense
-query x gallery re-ranked distances.
+affinities / reverse lists / degrees, propagation}, then the re-ranked
+query x gallery output.
 
-Default workload: cross-camera re-ID, 3,368 queries + 15,913 gallery items,
-d = 2048, 751 identities, 6 cameras (Market-1501-shaped synthetic features),
-k = 20 for the global and the cross-camera lists, gamma = 0.2, L = 3,
-alpha = 0.5, graph rebuilt every round.  BF16 screening with exact re-scoring;
-the FP32-screening run of the same input is checked for identical neighbour
-lists and final top-k before timing.
+Default workload (--workload large_retrieval): 20,000 queries + 200,000
+gallery items, d = 512, 5,000 cluster centres with noise 0.6, k = 20,
+gamma = 0.2, L = 2, graph rebuilt every round, top-100 per query.  BF16
+screening with exact re-scoring is timed; float32 and FP8 screening of the
+same input are checked for identical top-100 lists and features first and
+timed beside it, and the screening-only (raw) modes report their error.
+
+Other workloads: cross_camera (3,368 + 15,913, d = 2048, cameras), plain
+(500 + 1,500, d = 256), video (1,980 + 6,000 tracklets, profile vectors),
+local (GCR_Local / DSFP) and serving (resident 500,000 x 512 gallery).
 
 Prints one JSON line.
 """
@@ -42,10 +46,15 @@ def parse():
     ap.add_argument("--no-agreement", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=3,
                     help="steps timed with float32 screening for comparison (0: skip)")
-    ap.add_argument("--cpu-sample-rows", type=int, default=3840)
-    ap.add_argument("--workload", default="cross_camera", choices=["cross_camera", "serving", "local"],
-                    help="cross_camera: whole re-ranking steps (default); serving: resident 500,000 x 512 "
-                         "gallery and a Poisson request trace")
+    ap.add_argument("--fp8-steps", type=int, default=3,
+                    help="large_retrieval: steps timed with FP8 screening for comparison (0: skip)")
+    ap.add_argument("--cpu-sample-rows", type=int, default=0,
+                    help="rows of the CPU oracle sample (0: the workload's default)")
+    ap.add_argument("--workload", default="large_retrieval",
+                    choices=["large_retrieval", "cross_camera", "plain", "video", "serving", "local"],
+                    help="large_retrieval: 20,000 + 200,000 x 512 whole re-ranking steps (default); "
+                         "cross_camera / plain / video: the re-ID workloads; local: GCR_Local; "
+                         "serving: resident 500,000 x 512 gallery and Poisson request traces")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
     ap.add_argument("--load", type=float, default=0.7,
                     help="serving: offered load of the Poisson phase as a fraction of the saturated throughput")
@@ -55,7 +64,8 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sim_topk_cross_camera_traffic.md")
+def traffic_file(tag: str) -> str:
+    return os.path.join(ROOT, "profiles", f"sim_topk_{tag}_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_08792_amd", "csrc", f) for f in ("simtopk.hip", "common.h", "kernels.h")]
 
 
@@ -67,12 +77,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic():
+def recorded_traffic(tag: str):
     """HBM bytes per similarity/top-k launch from the committed counter
-    summary, or None when the summary is missing or was taken on other
-    kernel sources."""
+    summary of workload `tag`, or None when the summary is missing or was
+    taken on other kernel sources."""
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(traffic_file(tag)).read().splitlines()
     except OSError:
         return None
     kv = {}
@@ -147,6 +157,276 @@ def cpu_baseline(w, p, sample_rows: int):
     }
 
 
+def env_fingerprint() -> dict:
+    """Software and device the numbers were taken on."""
+    import subprocess
+
+    import torch
+
+    env = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None)}
+    try:
+        env["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        env["rocm"] = None
+    if torch.cuda.is_available():
+        pr = torch.cuda.get_device_properties(0)
+        env.update(gpu=pr.name, arch=getattr(pr, "gcnArchName", None), compute_units=pr.multi_processor_count,
+                   hbm_gib=round(pr.total_memory / 2**30, 1))
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        if r.returncode == 0:
+            card = next(iter(json.loads(r.stdout).values()))
+            env["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:  # rocm-smi is optional
+        pass
+    env["host_cores"] = len(os.sched_getaffinity(0))
+    return env
+
+
+def time_steps(fn, steps: int, warmup: int):
+    """Run `fn` warmup times, then time exactly `steps` calls bracketed by
+    device synchronisation; returns (wall seconds, per-step ms from events
+    on the current stream)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record()
+        fn()
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def _exhaustive_rows(X: np.ndarray, rows: np.ndarray, k: int, cols=None, exclude_self: bool = True):
+    """FP64 oracle lists of the given rows: full distance rows and stable
+    sorts (the oracle's knn_rows), restricted to `cols` when given."""
+    from oracle import gcr_oracle as O
+
+    if cols is None:
+        return O.knn_rows(O.sq_dists(X, rows), rows, k)
+    Xd = np.asarray(X, dtype=np.float64)
+    Xc = Xd[cols]
+    D = np.maximum(np.sum(Xd[rows] ** 2, 1)[:, None] + np.sum(Xc ** 2, 1)[None, :] - 2.0 * (Xd[rows] @ Xc.T), 0.0)
+    order = np.argsort(D, axis=1, kind="stable")[:, :k]
+    return order, np.take_along_axis(D, order, axis=1)
+
+
+def _list_agreement(got_idx, ref_idx, ref_dist, tie=1e-6):
+    """Fraction of rows whose list equals the oracle's as a set, allowing
+    swaps among items within `tie` of the k-th oracle distance."""
+    ok = 0
+    for g, r, dd in zip(got_idx, ref_idx, ref_dist):
+        gs, rs = set(int(v) for v in g if v >= 0), set(int(v) for v in r if v >= 0)
+        if gs == rs:
+            ok += 1
+            continue
+        kth = dd[np.isfinite(dd)].max() if np.isfinite(dd).any() else np.inf
+        firm = {int(j) for j, v in zip(r, dd) if v < kth - tie}
+        ok += int(firm <= gs and len(gs) == len(rs))
+    return ok / max(1, len(got_idx))
+
+
+def large_retrieval_bench(args):
+    """20,000 queries + 200,000 gallery, d = 512 (5,000 centres, noise 0.6),
+    k = 20, gamma = 0.2, L = 2 (graph rebuilt each round), top-100 per query.
+    One step = one gcr_rerank call with the top-100 output."""
+    import torch
+
+    from paper_2306_08792_amd import datagen
+    from paper_2306_08792_amd.gcr import BF16, BF16_RAW, FP8, FP8_RAW, FP32, Context, Params
+
+    prec = {"fp32": FP32, "bf16": BF16, "fp8": FP8}[args.precision]
+    print("generating the large retrieval workload", file=sys.stderr, flush=True)
+    w = datagen.large_retrieval()
+    n, d = w.X.shape
+    K = 100
+    P = dict(k=20, gamma=0.2, rounds=2)
+    ctx = Context(0)
+    X = torch.from_numpy(w.X).cuda()
+
+    def params(pr):
+        return Params(k=P["k"], gamma=P["gamma"], rounds=P["rounds"], precision=pr, topk_out=K,
+                      rebuild_each_round=True)
+
+    p = params(prec)
+    res_modes = {}
+    agreement = None
+    raw = None
+    if not args.no_agreement:
+        print("checking top-100 agreement across screening precisions", file=sys.stderr, flush=True)
+        outs = {}
+        for name, pr in (("fp32", FP32), ("bf16", BF16), ("fp8", FP8), ("bf16_raw", BF16_RAW), ("fp8_raw", FP8_RAW)):
+            o = ctx.rerank(X, w.nq, params(pr), dense=False, topk=True, keep_features=True)
+            torch.cuda.synchronize()
+            outs[name] = (o["topk_idx"].cpu().numpy(), o["topk_dist"].cpu().numpy(), o["X"].cpu().numpy())
+            del o
+        ref_i, _, ref_x = outs["fp32"]
+        agreement = {}
+        for name in ("bf16", "fp8"):
+            gi, _, gx = outs[name]
+            agreement[name] = {"final_top100_rows_equal": float(np.mean(np.all(gi == ref_i, axis=1))),
+                               "features_bitwise_equal": bool(np.array_equal(gx.view(np.uint32), ref_x.view(np.uint32)))}
+        # errors of every mode against the FP64 oracle on sampled rows: the
+        # first-round neighbour lists (from the normalised input) and the
+        # final top-100 lists (from each mode's own propagated features,
+        # and the FP32 path's features compared with each mode's)
+        print("raw-mode errors against the FP64 oracle (sampled rows)", file=sys.stderr, flush=True)
+        from oracle import gcr_oracle as O
+
+        Xn = O.row_normalize(w.X)
+        rng = np.random.default_rng(3)
+        rows = np.sort(rng.choice(n, size=256, replace=False))
+        oi, od = _exhaustive_rows(Xn, rows, P["k"])
+        Xt = torch.from_numpy(Xn.astype(np.float32)).cuda()
+        raw = {"sample_rows": int(len(rows)), "tie_band": 1e-6}
+        qs = np.sort(rng.choice(w.nq, size=128, replace=False))
+        for name, pr in (("fp32", FP32), ("bf16", BF16), ("fp8", FP8), ("bf16_raw", BF16_RAW), ("fp8_raw", FP8_RAW)):
+            gi, gd = ctx.knn(Xt, Params(k=P["k"], precision=pr))
+            gi, gd = gi.cpu().numpy()[rows], gd.cpu().numpy()[rows].astype(np.float64)
+            XL = outs[name][2].astype(np.float64)
+            fi, fd = _exhaustive_rows(XL, qs, K, cols=np.arange(w.nq, n))
+            raw[name] = {
+                "knn_agreement": _list_agreement(gi, oi, od),
+                "knn_dist_max_abs_err": float(np.max(np.abs(gd - od))),
+                "final_top100_agreement_own_features": _list_agreement(outs[name][0][qs], fi, fd),
+                "features_max_rel_err_vs_fp32_path": float(np.max(
+                    np.linalg.norm(XL - ref_x.astype(np.float64), axis=1) / np.linalg.norm(ref_x.astype(np.float64), axis=1))),
+            }
+        del Xt, outs
+
+    print("timing", file=sys.stderr, flush=True)
+    out = {}
+    step = lambda: ctx.rerank(X, w.nq, p, dense=False, topk=True, out=out)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing()
+    ctx.reset_stats()
+    ctx.set_timing(True)
+    wall, step_ms = time_steps(step, args.steps, 0)
+    ctx.set_timing(False)
+    tim = ctx.timing()
+    st = ctx.stats()
+    value = w.nq * args.steps / wall
+    res_modes[args.precision] = {"value": round(value, 2), "ms_per_step": round(wall * 1e3 / args.steps, 3)}
+    for name, pr, ns in (("fp32", FP32, args.fp32_steps), ("fp8", FP8, args.fp8_steps)):
+        if ns <= 0 or name == args.precision:
+            continue
+        print(f"timing {name} screening", file=sys.stderr, flush=True)
+        o2 = {}
+        pq = params(pr)
+        ctx.rerank(X, w.nq, pq, dense=False, topk=True, out=o2)
+        torch.cuda.synchronize()
+        ctx.timing()
+        ctx.set_timing(True)
+        w2, _ = time_steps(lambda: ctx.rerank(X, w.nq, pq, dense=False, topk=True, out=o2), ns, 0)
+        ctx.set_timing(False)
+        t2 = ctx.timing()
+        res_modes[name] = {"value": round(w.nq * ns / w2, 2), "ms_per_step": round(w2 * 1e3 / ns, 3), "steps": ns,
+                           "stage_ms_per_step": {kk: round(v[0] / ns, 3) for kk, v in t2.items() if v[1]}}
+        del o2
+    for v in res_modes.values():
+        v["speedup_of_timed_mode"] = round(value / v["value"], 3)
+
+    sim_ms, sim_n = tim["sim_topk"]
+    sim_avg = sim_ms / max(1, sim_n)
+    flops = 2.0 * n * n * d
+    achieved = flops / (sim_avg * 1e-3) / 1e12
+    peak = PEAK[args.precision]
+    pr_ms, pr_n = tim["propagate"]
+    pr_avg = pr_ms / max(1, pr_n)
+    pbytes = 2.0 * n * d * 4 + 2.0 * n * P["k"] * 8 + n * 8
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "p50_ms": round(float(np.percentile(step_ms, 50)), 3),
+        "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name, "queries": w.nq, "gallery": w.ng, "d": d, "centres": 5000, "noise": 0.6,
+                   "k": P["k"], "gamma": P["gamma"], "rounds": P["rounds"], "graph": "rebuilt each round",
+                   "output": f"top-{K} per query", "screening": args.precision + "+exact refine",
+                   "parallelism": "single GPU"},
+        "top_k_agreement": agreement,
+        "precision_modes_same_gpu": res_modes,
+        "raw_mode_errors_vs_fp64_oracle": raw,
+        "roofline": {"bound": "mfma", "kernel": "sim_topk", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic("large_retrieval"),
+                     "avg_launch_ms": round(sim_avg, 4), "launches": int(sim_n), "flops_per_launch": flops},
+        "roofline_propagate": {"bound": "hbm", "kernel": "propagate", "achieved": round(pbytes / (pr_avg * 1e-3) / 1e9, 1),
+                               "peak": 8000.0, "unit": "GB/s",
+                               "frac": round(pbytes / (pr_avg * 1e-3) / 1e9 / 8000.0, 4), "traffic": None,
+                               "avg_launch_ms": round(pr_avg, 4), "launches": int(pr_n),
+                               "compulsory_bytes_per_launch": pbytes},
+        "stage_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in tim.items()},
+        "knn_stats": {"candidates_per_row": round(st["knn_candidates"] / max(1, st["knn_rows"]), 2),
+                      "fallback_rows": st["knn_fallback_rows"], "exhaustive_rows": st["knn_exhaustive_rows"],
+                      "splits": st["splits"]},
+        "env": env_fingerprint(),
+    }
+    del out
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline_large(w, P, K, args.cpu_sample_rows or 600)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline_large(w, P, K: int, sample_rows: int):
+    """The FP64 oracle's large-N path (blocked exhaustive kNN by full distance
+    rows and stable sorts, then a scipy.sparse FP64 round with the same
+    nonzeros) timed on the host: kNN rows on a row sample, one whole sparse
+    round on lists of the same shape, final top-K rows on a query sample;
+    scaled to 2 rounds over all rows and all queries."""
+    from oracle import gcr_oracle as O
+
+    X = O.row_normalize(w.X)
+    n = X.shape[0]
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(n, size=min(sample_rows, n), replace=False))
+    t0 = time.perf_counter()
+    for a in range(0, len(rows), 64):
+        b = rows[a:a + 64]
+        O.knn_rows(O.sq_dists(X, b), b, P["k"])
+    t_knn = (time.perf_counter() - t0) / len(rows)
+    # a whole sparse round: lists of the real shape (k random other rows)
+    idx = (np.arange(n)[:, None] + rng.integers(1, n, size=(n, P["k"]))) % n
+    dist = rng.random((n, P["k"])) * 0.5
+    op = O.Params(k=P["k"], gamma=P["gamma"], rounds=1)
+    t1 = time.perf_counter()
+    O.sparse_round_from_lists(X, op, idx, dist)
+    t_round = time.perf_counter() - t1
+    qs = np.sort(rng.choice(w.nq, size=min(sample_rows // 2, w.nq), replace=False))
+    t2 = time.perf_counter()
+    for a in range(0, len(qs), 64):
+        _exhaustive_rows(X, qs[a:a + 64], K, cols=np.arange(w.nq, n))
+    t_q = (time.perf_counter() - t2) / len(qs)
+    total = P["rounds"] * (t_knn * n + t_round) + t_q * w.nq
+    return {
+        "value": round(w.nq / total, 3), "unit": "queries/s", "cores": len(os.sched_getaffinity(0)),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle on the host: exhaustive kNN rows (distance row + full stable sort) for {len(rows)} "
+                   f"of {n} rows, one whole scipy.sparse FP64 propagation round ({t_round:.1f} s), final top-{K} "
+                   f"rows for {len(qs)} of {w.nq} queries; scaled to {P['rounds']} rounds over {n} rows and "
+                   f"{w.nq} queries (extrapolated; one run)"),
+    }
+
+
 def serving_bench(args):
     """Resident 500,000 x 512 BF16 gallery (10,000 centres), k = 20, L = 2,
     K = 100; requests of 1..512 queries (log-uniform).  Phase 1 queues the
@@ -158,7 +438,7 @@ def serving_bench(args):
     import torch
 
     from paper_2306_08792_amd import datagen
-    from paper_2306_08792_amd.gcr import BF16, FP32, Context, Params, Server
+    from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params, Server
 
     print("generating the serving gallery", file=sys.stderr, flush=True)
     bits, vals, centres = datagen.serving_gallery()
@@ -168,8 +448,9 @@ def serving_bench(args):
     ctx = Context(0)
     g = torch.from_numpy(bits.view(np.int16)).cuda()
     del vals
-    p = Params(k=20, rounds=2, gamma=0.2, topk_out=100, precision=BF16, rebuild_each_round=False)
-    print("building the resident gallery state (BF16 screening)", file=sys.stderr, flush=True)
+    prec = {"fp32": FP32, "bf16": BF16, "fp8": FP8}[args.precision]
+    p = Params(k=20, rounds=2, gamma=0.2, topk_out=100, precision=prec, rebuild_each_round=False)
+    print(f"building the resident gallery state ({args.precision} screening)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     n_mut = 1000
     srv = Server(ctx, g, p, slots=4, max_batch=512, max_recomputed=65536, gallery_capacity=ng + n_mut)
@@ -282,7 +563,7 @@ def serving_bench(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"serving_gallery_{ng}x{d}_bf16", "gallery": ng, "d": d, "centres": 10000,
                    "k": 20, "rounds": 2, "top_k": 100, "batch": "log-uniform 1..512",
@@ -375,7 +656,7 @@ def local_bench(args):
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         Xn = O.row_normalize(w.X)
         rng = np.random.default_rng(0)
-        rows = np.sort(rng.choice(n, size=min(args.cpu_sample_rows, n), replace=False))
+        rows = np.sort(rng.choice(n, size=min(args.cpu_sample_rows or 3840, n), replace=False))
         t0 = time.perf_counter()
         idx, _ = O.knn_rows(O.sq_dists(Xn, rows), rows, k)
         for t, i in enumerate(rows):
@@ -412,6 +693,9 @@ def main():
         return
     if args.workload == "local":
         local_bench(args)
+        return
+    if args.workload == "large_retrieval":
+        large_retrieval_bench(args)
         return
     import torch
 
@@ -519,7 +803,7 @@ def main():
         "top_k_agreement": agreement,
         "fp32_screening_same_gpu": fp32,
         "roofline": {"bound": "mfma", "kernel": "sim_topk", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic(),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic("cross_camera"),
                      "avg_launch_ms": round(sim_avg, 4), "launches": int(sim_n),
                      "flops_per_launch": flops},
         "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
@@ -528,7 +812,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(w, P, args.cpu_sample_rows)
+        res["cpu_baseline"] = cpu_baseline(w, P, args.cpu_sample_rows or 3840)
     print(json.dumps(res), flush=True)
     ctx.close()
 

@@ -28,9 +28,13 @@
  * Conventions
  *   Memory: every array argument is a DEVICE pointer owned by the caller,
  *     contiguous and row-major, unless stated otherwise.  The library owns
- *     only the workspace inside a gcr_ctx, which grows on demand (a call that
- *     needs a larger workspace than any earlier call allocates it, so the
- *     first call at a new size is not capture-safe).
+ *     only the workspace inside a gcr_ctx: one device block sized at
+ *     gcr_create (gcr_workspace_size gives the bytes for a problem size) and
+ *     grown only by gcr_reserve.  No other call allocates, frees or
+ *     synchronises the device (except those that say so: statistics, timing,
+ *     profile vectors, servers), so the batch calls can be captured into a
+ *     HIP graph on their first use; a call whose workspace is too small
+ *     fails with GCR_ERR_NOMEM and names the size it needs.
  *   Streams: `stream` is a hipStream_t passed as void*; NULL means the
  *     default stream.  Calls enqueue work on that stream and return without
  *     synchronising, except where a function says it synchronises.
@@ -63,13 +67,26 @@ typedef enum {
   GCR_ERR_TIMEOUT = -5      /* gcr_server_wait: the request is not done yet */
 } gcr_status;
 
-/* Precision of the similarity screening.  Every mode re-scores the screened
- * candidates exactly (float64 sums of squared float64 differences), so the neighbour lists
- * and distances are the same in all modes; only speed differs. */
+/* Precision of the similarity screening (Eq. (4) neighbour sets are ranked
+ * by squared distance).  The refine modes re-score every screened candidate
+ * within the screening margin of the k-th key exactly (float64 sums of
+ * squared float64 differences of the float32 rows), so their neighbour lists
+ * and distances equal the float32 mode's; only speed differs.  The raw modes
+ * keep the k smallest screened distances n2_i + n2_j - 2 s~ (float32 norms,
+ * screened inner product s~) with no re-score: faster, not exact; they exist
+ * to measure what the re-score buys.  With GCR_FP8 the final top-K output
+ * (gcr_final_distances, gcr_rerank, servers) is screened in BF16: FP8's
+ * margin, about 0.13 in squared distance for unit rows, spans thousands of
+ * unrelated items once K exceeds the natural neighbourhood size and would
+ * send queries to the exhaustive path; the kNN graph keeps FP8. */
 typedef enum {
-  GCR_FP32 = 0,  /* float32 MFMA screening                                   */
-  GCR_BF16 = 1,  /* bfloat16 (RNE) MFMA screening, float32 accumulation      */
-  GCR_FP8 = 2    /* OCP E4M3 with per-row scale, float32 accumulation        */
+  GCR_FP32 = 0,     /* float32 MFMA screening + exact re-score               */
+  GCR_BF16 = 1,     /* bfloat16 (RNE) MFMA screening, float32 accumulation,
+                       + exact re-score                                      */
+  GCR_FP8 = 2,      /* OCP E4M3 with per-row scale, float32 accumulation,
+                       + exact re-score                                      */
+  GCR_BF16_RAW = 3, /* bfloat16 screening only (lists by screened key)       */
+  GCR_FP8_RAW = 4   /* FP8 E4M3 screening only (lists by screened key)       */
 } gcr_precision;
 
 typedef struct {
@@ -96,9 +113,32 @@ void gcr_params_default(gcr_params* p);
 typedef struct gcr_ctx gcr_ctx;
 
 /* Create a context on HIP device `device` (made current for the calls that
- * use this context).  *out receives the handle.  Errors: INVALID (bad
- * device / NULL out), HIP. */
-gcr_status gcr_create(gcr_ctx** out, int device);
+ * use this context) with a workspace of workspace_bytes (0: none yet).
+ * *out receives the handle.  Errors: INVALID (bad device / NULL out), NOMEM
+ * (the workspace allocation failed), HIP. */
+gcr_status gcr_create(gcr_ctx** out, int device, size_t workspace_bytes);
+/* Grow the workspace to at least workspace_bytes (never shrinks).  This is
+ * the one call after gcr_create that allocates: it synchronises the device
+ * and frees the old block, so work enqueued earlier must not be relied on
+ * to keep using it (the synchronisation finishes that work first).  Not
+ * capturable.  Errors: INVALID, NOMEM, HIP. */
+gcr_status gcr_reserve(gcr_ctx* ctx, size_t workspace_bytes);
+/* Bytes of workspace the context holds. */
+size_t gcr_workspace_bytes(const gcr_ctx* ctx);
+/* Workspace bytes that every batch entry point (gcr_knn, gcr_build_graph,
+ * gcr_propagate, gcr_final_distances with dense and top-K output,
+ * gcr_rerank, gcr_dsfp, gcr_rerank_local) needs for nq queries and ng
+ * gallery rows of width d with parameters p (precision, k, cross_k,
+ * topk_out), with the cross-camera lists when with_cameras != 0; entry
+ * points that take n rows use n = nq + ng (nq may be 0).  Computed on the
+ * host for the current HIP device (the similarity schedule depends on its
+ * compute-unit count).  Returns 0 for invalid or unsupported sizes: d
+ * outside 1..2048, invalid parameters, or a screening operand above 4 GiB
+ * (about 1M rows of BF16 or 524k rows of float32 at d = 2048). */
+size_t gcr_workspace_size(const gcr_params* p, int64_t nq, int64_t ng, int32_t d, int32_t with_cameras);
+/* Workspace bytes gcr_profile_vectors needs for nt tracklets with nf frames
+ * in all of width d (mode as there); 0 for invalid sizes. */
+size_t gcr_profile_workspace_size(int32_t nt, int64_t nf, int32_t d, int32_t mode);
 /* Free the context and its workspace (synchronises the device). */
 gcr_status gcr_destroy(gcr_ctx* ctx);
 /* Message of the last error on ctx (never NULL; "" if none). */
@@ -119,13 +159,16 @@ gcr_status gcr_reset_stats(gcr_ctx* ctx);
 
 /* Per-kernel-class timing with HIP events recorded on the launch stream
  * around every launch of that class while timing is on (off by default).
- * Classes: 0 similarity + top-k screening, 1 exact refine (with the
- * exhaustive fallback), 2 graph build (weights, reverse lists, degrees,
- * normalised values), 3 propagation (global rounds, or the DSFP kernel), 4 dense final distances, 5 input
- * preparation (normalisation and screening operands).
+ * Classes: 0 similarity + top-k screening of the kNN graph, 1 its exact
+ * refine (with the exhaustive fallback and threshold seeding), 2 graph
+ * build (weights, reverse lists, degrees, normalised values), 3
+ * propagation (global rounds, or the DSFP kernel), 4 dense final
+ * distances, 5 input preparation (normalisation and screening operands),
+ * 6 screening sweep of the final top-K (queries against the gallery), 7
+ * its exact refine.
  * gcr_get_timing synchronises the device, returns the totals since the last
  * reset (milliseconds and launch counts) and resets them. */
-#define GCR_NUM_TIMERS 6
+#define GCR_NUM_TIMERS 8
 typedef struct {
   double ms[GCR_NUM_TIMERS];
   int64_t launches[GCR_NUM_TIMERS];
@@ -223,11 +266,15 @@ gcr_status gcr_final_distances(gcr_ctx* ctx, const float* X, int64_t nq,
  * gcr_final_distances.  X_final (float32 [nq+ng, d]) receives X_T if not
  * NULL.  cam (int32 [nq+ng]) may be NULL; with cam and alpha < 1 the
  * cross-camera graph and the blend of Eq. (9) are used.
- * Errors: INVALID, UNSUPPORTED, NOMEM, HIP. */
+ * last_graph: NULL, or a graph bound by gcr_graph_bind for n = nq + ng,
+ * k = p->k and, with cameras and alpha < 1, has_cross = 1 and cross_k as in
+ * p (else has_cross = 0); the rounds then build into it, so it holds the
+ * graph of the last round afterwards (untouched when p->rounds = 0).
+ * Errors: INVALID, UNSUPPORTED, NOMEM (workspace too small), HIP. */
 gcr_status gcr_rerank(gcr_ctx* ctx, const float* X, int64_t nq, int64_t ng,
                       int32_t d, const int32_t* cam, const gcr_params* p,
                       float* dist_out, int32_t* topk_idx, float* topk_dist,
-                      float* X_final, void* stream);
+                      float* X_final, gcr_graph* last_graph, void* stream);
 
 /* Decentralised synchronous feature propagation, DSFP (Alg. 1).  For every
  * node i independently: the local set L_i = {i} plus the entries of row i
@@ -340,8 +387,10 @@ typedef struct {
  *   normalize_input; rebuild_each_round must be 0 (the gallery graph is
  *   fixed); alpha / beta / cross_k are ignored.
  *   cfg: NULL for the defaults.
- * Synchronous: builds the gallery graph and the resident propagated copies
- * with ctx's workspace, then starts the worker thread.
+ * Synchronous: first synchronises the device, so work the caller enqueued
+ * on any stream (for example a kernel still writing the gallery) completes
+ * before the gallery is read; then builds the gallery graph and the
+ * resident propagated copies and starts the worker thread.
  * Errors: INVALID, UNSUPPORTED, NOMEM, HIP (message in gcr_last_error(ctx)). */
 gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery,
                              int32_t gallery_dtype, int64_t ng, int32_t d,

@@ -19,6 +19,7 @@ GCR_ERR_TIMEOUT = -5
 # every exported entry point of include/gcr.h
 EXPORTS = [
     "gcr_params_default", "gcr_create", "gcr_destroy", "gcr_last_error", "gcr_get_stats",
+    "gcr_reserve", "gcr_workspace_bytes", "gcr_workspace_size", "gcr_profile_workspace_size",
     "gcr_reset_stats", "gcr_normalize_rows", "gcr_knn", "gcr_graph_bytes", "gcr_graph_bind",
     "gcr_build_graph", "gcr_propagate", "gcr_final_distances", "gcr_rerank",
     "gcr_profile_vectors", "gcr_set_timing", "gcr_get_timing",
@@ -27,8 +28,9 @@ EXPORTS = [
     "gcr_dsfp", "gcr_rerank_local",
     "gcr_server_insert", "gcr_server_remove", "gcr_server_gallery_ids", "gcr_server_save", "gcr_server_load",
 ]
-NUM_TIMERS = 6
-TIMER_NAMES = ["sim_topk", "refine", "graph", "propagate", "final_dense", "prep"]
+NUM_TIMERS = 8
+TIMER_NAMES = ["sim_topk", "refine", "graph", "propagate", "final_dense", "prep", "final_topk_sweep",
+               "final_topk_refine"]
 
 
 class GcrParams(C.Structure):
@@ -51,7 +53,7 @@ _P = C.c_void_p
 
 
 class GcrTiming(C.Structure):
-    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6)]
+    _fields_ = [("ms", C.c_double * NUM_TIMERS), ("launches", C.c_int64 * NUM_TIMERS)]
 
 
 class GcrGraph(C.Structure):
@@ -100,7 +102,14 @@ def load(path: str = LIB_PATH):
     pP = C.POINTER(GcrParams)
     L.gcr_params_default.argtypes = [pP]
     L.gcr_params_default.restype = None
-    L.gcr_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.gcr_create.argtypes = [C.POINTER(vp), C.c_int, C.c_size_t]
+    L.gcr_reserve.argtypes = [vp, C.c_size_t]
+    L.gcr_workspace_bytes.argtypes = [vp]
+    L.gcr_workspace_bytes.restype = C.c_size_t
+    L.gcr_workspace_size.argtypes = [pP, i64, i64, i32, i32]
+    L.gcr_workspace_size.restype = C.c_size_t
+    L.gcr_profile_workspace_size.argtypes = [i32, i64, i32, i32]
+    L.gcr_profile_workspace_size.restype = C.c_size_t
     L.gcr_destroy.argtypes = [vp]
     L.gcr_last_error.argtypes = [vp]
     L.gcr_last_error.restype = C.c_char_p
@@ -114,7 +123,7 @@ def load(path: str = LIB_PATH):
     L.gcr_build_graph.argtypes = [vp, vp, i64, i32, vp, pP, C.POINTER(GcrGraph), vp]
     L.gcr_propagate.argtypes = [vp, C.POINTER(GcrGraph), vp, vp, i64, i32, vp]
     L.gcr_final_distances.argtypes = [vp, vp, i64, i64, i32, pP, vp, vp, vp, vp]
-    L.gcr_rerank.argtypes = [vp, vp, i64, i64, i32, vp, pP, vp, vp, vp, vp, vp]
+    L.gcr_rerank.argtypes = [vp, vp, i64, i64, i32, vp, pP, vp, vp, vp, vp, C.POINTER(GcrGraph), vp]
     L.gcr_set_timing.argtypes = [vp, i32]
     L.gcr_get_timing.argtypes = [vp, C.POINTER(GcrTiming)]
     L.gcr_profile_vectors.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, f32, vp, vp]

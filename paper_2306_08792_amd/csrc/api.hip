@@ -62,7 +62,9 @@ gcr_status fail(gcr_ctx* c, gcr_status s, const char* fmt, ...) {
 
 
 
-gcr_status ensure_ws(gcr_ctx* c, size_t bytes) {
+// Grow the context workspace (the only allocation a context makes after
+// creation): synchronises the device, frees the old block, allocates anew.
+gcr_status reserve_ws(gcr_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return GCR_OK;
   HIP_TRY(c, hipSetDevice(c->device));
   if (c->ws) {
@@ -71,7 +73,7 @@ gcr_status ensure_ws(gcr_ctx* c, size_t bytes) {
     c->ws = nullptr;
     c->ws_bytes = 0;
   }
-  size_t want = align_up(bytes + (bytes >> 3), 1 << 20);
+  size_t want = align_up(bytes, 1 << 20);
   if (hipMalloc(&c->ws, want) != hipSuccess) {
     c->ws = nullptr;
     (void)hipGetLastError();
@@ -79,6 +81,16 @@ gcr_status ensure_ws(gcr_ctx* c, size_t bytes) {
   }
   c->ws_bytes = want;
   return GCR_OK;
+}
+
+// A batch call never allocates: it runs in the workspace the context holds
+// or fails with NOMEM naming the size it needs.
+gcr_status need_ws(gcr_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return GCR_OK;
+  return fail(c, GCR_ERR_NOMEM,
+              "this call needs a workspace of %zu bytes and the context holds %zu "
+              "(size it with gcr_workspace_size at gcr_create, or grow it with gcr_reserve)",
+              bytes, c->ws_bytes);
 }
 
 __global__ void fill_u32_kernel(unsigned* p, unsigned v, int64_t n) {
@@ -92,6 +104,28 @@ void fill_u32(void* p, unsigned v, int64_t n, hipStream_t st) {
 __global__ void add_count_kernel(unsigned long long* dst, const int* src) { *dst += (unsigned long long)*src; }
 
 int esize_of(int prec) { return prec == GCR_PREC_FP32 ? 4 : (prec == GCR_PREC_BF16 ? 2 : 1); }
+int screen_prec_of(int precision) {
+  return precision == GCR_BF16_RAW ? GCR_PREC_BF16 : (precision == GCR_FP8_RAW ? GCR_PREC_FP8 : precision);
+}
+int is_raw_precision(int precision) { return precision == GCR_BF16_RAW || precision == GCR_FP8_RAW; }
+// Screening of the final top-K: FP8's margin (about 0.13 in squared distance
+// for unit rows) spans thousands of unrelated items at a K beyond the
+// natural neighbourhood size, which would send queries to the refine's
+// exhaustive path, so the exact FP8 mode screens the final top-K in BF16.
+int final_screen_prec(int precision) { return precision == GCR_FP8 ? GCR_BF16 : precision; }
+
+// The similarity kernel reads its screening operand [npad, ld] through one
+// buffer descriptor with 32-bit byte offsets, so the operand must stay below
+// 4 GiB (e.g. about 1M rows of BF16 or 524k rows of float32 at d = 2048).
+gcr_status check_operand(gcr_ctx* c, int precision, int64_t rows, int d) {
+  const int64_t npad = roundup(rows, 128) + 128;
+  const int64_t ld = roundup((int64_t)d * esize_of(screen_prec_of(precision)), 128);
+  if (npad * ld >= ((int64_t)1 << 32))
+    return fail(c, GCR_ERR_UNSUPPORTED,
+                "%lld rows of width %d exceed the 4 GiB screening operand of the similarity kernel",
+                (long long)rows, d);
+  return GCR_OK;
+}
 
 // Compute units of the current device (one similarity workgroup each).
 int compute_units() {
@@ -135,9 +169,11 @@ int capacity_for(int prec, int kmax, int nl) {
 }
 
 
-void plan_knn(Arena& ar, KnnPlan& kp, int prec, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
+void plan_knn(Arena& ar, KnnPlan& kp, int precision, int64_t n, int d, int64_t r0, int64_t r1, int64_t c0,
               int64_t c1, int k0, int k1) {
+  const int prec = screen_prec_of(precision);
   kp.prec = prec;
+  kp.raw = is_raw_precision(precision);
   kp.nl = k1 > 0 ? 2 : 1;
   kp.n = n;
   kp.npad = roundup(n, 128) + 128;
@@ -242,7 +278,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
     fill_u32(kp.thr, 0x7f800000u, kp.rows * kp.nl * kp.S, st);
   }
   if (prev0 && r0 == 0 && c0 == 0 && r1 == c1 && (k1 == 0 || prev1)) {
-    TimedScope ts(c, 1, st);
+    TimedScope ts(c, kp.trefine, st);
     if (kp.prec == GCR_PREC_BF16 && (kp.ld == 1024 || kp.ld == 2048 || kp.ld == 4096))
       launch_seed_thresholds_bf16(kp.Xs, kp.ld, r1, prev0, k0, k1 ? prev1 : nullptr, k1, kp.n2, kp.rn,
                                   (const float*)kp.maxn2, sa.eps_s, sa.eps_n, kp.seed, order, st);
@@ -252,7 +288,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
     sa.thr_init = kp.seed;
   }
   {
-    TimedScope ts(c, 0, st);
+    TimedScope ts(c, kp.tsweep, st);
     launch_sim_topk(kp.prec, kp.nl, sa, st);
   }
   RefineArgs ra;
@@ -269,13 +305,20 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   ra.ovf_list = kp.ovf_list; ra.ovf_count = kp.fb_count + 1;
   ra.heavy_list = kp.heavy_list; ra.heavy_count = kp.fb_count + 2;
   ra.order = nullptr;
+  if (kp.raw) {
+    TimedScope ts(c, kp.trefine, st);
+    launch_raw_select(ra, st);
+    c->knn_rows += kp.rows;
+    c->splits = kp.S;
+    return;
+  }
   if (kp.ord && r0 == 0 && c0 == 0 && r1 == c1 && k0 > 0) {
-    TimedScope ts(c, 1, st);
+    TimedScope ts(c, kp.trefine, st);
     launch_cand_order(r1, kp.cand, kp.cnt, kp.S, kp.C, kp.nl, kp.ord_label, kp.ord_cnt, kp.ord_blk, kp.ord, st);
     ra.order = kp.ord;
   }
   {
-    TimedScope ts(c, 1, st);
+    TimedScope ts(c, kp.trefine, st);
     launch_refine(ra, st);
   }
   hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(1), 0, st, c->stats + 1, kp.fb_count);
@@ -292,7 +335,7 @@ gcr_status check_params(gcr_ctx* c, const gcr_params* p) {
   if (!(p->gamma > 0.f)) return fail(c, GCR_ERR_INVALID, "gamma must be > 0");
   if (!(p->alpha >= 0.f && p->alpha <= 1.f)) return fail(c, GCR_ERR_INVALID, "alpha must be in [0, 1]");
   if (!(p->beta_same > 0.f && p->beta_cross > 0.f)) return fail(c, GCR_ERR_INVALID, "beta factors must be > 0");
-  if (p->precision < 0 || p->precision > 2) return fail(c, GCR_ERR_INVALID, "unknown precision %d", p->precision);
+  if (p->precision < 0 || p->precision > 4) return fail(c, GCR_ERR_INVALID, "unknown precision %d", p->precision);
   if (p->rounds < 0) return fail(c, GCR_ERR_INVALID, "rounds must be >= 0");
   if (p->symmetric != 0 && p->symmetric != 1) return fail(c, GCR_ERR_INVALID, "symmetric must be 0 or 1");
   return GCR_OK;
@@ -450,7 +493,7 @@ void gcr_params_default(gcr_params* p) {
   p->lambda = 10.0f;
 }
 
-gcr_status gcr_create(gcr_ctx** out, int device) {
+gcr_status gcr_create(gcr_ctx** out, int device, size_t workspace_bytes) {
   if (!out) return GCR_ERR_INVALID;
   *out = nullptr;
   int nd = 0;
@@ -462,12 +505,26 @@ gcr_status gcr_create(gcr_ctx** out, int device) {
   c->device = device;
   if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->stats, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->stats) (void)hipFree(c->stats);
     delete c;
     return GCR_ERR_HIP;
+  }
+  if (workspace_bytes > 0 && reserve_ws(c, workspace_bytes) != GCR_OK) {
+    (void)hipFree(c->stats);
+    delete c;
+    return GCR_ERR_NOMEM;
   }
   *out = c;
   return GCR_OK;
 }
+
+gcr_status gcr_reserve(gcr_ctx* c, size_t workspace_bytes) {
+  if (!c) return GCR_ERR_INVALID;
+  return reserve_ws(c, workspace_bytes);
+}
+
+size_t gcr_workspace_bytes(const gcr_ctx* c) { return c ? c->ws_bytes : 0; }
 
 gcr_status gcr_destroy(gcr_ctx* c) {
   if (!c) return GCR_ERR_INVALID;
@@ -549,6 +606,7 @@ gcr_status gcr_knn(gcr_ctx* c, const float* X, int64_t n, int32_t d, const int32
   if (n < 1 || d <= 0 || !X) return fail(c, GCR_ERR_INVALID, "bad X / n / d");
   if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
   if (n > (int64_t)INT32_MAX / 2) return fail(c, GCR_ERR_UNSUPPORTED, "n too large");
+  if ((s = check_operand(c, p->precision, n, d)) != GCR_OK) return s;
   const bool cross = cr_idx != nullptr;
   if (cross && (!cam || !cr_dist)) return fail(c, GCR_ERR_INVALID, "cross list needs cam and cr_dist");
   if (p->k > 0 && (!idx || !dist)) return fail(c, GCR_ERR_INVALID, "idx / dist are NULL");
@@ -557,7 +615,7 @@ gcr_status gcr_knn(gcr_ctx* c, const float* X, int64_t n, int32_t d, const int32
   Arena dry;
   KnnPlan kp;
   plan_knn(dry, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
-  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  if ((s = need_ws(c, dry.off)) != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
   plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
   hipStream_t st = (hipStream_t)stream;
@@ -589,13 +647,14 @@ gcr_status gcr_build_graph(gcr_ctx* c, const float* X, int64_t n, int32_t d, con
     return fail(c, GCR_ERR_INVALID, "graph / X shape mismatch");
   if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
   if (g->has_cross && !cam) return fail(c, GCR_ERR_INVALID, "cross graph needs camera labels");
+  if ((s = check_operand(c, p->precision, n, d)) != GCR_OK) return s;
   HIP_TRY(c, hipSetDevice(c->device));
   Arena dry;
   KnnPlan kp;
   GraphTmp gt;
   plan_knn(dry, kp, p->precision, n, d, 0, n, 0, n, g->k, g->has_cross ? g->cross_k : 0);
   plan_graph_tmp(dry, gt, n);
-  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  if ((s = need_ws(c, dry.off)) != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
   plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, g->k, g->has_cross ? g->cross_k : 0);
   plan_graph_tmp(ar, gt, n);
@@ -614,7 +673,7 @@ gcr_status gcr_propagate(gcr_ctx* c, const gcr_graph* g, const float* X_in, floa
   GraphTmp gt;
   Arena dry;
   plan_graph_tmp(dry, gt, n);
-  gcr_status s = ensure_ws(c, dry.off);
+  gcr_status s = need_ws(c, dry.off);
   if (s != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
   plan_graph_tmp(ar, gt, n);
@@ -634,7 +693,63 @@ static void plan_final(Arena& ar, FinalPlan& fp, const gcr_params* p, int64_t nq
                        bool dense, bool topk) {
   const int64_t n = nq + ng;
   if (dense) plan_knn(ar, fp.kd, GCR_PREC_FP32, n, d, 0, nq, nq, n, 1, 0);
-  if (topk) plan_knn(ar, fp.kt, p->precision, n, d, 0, nq, nq, n, p->topk_out, 0);
+  if (topk) {
+    plan_knn(ar, fp.kt, final_screen_prec(p->precision), n, d, 0, nq, nq, n, p->topk_out, 0);
+    fp.kt.tsweep = 6;
+    fp.kt.trefine = 7;
+  }
+}
+
+// Workspace of a whole re-ranking: the two feature buffers, the graph (unless
+// the caller's last_graph is used), the locality-order scratch, then the kNN
+// plan of the rounds and the final plan overlaid on the same bytes (the
+// final launches follow the last round's on the same stream).
+struct RerankLayout {
+  float *xa = nullptr, *xb = nullptr;
+  gcr_graph g;
+  KnnPlan kp;
+  GraphTmp gt;
+  FinalPlan fp;
+};
+static void layout_rerank(Arena& ar, RerankLayout& L, const gcr_params* p, int64_t nq, int64_t ng, int d,
+                          int has_cross, int ck, bool own_graph, bool dense, bool topk) {
+  const int64_t n = nq + ng;
+  L.xa = ar.take<float>((size_t)n * d);
+  L.xb = ar.take<float>((size_t)n * d);
+  memset(&L.g, 0, sizeof(L.g));
+  if (own_graph) {
+    void* gbuf = ar.take<char>(gcr_graph_bytes(n, p->k, ck, has_cross));
+    if (gbuf) gcr_graph_bind(&L.g, gbuf, n, p->k, ck, has_cross);
+  }
+  plan_graph_tmp(ar, L.gt, n);
+  Arena fin = ar;
+  plan_knn(ar, L.kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
+  plan_final(fin, L.fp, p, nq, ng, d, dense, topk);
+  ar.off = std::max(ar.off, fin.off);
+}
+
+// GCR_Local: feature buffers, the neighbour lists, the locality-order
+// scratch, then the kNN plan and the final plan overlaid.
+struct LocalLayout {
+  float *xa = nullptr, *xb = nullptr, *dist = nullptr;
+  int32_t* idx = nullptr;
+  KnnPlan kp;
+  GraphTmp gt;
+  FinalPlan fp;
+};
+static void layout_local(Arena& ar, LocalLayout& L, const gcr_params* p, int64_t nq, int64_t ng, int d, bool dense,
+                         bool topk) {
+  const int64_t n = nq + ng;
+  const int k = p->k;
+  L.xa = ar.take<float>((size_t)n * d);
+  L.xb = ar.take<float>((size_t)n * d);
+  L.idx = ar.take<int32_t>((size_t)n * (k > 0 ? k : 1));
+  L.dist = ar.take<float>((size_t)n * (k > 0 ? k : 1));
+  plan_graph_tmp(ar, L.gt, n);
+  Arena fin = ar;
+  plan_knn(ar, L.kp, p->precision, n, d, 0, n, 0, n, k, 0);
+  plan_final(fin, L.fp, p, nq, ng, d, dense, topk);
+  ar.off = std::max(ar.off, fin.off);
 }
 static void run_final(gcr_ctx* c, const FinalPlan& fp, const float* X, int64_t nq, int64_t ng, int32_t d,
                       const gcr_params* p, float* dist_out, int32_t* topk_idx, float* topk_dist, hipStream_t st) {
@@ -662,13 +777,15 @@ gcr_status gcr_final_distances(gcr_ctx* c, const float* X, int64_t nq, int64_t n
   if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported");
   if (topk_idx && (!topk_dist || p->topk_out < 1 || p->topk_out > 120))
     return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
-  if (p->precision < 0 || p->precision > 2) return fail(c, GCR_ERR_INVALID, "unknown precision");
+  if (p->precision < 0 || p->precision > 4) return fail(c, GCR_ERR_INVALID, "unknown precision");
+  gcr_status s = GCR_OK;
+  if (dist_out && (s = check_operand(c, GCR_FP32, nq + ng, d)) != GCR_OK) return s;
+  if (topk_idx && (s = check_operand(c, final_screen_prec(p->precision), nq + ng, d)) != GCR_OK) return s;
   HIP_TRY(c, hipSetDevice(c->device));
   FinalPlan fp;
   Arena dry;
   plan_final(dry, fp, p, nq, ng, d, dist_out != nullptr, topk_idx != nullptr);
-  gcr_status s = ensure_ws(c, dry.off);
-  if (s != GCR_OK) return s;
+  if ((s = need_ws(c, dry.off)) != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
   plan_final(ar, fp, p, nq, ng, d, dist_out != nullptr, topk_idx != nullptr);
   run_final(c, fp, X, nq, ng, d, p, dist_out, topk_idx, topk_dist, (hipStream_t)stream);
@@ -678,7 +795,7 @@ gcr_status gcr_final_distances(gcr_ctx* c, const float* X, int64_t nq, int64_t n
 
 gcr_status gcr_rerank(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_t d, const int32_t* cam,
                       const gcr_params* p, float* dist_out, int32_t* topk_idx, float* topk_dist, float* X_final,
-                      void* stream) {
+                      gcr_graph* last_graph, void* stream) {
   if (!c) return GCR_ERR_INVALID;
   gcr_status s = check_params(c, p);
   if (s != GCR_OK) return s;
@@ -689,30 +806,28 @@ gcr_status gcr_rerank(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, int32_
     return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
   const int has_cross = (cam && p->alpha < 1.0f) ? 1 : 0;
   const int ck = has_cross ? cross_k_of(p) : 0;
+  if ((s = check_operand(c, p->precision, n, d)) != GCR_OK) return s;
+  if (dist_out && (s = check_operand(c, GCR_FP32, n, d)) != GCR_OK) return s;
+  if (last_graph && (last_graph->n != n || last_graph->k != p->k || last_graph->has_cross != has_cross ||
+                     (has_cross && last_graph->cross_k != ck) || !last_graph->idx || !last_graph->self))
+    return fail(c, GCR_ERR_INVALID, "last_graph must be bound for n = %lld, k = %d, cross_k = %d, has_cross = %d",
+                (long long)n, p->k, ck, has_cross);
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
 
-  auto plan = [&](Arena& ar, float** xa, float** xb, gcr_graph* g, KnnPlan& kp, GraphTmp& gt) {
-    *xa = ar.take<float>((size_t)n * d);
-    *xb = ar.take<float>((size_t)n * d);
-    void* gbuf = ar.take<char>(gcr_graph_bytes(n, p->k, ck, has_cross));
-    if (g && gbuf) gcr_graph_bind(g, gbuf, n, p->k, ck, has_cross);
-    plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
-    plan_graph_tmp(ar, gt, n);
-  };
-  float *xa, *xb;
-  gcr_graph g;
-  KnnPlan kp;
-  GraphTmp gt;
-  FinalPlan fp;
   const bool dense = dist_out != nullptr, topk = topk_idx != nullptr;
+  RerankLayout L;
   Arena dry;
-  plan(dry, &xa, &xb, nullptr, kp, gt);
-  plan_final(dry, fp, p, nq, ng, d, dense, topk);
-  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  layout_rerank(dry, L, p, nq, ng, d, has_cross, ck, last_graph == nullptr, dense, topk);
+  if ((s = need_ws(c, dry.off)) != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
-  plan(ar, &xa, &xb, &g, kp, gt);
-  plan_final(ar, fp, p, nq, ng, d, dense, topk);
+  layout_rerank(ar, L, p, nq, ng, d, has_cross, ck, last_graph == nullptr, dense, topk);
+  const gcr_graph& g = last_graph ? *last_graph : L.g;
+  float* xa = L.xa;
+  float* xb = L.xb;
+  const KnnPlan& kp = L.kp;
+  const GraphTmp& gt = L.gt;
+  const FinalPlan& fp = L.fp;
 
   if (p->normalize_input) {
     TimedScope ts(c, 5, st);
@@ -768,7 +883,7 @@ gcr_status gcr_dsfp(gcr_ctx* c, const float* X, const int32_t* idx, int64_t n, i
   Arena dry;
   GraphTmp gt;
   plan_graph_tmp(dry, gt, n);
-  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  if ((s = need_ws(c, dry.off)) != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
   plan_graph_tmp(ar, gt, n);
   HIP_TRY(c, enqueue_dsfp(c, gt, X, idx, n, d, k, gamma, rounds, Y, (hipStream_t)stream));
@@ -784,32 +899,27 @@ gcr_status gcr_rerank_local(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, 
   const int64_t n = nq + ng;
   if (!X || nq < 1 || ng < 1) return fail(c, GCR_ERR_INVALID, "bad X / nq / ng");
   if ((s = check_dsfp_args(c, n, d, p->k, p->gamma, p->rounds)) != GCR_OK) return s;
+  if ((s = check_operand(c, p->precision, n, d)) != GCR_OK) return s;
+  if (dist_out && (s = check_operand(c, GCR_FP32, n, d)) != GCR_OK) return s;
   if (topk_idx && (!topk_dist || p->topk_out < 1 || p->topk_out > 120))
     return fail(c, p->topk_out > 120 ? GCR_ERR_UNSUPPORTED : GCR_ERR_INVALID, "bad top-K output (K in 1..120)");
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const int k = p->k;
-  auto plan = [&](Arena& ar, float** xa, float** xb, int32_t** idx, float** dist, KnnPlan& kp, GraphTmp& gt) {
-    *xa = ar.take<float>((size_t)n * d);
-    *xb = ar.take<float>((size_t)n * d);
-    *idx = ar.take<int32_t>((size_t)n * (k > 0 ? k : 1));
-    *dist = ar.take<float>((size_t)n * (k > 0 ? k : 1));
-    plan_knn(ar, kp, p->precision, n, d, 0, n, 0, n, k, 0);
-    plan_graph_tmp(ar, gt, n);
-  };
-  float *xa, *xb, *dist;
-  int32_t* idx;
-  KnnPlan kp;
-  GraphTmp gt;
-  FinalPlan fp;
   const bool dense = dist_out != nullptr, topk = topk_idx != nullptr;
+  LocalLayout L;
   Arena dry;
-  plan(dry, &xa, &xb, &idx, &dist, kp, gt);
-  plan_final(dry, fp, p, nq, ng, d, dense, topk);
-  if ((s = ensure_ws(c, dry.off)) != GCR_OK) return s;
+  layout_local(dry, L, p, nq, ng, d, dense, topk);
+  if ((s = need_ws(c, dry.off)) != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
-  plan(ar, &xa, &xb, &idx, &dist, kp, gt);
-  plan_final(ar, fp, p, nq, ng, d, dense, topk);
+  layout_local(ar, L, p, nq, ng, d, dense, topk);
+  float* xa = L.xa;
+  float* xb = L.xb;
+  float* dist = L.dist;
+  int32_t* idx = L.idx;
+  const KnnPlan& kp = L.kp;
+  const GraphTmp& gt = L.gt;
+  const FinalPlan& fp = L.fp;
 
   if (p->normalize_input) {
     TimedScope ts(c, 5, st);
@@ -822,6 +932,80 @@ gcr_status gcr_rerank_local(gcr_ctx* c, const float* X, int64_t nq, int64_t ng, 
   if (X_final) HIP_TRY(c, hipMemcpyAsync(X_final, xb, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, st));
   HIP_TRY(c, hipGetLastError());
   return GCR_OK;
+}
+
+static int profile_ksplit(int64_t nf) { return (int)std::min<int64_t>(64, std::max<int64_t>(1, nf / 2048)); }
+
+// Workspace of the profile vectors: per-tracklet means, the group mean, the
+// member and frame row lists, split-K Gram partials and the Gram, and the
+// Chebyshev iterates of the largest group (maxm members).
+struct ProfileLayout {
+  float *mu_c, *mu, *part, *G, *B, *Wt, *P, *R, *tr;
+  int32_t *dm, *dr;
+};
+static void layout_profile(Arena& ar, ProfileLayout& L, int64_t nt, int64_t nf, int64_t maxm, int d, int mode,
+                           int ksplit) {
+  L.mu_c = ar.take<float>((size_t)nt * d);
+  L.mu = ar.take<float>((size_t)d);
+  L.dm = ar.take<int32_t>((size_t)nt);
+  L.dr = ar.take<int32_t>((size_t)nf);
+  L.part = mode == 0 ? ar.take<float>((size_t)ksplit * d * d) : nullptr;
+  L.G = mode == 0 ? ar.take<float>((size_t)d * d) : nullptr;
+  L.B = ar.take<float>((size_t)maxm * d);
+  L.Wt = ar.take<float>((size_t)maxm * d);
+  L.P = ar.take<float>((size_t)maxm * d);
+  L.R = ar.take<float>((size_t)maxm * d);
+  L.tr = ar.take<float>(64);
+}
+
+size_t gcr_profile_workspace_size(int32_t nt, int64_t nf, int32_t d, int32_t mode) {
+  if (nt < 1 || nf < nt || d < 1 || d > 8192 || (mode != 0 && mode != 1)) return 0;
+  ProfileLayout L;
+  Arena dry;
+  layout_profile(dry, L, nt, nf, nt, d, mode, profile_ksplit(nf));
+  return dry.off + 256;
+}
+
+// Largest workspace any batch entry point needs at these sizes.
+size_t gcr_workspace_size(const gcr_params* p, int64_t nq, int64_t ng, int32_t d, int32_t with_cameras) {
+  if (!p || nq < 0 || ng < 0 || nq + ng < 1 || d < 1 || d > 2048) return 0;
+  if (check_params(nullptr, p) != GCR_OK) return 0;
+  const int64_t n = nq + ng;
+  if (n > (int64_t)INT32_MAX / 2) return 0;
+  if (check_operand(nullptr, p->precision, n, d) != GCR_OK || check_operand(nullptr, GCR_FP32, n, d) != GCR_OK)
+    return 0;
+  const int ck = with_cameras ? cross_k_of(p) : 0;
+  size_t best = 0;
+  {  // gcr_knn, gcr_build_graph, gcr_propagate, gcr_dsfp over n rows
+    Arena a;
+    KnnPlan kp;
+    GraphTmp gt;
+    plan_knn(a, kp, p->precision, n, d, 0, n, 0, n, p->k, ck);
+    plan_graph_tmp(a, gt, n);
+    best = std::max(best, a.off);
+  }
+  if (nq >= 1 && ng >= 1) {
+    const bool topk = p->topk_out >= 1 && p->topk_out <= 120;
+    {
+      Arena a;
+      FinalPlan fp;
+      plan_final(a, fp, p, nq, ng, d, true, topk);
+      best = std::max(best, a.off);
+    }
+    {
+      Arena a;
+      RerankLayout L;
+      layout_rerank(a, L, p, nq, ng, d, with_cameras ? 1 : 0, ck, true, true, topk);
+      best = std::max(best, a.off);
+    }
+    if (p->k <= DSFP_K_MAX) {
+      Arena a;
+      LocalLayout L;
+      layout_local(a, L, p, nq, ng, d, true, topk);
+      best = std::max(best, a.off);
+    }
+  }
+  return best + 256;
 }
 
 gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* offsets, const int32_t* group,
@@ -862,30 +1046,17 @@ gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* o
   rstart.push_back((int64_t)rows.size());
   int maxm = 0;
   for (size_t q = 0; q + 1 < mstart.size(); ++q) maxm = std::max<int>(maxm, (int)(mstart[q + 1] - mstart[q]));
-  const int ksplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, nf / 2048));
+  const int ksplit = profile_ksplit(nf);
 
-  auto plan = [&](Arena& ar, float** mu_c, float** mu, int32_t** dm, int32_t** dr, float** part, float** G,
-                  float** B, float** Wt, float** P, float** R, float** tr) {
-    *mu_c = ar.take<float>((size_t)nt * d);
-    *mu = ar.take<float>((size_t)d);
-    *dm = ar.take<int32_t>(members.size());
-    *dr = ar.take<int32_t>(rows.size());
-    *part = mode == 0 ? ar.take<float>((size_t)ksplit * d * d) : nullptr;
-    *G = mode == 0 ? ar.take<float>((size_t)d * d) : nullptr;
-    *B = ar.take<float>((size_t)maxm * d);
-    *Wt = ar.take<float>((size_t)maxm * d);
-    *P = ar.take<float>((size_t)maxm * d);
-    *R = ar.take<float>((size_t)maxm * d);
-    *tr = ar.take<float>(64);
-  };
-  float *mu_c, *mu, *part, *G, *B, *Wt, *P, *R, *tr;
-  int32_t *dm, *dr;
+  ProfileLayout L;
   Arena dry;
-  plan(dry, &mu_c, &mu, &dm, &dr, &part, &G, &B, &Wt, &P, &R, &tr);
-  gcr_status s = ensure_ws(c, dry.off);
+  layout_profile(dry, L, nt, (int64_t)rows.size(), maxm, d, mode, ksplit);
+  gcr_status s = need_ws(c, dry.off);
   if (s != GCR_OK) return s;
   Arena ar{(char*)c->ws, 0};
-  plan(ar, &mu_c, &mu, &dm, &dr, &part, &G, &B, &Wt, &P, &R, &tr);
+  layout_profile(ar, L, nt, (int64_t)rows.size(), maxm, d, mode, ksplit);
+  float *mu_c = L.mu_c, *mu = L.mu, *part = L.part, *G = L.G, *B = L.B, *Wt = L.Wt, *P = L.P, *R = L.R;
+  int32_t *dm = L.dm, *dr = L.dr;
   HIP_TRY(c, hipMemcpyAsync(dm, members.data(), members.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(dr, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, st));
   launch_segment_means(frames, offsets, nt, d, mu_c, st);

@@ -58,6 +58,8 @@ struct KnnPlan {
   unsigned* thr_shared;
   float* fb_cut; uint64_t* band; int* band_cnt; int band_cap, band_max; int* ovf_list; int* heavy_list;
   int32_t *ord, *ord_label, *ord_cnt, *ord_blk;  // refine row order (square sweeps)
+  int tsweep = 0, trefine = 1;  // timer classes of the screening sweep and its refine
+  int raw = 0;                  // 1: screened keys decide the lists (no exact re-score)
 };
 
 struct GraphTmp {
@@ -67,9 +69,16 @@ struct GraphTmp {
 };
 
 gcr_status fail(gcr_ctx* c, gcr_status s, const char* fmt, ...);
-gcr_status ensure_ws(gcr_ctx* c, size_t bytes);
+gcr_status reserve_ws(gcr_ctx* c, size_t bytes);
+gcr_status need_ws(gcr_ctx* c, size_t bytes);
 void fill_u32(void* p, unsigned v, int64_t n, hipStream_t st);
 int esize_of(int prec);
+// Screening operand precision of a gcr_precision value, and whether it is a
+// screening-only (raw) mode.
+int screen_prec_of(int precision);
+int is_raw_precision(int precision);
+int final_screen_prec(int precision);
+gcr_status check_operand(gcr_ctx* c, int precision, int64_t rows, int d);
 int compute_units();
 float eps_accumulation(int prec, int d);
 float eps_norm(int d);

@@ -133,6 +133,8 @@ void launch_merge_splits(const MergeArgs& m, hipStream_t st);
 // queued pairs handled by the column-parallel exhaustive path (batch calls)
 constexpr int FB_MAX = 8192;
 void launch_refine(const RefineArgs& a, hipStream_t st);
+// k smallest screened keys per (row, list), no exact re-score (raw modes).
+void launch_raw_select(const RefineArgs& a, hipStream_t st);
 
 // ---- graph.hip : affinities, reverse CSR, degrees, normalised values
 struct GraphBuildArgs {

@@ -1142,6 +1142,68 @@ void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx
 #undef GCR_SEED
 }
 
+// ---------------------------------------------------------------------------
+// Screening-only selection (the raw precision modes): per (row, list) the k
+// smallest screened keys of the union of the split buffers, ties by column,
+// with no exact re-score.  The reported distance is n2_i + key (squared norms
+// exact in float32, the inner product screened), clamped at zero.  Every
+// split buffer holds all of its items up to its threshold, which is at least
+// the split's own k-th key, so the union holds the row's k smallest screened
+// keys.  One wave per pair: k rounds of "smallest entry above the last one".
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(v >> 32), off, 64) << 32) |
+                       (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)v, off, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void raw_select_kernel(RefineArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t items = (a.r1 - a.r0) * a.NL;
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= items) return;
+  const int64_t rrel = p / a.NL;
+  const int L = (int)(p - rrel * a.NL);
+  const int64_t row = a.r0 + rrel;
+  const int kk = L == 0 ? a.k0 : a.k1;
+  int32_t* oidx = (L == 0 ? a.idx0 : a.idx1) + rrel * kk;
+  float* odist = (L == 0 ? a.dist0 : a.dist1) + rrel * kk;
+  const int64_t o = (rrel * a.NL + L) * (int64_t)a.S;
+  const float n2r = a.n2[row];
+  uint64_t prev = 0;
+  for (int t = 0; t < kk; ++t) {
+    uint64_t best = GCR_EMPTY;
+    for (int s = 0; s < a.S; ++s) {
+      const int cs = min(a.cnt[o + s], a.C);
+      const uint64_t* b = a.cand + (o + s) * (int64_t)a.C;
+      for (int e = lane; e < cs; e += 64) {
+        const uint64_t v = b[e];
+        if ((t == 0 || v > prev) && v < best) best = v;
+      }
+    }
+    best = wave_min_u64(best);
+    if (lane == 0) {
+      if (best == GCR_EMPTY) {
+        oidx[t] = -1;
+        odist[t] = INFINITY;
+      } else {
+        oidx[t] = (int32_t)cand_col(best);
+        odist[t] = fmaxf(0.0f, n2r + cand_key(best));
+      }
+    }
+    prev = best;
+  }
+}
+
+void launch_raw_select(const RefineArgs& a, hipStream_t st) {
+  const int64_t items = (a.r1 - a.r0) * a.NL;
+  if (items <= 0) return;
+  hipLaunchKernelGGL(raw_select_kernel, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, a);
+}
+
 void launch_refine(const RefineArgs& a, hipStream_t st) {
   const int64_t rows = a.r1 - a.r0;
   if (rows <= 0) return;

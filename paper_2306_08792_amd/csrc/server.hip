@@ -236,7 +236,7 @@ std::string enqueue_request(gcr_server* s, Slot& sl, Request& r) {
   float* q0 = s->X[0] + sl.qbase * d;
   SRV_HIP(hipMemcpyAsync(q0, sl.h_q, (size_t)b * d * sizeof(float), hipMemcpyHostToDevice, st));
   if (s->p.normalize_input) launch_normalize_rows(q0, q0, b, d, st);
-  launch_screen_prep_rows(s->prec, s->X[0], sl.qbase, b, nullptr, d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
+  launch_screen_prep_rows(s->op0.prec, s->X[0], sl.qbase, b, nullptr, d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
                           s->op0.rn, sl.scratch_max, st);
   if (L == 0) {
     serve_knn(s->op0, (const float*)s->max0, s->X[0], d, sl.knA, sl.qbase, b, 0, s->G, K, sl.oi, sl.od,
@@ -273,9 +273,9 @@ std::string enqueue_request(gcr_server* s, Slot& sl, Request& r) {
     // resident copy (recomputed ones masked out), recomputed rows from the
     // slot, merged
     launch_copy_u32(s->maxLg, sl.maxL, 2, st);
-    launch_screen_prep_rows(s->prec, s->X[L], sl.qbase, b, nullptr, d, s->opL.Xs, s->opL.ld, s->opL.n2,
+    launch_screen_prep_rows(s->opL.prec, s->X[L], sl.qbase, b, nullptr, d, s->opL.Xs, s->opL.ld, s->opL.n2,
                             s->opL.scale, s->opL.rn, sl.scratch_max, st);
-    launch_screen_prep_rows(s->prec, s->X[L], sl.pbase, s->Rc, sl.counts + L, d, s->opL.Xs, s->opL.ld, s->opL.n2,
+    launch_screen_prep_rows(s->opL.prec, s->X[L], sl.pbase, s->Rc, sl.counts + L, d, s->opL.Xs, s->opL.ld, s->opL.n2,
                             s->opL.scale, s->opL.rn, sl.maxL, st);
     ColumnFilter fa;
     fa.stamp_of = sl.mark[L];
@@ -383,18 +383,23 @@ void plan_server(Arena& ar, gcr_server* s) {
   const int64_t npad = roundup(s->rows_total, 128) + 128;
   s->X.assign(s->L + 1, nullptr);
   for (int t = 0; t <= s->L; ++t) s->X[t] = ar.take<float>((size_t)s->rows_total * s->d);
-  auto plan_op = [&](Operand& o) {
-    o.prec = s->prec;
+  // The final top-K screens in BF16 when the kNN screening is FP8: at
+  // K = 100 the K-th neighbour lies among unrelated items, and FP8's margin
+  // would admit thousands of them per query (the refine's exhaustive path).
+  const int prec_final = final_screen_prec(s->prec);
+  auto plan_op = [&](Operand& o, int prec) {
+    o.prec = prec;
     o.npad = npad;
-    o.ld = roundup((int64_t)s->d * esize_of(s->prec), 128);
+    o.ld = roundup((int64_t)s->d * esize_of(prec), 128);
     o.kch = (int)(o.ld / 128);
     o.Xs = ar.take<uint8_t>((size_t)(npad * o.ld));
     o.n2 = ar.take<float>(npad);
     o.scale = ar.take<float>(npad);
     o.rn = ar.take<float>(npad);
   };
-  plan_op(s->op0);
-  if (s->L > 0) plan_op(s->opL);
+  // with no rounds the round-0 operand serves only the final top-K
+  plan_op(s->op0, s->L > 0 ? s->prec : prec_final);
+  if (s->L > 0) plan_op(s->opL, prec_final);
   else s->opL = s->op0;
   s->max0 = ar.take<unsigned>(64);
   s->maxLg = ar.take<unsigned>(64);
@@ -473,6 +478,8 @@ gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config
   if (p->rebuild_each_round) return fail(ctx, GCR_ERR_INVALID, "serving keeps the gallery graph fixed "
                                                                "(rebuild_each_round must be 0)");
   if (p->symmetric != 1) return fail(ctx, GCR_ERR_UNSUPPORTED, "serving uses the symmetric normalisation");
+  if (is_raw_precision(p->precision))
+    return fail(ctx, GCR_ERR_UNSUPPORTED, "serving needs an exact mode (raw screening is not served)");
   gcr_server_config c;
   gcr_server_config_default(&c);
   if (cfg) c = *cfg;
@@ -481,6 +488,12 @@ gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config
   const int64_t cap = c.gallery_capacity > 0 ? c.gallery_capacity : ng;
   if (cap < ng) return fail(ctx, GCR_ERR_INVALID, "gallery_capacity is below the gallery size");
   if (cap > (int64_t)1 << 30) return fail(ctx, GCR_ERR_UNSUPPORTED, "galleries above 2^30 items are not supported");
+  {
+    // screening operands over the gallery capacity plus every slot's rows
+    const int64_t rq = std::min(c.max_batch, 16384 / p->k), rc = std::min<int64_t>(c.max_recomputed, cap);
+    const gcr_status ost = check_operand(ctx, p->precision, cap + (int64_t)c.slots * (rq + rc), d);
+    if (ost != GCR_OK) return ost;
+  }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
 
   gcr_server* s = new gcr_server();
@@ -523,7 +536,7 @@ gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config
   Arena ar{(char*)s->mem, 0};
   plan_server(ar, s);
   hipError_t e = hipStreamCreateWithFlags(&s->mst, hipStreamNonBlocking);
-  if (e == hipSuccess && gcr_create(&s->mctx, ctx->device) != GCR_OK) e = hipErrorOutOfMemory;
+  if (e == hipSuccess && gcr_create(&s->mctx, ctx->device, 0) != GCR_OK) e = hipErrorOutOfMemory;
   if (e != hipSuccess) {
     release(s);
     return fail(ctx, GCR_ERR_HIP, "server set-up: %s", hipGetErrorString(e));
@@ -537,7 +550,7 @@ gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config
 
 // Workspace of the private context for a plan of `bytes`.
 std::string mctx_ws(gcr_server* s, size_t bytes) {
-  if (ensure_ws(s->mctx, bytes) != GCR_OK) return std::string("maintenance workspace: ") + gcr_last_error(s->mctx);
+  if (reserve_ws(s->mctx, bytes) != GCR_OK) return std::string("maintenance workspace: ") + gcr_last_error(s->mctx);
   return "";
 }
 
@@ -573,11 +586,11 @@ std::string refresh_gallery(gcr_server* s) {
   enqueue_graph_from_lists(s->mctx, gt, s->G, nullptr, &gp, &s->g, st);
   for (int t = 1; t <= s->L; ++t) enqueue_propagate(s->mctx, &s->g, s->X[t - 1], s->X[t], s->G, s->d, st, gt.order);
   fill_u32(s->max0, 0u, 2, st);
-  launch_screen_prep_rows(s->prec, s->X[0], 0, s->G, nullptr, s->d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
+  launch_screen_prep_rows(s->op0.prec, s->X[0], 0, s->G, nullptr, s->d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
                           s->op0.rn, s->max0, st);
   if (s->L > 0) {
     fill_u32(s->maxLg, 0u, 2, st);
-    launch_screen_prep_rows(s->prec, s->X[s->L], 0, s->G, nullptr, s->d, s->opL.Xs, s->opL.ld, s->opL.n2,
+    launch_screen_prep_rows(s->opL.prec, s->X[s->L], 0, s->G, nullptr, s->d, s->opL.Xs, s->opL.ld, s->opL.n2,
                             s->opL.scale, s->opL.rn, s->maxLg, st);
   }
   SRV_HIP(hipStreamSynchronize(st));
@@ -710,8 +723,14 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_
   gcr_server* s = nullptr;
   gcr_status st = server_new(ctx, p, cfg, ng, d, &s);
   if (st != GCR_OK) return st;
-  // resident gallery: level-0 features as given (float32, or BF16 widened)
-  hipError_t e = hipSuccess;
+  // resident gallery: level-0 features as given (float32, or BF16 widened).
+  // The copy runs on the server's own stream: finish whatever the caller
+  // enqueued on any stream first (it may still be writing the gallery).
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    release(s);
+    return fail(ctx, GCR_ERR_HIP, "hipDeviceSynchronize before the gallery copy: %s", hipGetErrorString(e));
+  }
   if (gallery_dtype == 0)
     e = hipMemcpyAsync(s->X[0], gallery, (size_t)ng * d * sizeof(float), hipMemcpyDeviceToDevice, s->mst);
   else

@@ -24,8 +24,8 @@ import torch
 
 from . import _lib as L
 
-FP32, BF16, FP8 = 0, 1, 2
-PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
+FP32, BF16, FP8, BF16_RAW, FP8_RAW = 0, 1, 2, 3, 4
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8, "bf16_raw": BF16_RAW, "fp8_raw": FP8_RAW}
 
 
 @dataclasses.dataclass
@@ -130,19 +130,46 @@ class Graph:
 
 
 class Context:
-    """A library context bound to one GPU (gcr_ctx)."""
+    """A library context bound to one GPU (gcr_ctx).
 
-    def __init__(self, device: int = 0):
+    workspace_bytes: the context's workspace at creation (see
+    workspace_size()).  auto_reserve: before each call, grow the workspace
+    to what gcr_workspace_size reports for the call's sizes (gcr_reserve,
+    which synchronises the device); with False a call that needs more fails
+    with NOMEM, and nothing allocates after creation (capture-safe use)."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 0, auto_reserve: bool = True):
         if not torch.cuda.is_available():
             raise GcrError("no GPU visible: the GCR library has no CPU path")
         self.lib = L.load()
         self.device = torch.device("cuda", device)
+        self.auto_reserve = auto_reserve
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            st = self.lib.gcr_create(C.byref(h), device)
+            st = self.lib.gcr_create(C.byref(h), device, int(workspace_bytes))
         if st != L.GCR_OK:
             raise GcrError(f"gcr_create failed ({L.STATUS_NAMES.get(st, st)})")
         self.h = h
+
+    @staticmethod
+    def workspace_size(p: "Params", nq: int, ng: int, d: int, with_cameras: bool = False) -> int:
+        """Workspace bytes every batch call needs at these sizes (0: unsupported)."""
+        lib = L.load()
+        pc = p.c()
+        return int(lib.gcr_workspace_size(C.byref(pc), nq, ng, d, int(with_cameras)))
+
+    def workspace_bytes(self) -> int:
+        return int(self.lib.gcr_workspace_bytes(self.h))
+
+    def reserve(self, nbytes: int):
+        self._ok(self.lib.gcr_reserve(self.h, int(nbytes)), "gcr_reserve")
+
+    def _need(self, p: "Params", nq: int, ng: int, d: int, with_cameras: bool = False):
+        if not self.auto_reserve:
+            return
+        nb = self.workspace_size(p, nq, ng, d, with_cameras)
+        if nb > self.workspace_bytes():
+            self.reserve(nb)
 
     def close(self):
         if getattr(self, "h", None):
@@ -202,6 +229,7 @@ class Context:
             cdist = torch.empty((n, ck), dtype=torch.float32, device=self.device)
         if cam is not None:
             _check(cam, torch.int32, "cam", self.device)
+        self._need(p, 0, n, d, cross)
         pc = p.c()
         self._ok(self.lib.gcr_knn(self.h, _ptr(X), n, d, _ptr(cam), C.byref(pc), _ptr(idx), _ptr(dist),
                                   _ptr(cidx), _ptr(cdist), _stream()), "gcr_knn")
@@ -214,6 +242,7 @@ class Context:
         if cam is not None:
             _check(cam, torch.int32, "cam", self.device)
         g = Graph(n, p.k, p.cross_k, has_cross, self.device)
+        self._need(p, 0, n, d, has_cross)
         pc = p.c()
         self._ok(self.lib.gcr_build_graph(self.h, _ptr(X), n, d, _ptr(cam), C.byref(pc), C.byref(g.g),
                                           _stream()), "gcr_build_graph")
@@ -222,6 +251,7 @@ class Context:
     def propagate(self, g: Graph, X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         _check(X, torch.float32, "X", self.device)
         Y = torch.empty_like(X) if out is None else out
+        self._need(Params(k=0), 0, X.shape[0], X.shape[1])
         self._ok(self.lib.gcr_propagate(self.h, C.byref(g.g), _ptr(X), _ptr(Y), X.shape[0], X.shape[1],
                                         _stream()), "gcr_propagate")
         return Y
@@ -233,6 +263,7 @@ class Context:
         D = torch.empty((nq, ng), dtype=torch.float32, device=self.device) if dense else None
         ti = torch.empty((nq, p.topk_out), dtype=torch.int32, device=self.device) if topk else None
         td = torch.empty((nq, p.topk_out), dtype=torch.float32, device=self.device) if topk else None
+        self._need(p, nq, ng, d)
         pc = p.c()
         self._ok(self.lib.gcr_final_distances(self.h, _ptr(X), nq, ng, d, C.byref(pc), _ptr(D), _ptr(ti),
                                               _ptr(td), _stream()), "gcr_final_distances")
@@ -240,8 +271,10 @@ class Context:
 
     def rerank(self, X: torch.Tensor, nq: int, p: Params, cam: Optional[torch.Tensor] = None,
                dense: bool = True, topk: bool = False, keep_features: bool = False,
-               out: Optional[dict] = None):
-        """Whole re-ranking; returns dict(dist, topk_idx, topk_dist, X)."""
+               out: Optional[dict] = None, last_graph: Optional["Graph"] = None):
+        """Whole re-ranking; returns dict(dist, topk_idx, topk_dist, X).
+        last_graph: a Graph (from new_graph) that receives the graph of the
+        last round."""
         _check(X, torch.float32, "X", self.device)
         if cam is not None:
             _check(cam, torch.int32, "cam", self.device)
@@ -255,13 +288,20 @@ class Context:
             o["topk_dist"] = torch.empty((nq, p.topk_out), dtype=torch.float32, device=self.device)
         if keep_features and o.get("X") is None:
             o["X"] = torch.empty_like(X)
+        self._need(p, nq, ng, d, cam is not None)
         pc = p.c()
         self._ok(self.lib.gcr_rerank(self.h, _ptr(X), nq, ng, d, _ptr(cam), C.byref(pc),
                                      _ptr(o.get("dist") if dense else None),
                                      _ptr(o.get("topk_idx") if topk else None),
                                      _ptr(o.get("topk_dist") if topk else None),
-                                     _ptr(o.get("X") if keep_features else None), _stream()), "gcr_rerank")
+                                     _ptr(o.get("X") if keep_features else None),
+                                     C.byref(last_graph.g) if last_graph is not None else None, _stream()),
+                 "gcr_rerank")
         return o
+
+    def new_graph(self, n: int, p: Params, has_cross: bool = False) -> "Graph":
+        """An empty graph bound for n nodes with p.k (and p.cross_k)."""
+        return Graph(n, p.k, p.cross_k, has_cross, self.device)
 
     def dsfp(self, X: torch.Tensor, idx: Optional[torch.Tensor], p: Params,
              out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -274,6 +314,7 @@ class Context:
             _check(idx, torch.int32, "idx", self.device)
             k = idx.shape[1]
         Y = out if out is not None else torch.empty_like(X)
+        self._need(Params(k=0), 0, n, d)
         self._ok(self.lib.gcr_dsfp(self.h, _ptr(X), _ptr(idx), n, d, k, p.gamma, p.rounds, _ptr(Y), _stream()),
                  "gcr_dsfp")
         return Y
@@ -293,6 +334,7 @@ class Context:
             o["topk_dist"] = torch.empty((nq, p.topk_out), dtype=torch.float32, device=self.device)
         if keep_features and o.get("X") is None:
             o["X"] = torch.empty_like(X)
+        self._need(p, nq, ng, d)
         pc = p.c()
         self._ok(self.lib.gcr_rerank_local(self.h, _ptr(X), nq, ng, d, C.byref(pc),
                                            _ptr(o.get("dist") if dense else None),
@@ -316,6 +358,10 @@ class Context:
             grp_d = grp_h.to(self.device)
         W = torch.empty((nt, frames.shape[1]), dtype=torch.float32, device=self.device)
         m = {"pvg": 0, "mean": 1}[mode]
+        if self.auto_reserve:
+            nb = int(self.lib.gcr_profile_workspace_size(nt, frames.shape[0], frames.shape[1], m))
+            if nb > self.workspace_bytes():
+                self.reserve(nb)
         self._ok(self.lib.gcr_profile_vectors(self.h, _ptr(frames), _ptr(offs_d), _ptr(grp_d), _ptr(offs_h),
                                               _ptr(grp_h), nt, frames.shape[1], m, lam, _ptr(W), _stream()),
                  "gcr_profile_vectors")

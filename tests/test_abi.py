@@ -100,3 +100,48 @@ def test_serving_gallery_bf16_is_round_to_nearest_even():
     g = r.view(np.float32).astype(np.float64)
     ulp = np.abs(g) * 2.0 ** -7
     assert np.all(np.abs(g - f) <= ulp / 2 + 1e-45)
+
+
+def _params(lib, **kw):
+    p = L.GcrParams()
+    lib.gcr_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_workspace_size_host_only(lib):
+    """gcr_workspace_size plans on the host: it grows with the problem, covers
+    the cross-camera lists, and is 0 for invalid or unsupported sizes."""
+    p = _params(lib, k=20, precision=1, topk_out=100)
+    small = lib.gcr_workspace_size(C.byref(p), 500, 1500, 256, 0)
+    big = lib.gcr_workspace_size(C.byref(p), 5000, 15000, 256, 0)
+    cams = lib.gcr_workspace_size(C.byref(p), 5000, 15000, 256, 1)
+    assert 0 < small < big <= cams
+    # n rows only (nq = 0): the entry points that take one feature matrix
+    assert 0 < lib.gcr_workspace_size(C.byref(p), 0, 2000, 256, 0) <= small
+    assert lib.gcr_workspace_size(C.byref(p), 0, 0, 256, 0) == 0
+    assert lib.gcr_workspace_size(C.byref(p), 10, 10, 4096, 0) == 0
+    bad = _params(lib, k=20, gamma=-1.0)
+    assert lib.gcr_workspace_size(C.byref(bad), 10, 10, 64, 0) == 0
+    assert lib.gcr_profile_workspace_size(10, 100, 64, 0) > lib.gcr_profile_workspace_size(10, 100, 64, 1) > 0
+    assert lib.gcr_profile_workspace_size(10, 5, 64, 0) == 0
+
+
+def test_screening_operand_guard_host_only(lib):
+    """The similarity kernel addresses its screening operand with 32-bit byte
+    offsets: shapes whose padded operand reaches 4 GiB are refused on the
+    host (workspace size 0; the entry points return UNSUPPORTED)."""
+    fp32 = _params(lib, k=20, precision=0, topk_out=100)
+    bf16 = _params(lib, k=20, precision=1, topk_out=100)
+    d = 2048
+    # float32 rows of 8 KiB: 524,288 rows make 4 GiB with the padding
+    assert lib.gcr_workspace_size(C.byref(fp32), 0, 500_000, d, 0) > 0
+    assert lib.gcr_workspace_size(C.byref(fp32), 0, 530_000, d, 0) == 0
+    # BF16 screening halves the row; the dense final distances still need a
+    # float32 operand, so a whole re-ranking is bounded by that one
+    assert lib.gcr_workspace_size(C.byref(bf16), 0, 1_000_000, d, 0) == 0  # float32 dense operand
+    assert lib.gcr_workspace_size(C.byref(bf16), 0, 500_000, d, 0) > 0
+    # d = 256: BF16 rows of 512 B, float32 rows of 1 KiB (the float32 operand binds)
+    assert lib.gcr_workspace_size(C.byref(bf16), 0, 4_000_000, 256, 0) > 0
+    assert lib.gcr_workspace_size(C.byref(bf16), 0, 4_300_000, 256, 0) == 0

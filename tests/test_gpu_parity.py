@@ -11,7 +11,7 @@ import torch
 
 from oracle import gcr_oracle as O
 from paper_2306_08792_amd import datagen
-from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params
+from paper_2306_08792_amd.gcr import BF16, BF16_RAW, FP8, FP8_RAW, FP32, Context, Params
 
 from parity import (check_distances, check_features, check_knn_rows,
                     oracle_round_from_lists)
@@ -57,6 +57,33 @@ def test_knn_matches_exhaustive(ctx, prec, n, d, k, seed):
     p = Params(k=k, precision=prec)
     idx, dist = ctx.knn(dev(X), p)
     check_knn_rows(host(idx), host(dist), X, np.arange(n), k)
+
+
+@pytest.mark.parametrize("prec,eps", [(BF16_RAW, 0.0080), (FP8_RAW, 0.14)])
+@pytest.mark.parametrize("n,d", [(517, 256), (300, 512)])
+def test_knn_raw_modes(ctx, prec, eps, n, d):
+    """Screening-only modes: errors are reported, not gated, so this checks
+    what holds for any screened selection.  With |s~ - s| <= eps for unit
+    rows, every reported distance is within 2 eps of the exact one, the list
+    is ordered by (reported distance, index), and every member's exact
+    distance is at most the exact k-th distance + 4 eps."""
+    print(f"raw knn prec={prec} n={n} d={d}", flush=True)
+    X = case(n, d, 5).astype(np.float64)
+    k = 20
+    idx, dist = ctx.knn(dev(X), Params(k=k, precision=prec))
+    gi, gd = host(idx), host(dist).astype(np.float64)
+    D = O.sq_dists(X)
+    ref, _ = O.knn_lists(D, k)
+    agree = 0
+    for i in range(n):
+        assert np.all(gi[i] >= 0) and len(set(gi[i].tolist())) == k and i not in gi[i]
+        ex = D[i, gi[i]]
+        assert np.all(np.abs(gd[i] - ex) <= 2 * eps), f"row {i}: reported distance off by more than 2 eps"
+        assert all((gd[i, t], gi[i, t]) <= (gd[i, t + 1], gi[i, t + 1]) for t in range(k - 1)), f"row {i}: order"
+        kth = D[i, ref[i, -1]]
+        assert np.all(ex <= kth + 4 * eps), f"row {i}: member beyond the k-th distance + 4 eps"
+        agree += int(set(gi[i].tolist()) == set(ref[i].tolist()))
+    print(f"raw mode {prec}: {agree}/{n} lists equal the exact ones", flush=True)
 
 
 @pytest.mark.parametrize("prec", PRECS)
