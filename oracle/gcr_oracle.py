@@ -76,6 +76,7 @@ __all__ = [
     "sparse_round_from_lists",
     "degrees_from_lists",
     "knn_rows",
+    "knn_blocked",
     "serve_request",
     "local_set",
     "dsfp",
@@ -157,6 +158,54 @@ def knn_rows(Drow_block: np.ndarray, rows: np.ndarray, k: int,
         take = cand[order[:k]]
         idx[t, : len(take)] = take
         dist[t, : len(take)] = Drow_block[t, take]
+    return idx, dist
+
+
+def knn_blocked(X: np.ndarray, k: int, rows: Optional[np.ndarray] = None,
+                cam: Optional[np.ndarray] = None, cross: bool = False,
+                block: int = 1024, threads: int = 0):
+    """The same lists as knn_rows (first min(k, |C_i|) of C_i by (distance,
+    index)) for inputs where the N x N matrix does not fit: distance rows
+    are formed a block at a time (the sq_dists arithmetic), the k-th smallest
+    eligible distance is found by a partition, every eligible item at or
+    below it is kept (so ties at the cut are all present) and those are
+    stably sorted by distance, index order breaking ties.  Blocks run on a
+    thread pool (NumPy's BLAS and partition release the interpreter lock).
+    Returns (idx int64 [len(rows), k], dist float64), -1 / +inf padded."""
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    nr_all = np.sum(X * X, axis=1)
+    idx = np.full((len(rows), k), -1, dtype=np.int64)
+    dist = np.full((len(rows), k), np.inf, dtype=np.float64)
+
+    def one_block(a):
+        r = rows[a:a + block]
+        D = nr_all[r][:, None] + nr_all[None, :] - 2.0 * (X[r] @ X.T)
+        np.maximum(D, 0.0, out=D)
+        D[np.arange(len(r)), r] = 0.0
+        # ineligible entries (the row itself, same-camera items for Eq. (8))
+        D[np.arange(len(r)), r] = np.inf
+        if cross:
+            D[cam[r][:, None] == cam[None, :]] = np.inf
+        m = min(k, n - 1)
+        if m <= 0:
+            return
+        kth = np.partition(D, m - 1, axis=1)[:, m - 1]
+        for t in range(len(r)):
+            cand = np.nonzero(D[t] <= kth[t])[0]  # ascending index order
+            cand = cand[np.isfinite(D[t, cand])]
+            order = np.argsort(D[t, cand], kind="stable")
+            take = cand[order[:k]]
+            idx[a + t, :len(take)] = take
+            dist[a + t, :len(take)] = D[t, take]
+
+    nt = threads or max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(one_block, range(0, len(rows), block)))
     return idx, dist
 
 

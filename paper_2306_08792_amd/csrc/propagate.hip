@@ -30,24 +30,51 @@ __device__ __forceinline__ void axpy_row(Acc<V>& acc, float p, const float* __re
   }
 }
 
-// Sum over an edge segment: indices/values loaded 64 at a time.
-template <int V>
+// Sum over an edge segment: indices/values loaded 64 at a time, then the
+// neighbour rows in groups of G whose loads are all issued before the first
+// of their multiply-adds, so that G rows (G * V 16-byte loads per lane) are
+// in flight per wave: the gather is bound by latency, not bandwidth.  The
+// multiply-adds still run in list order (bitwise reproducible).  `safe` is
+// a valid row index that stands in for padding entries (-1) in the loads;
+// their multiply-adds are skipped.
+template <int V, int G>
 __device__ __forceinline__ void gather_list(Acc<V>& acc, const float* __restrict__ X, int d,
                                             const int32_t* __restrict__ ids,
-                                            const float* __restrict__ vals, int cnt, int lane) {
+                                            const float* __restrict__ vals, int cnt, int lane, int64_t safe) {
   for (int base = 0; base < cnt; base += 64) {
     const int m = min(64, cnt - base);
     int jl = -1;
     float pl = 0.f;
     if (lane < m) { jl = ids[base + lane]; pl = vals[base + lane]; }
     int t = 0;
-    for (; t + 2 <= m; t += 2) {
-      const int j0 = __shfl(jl, t, 64), j1 = __shfl(jl, t + 1, 64);
-      const float p0 = __shfl(pl, t, 64), p1 = __shfl(pl, t + 1, 64);
-      if (j0 >= 0) axpy_row<V>(acc, p0, X + (int64_t)j0 * d, lane);
-      if (j1 >= 0) axpy_row<V>(acc, p1, X + (int64_t)j1 * d, lane);
+    for (; t + G <= m; t += G) {
+      int jj[G];
+      float pp[G];
+      f32x4 buf[G][V];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        jj[g] = __shfl(jl, t + g, 64);
+        pp[g] = __shfl(pl, t + g, 64);
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const f32x4* x4 = (const f32x4*)(X + (jj[g] >= 0 ? (int64_t)jj[g] : safe) * d);
+#pragma unroll
+        for (int q = 0; q < V; ++q) buf[g][q] = x4[q * 64 + lane];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (jj[g] < 0) continue;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          acc.v[q].x = fmaf(pp[g], buf[g][q].x, acc.v[q].x);
+          acc.v[q].y = fmaf(pp[g], buf[g][q].y, acc.v[q].y);
+          acc.v[q].z = fmaf(pp[g], buf[g][q].z, acc.v[q].z);
+          acc.v[q].w = fmaf(pp[g], buf[g][q].w, acc.v[q].w);
+        }
+      }
     }
-    if (t < m) {
+    for (; t < m; ++t) {
       const int j0 = __shfl(jl, t, 64);
       const float p0 = __shfl(pl, t, 64);
       if (j0 >= 0) axpy_row<V>(acc, p0, X + (int64_t)j0 * d, lane);
@@ -72,16 +99,17 @@ __global__ __launch_bounds__(256) void propagate_vec_kernel(PropArgs a) {
       acc.v[q] = t * s;
     }
   }
-  gather_list<V>(acc, a.X, d, a.idx + i * a.k, a.pf + i * a.k, a.k, lane);
+  constexpr int G = V >= 8 ? 2 : 16 / V;  // rows in flight: G * V <= 16 loads per lane
+  gather_list<V, G>(acc, a.X, d, a.idx + i * a.k, a.pf + i * a.k, a.k, lane, i);
   if (a.rev_ptr) {
     const int b = a.rev_ptr[i], e = a.rev_ptr[i + 1];
-    gather_list<V>(acc, a.X, d, a.rev_src + b, a.pr + b, e - b, lane);
+    gather_list<V, G>(acc, a.X, d, a.rev_src + b, a.pr + b, e - b, lane, i);
   }
   if (a.cr_idx) {
-    gather_list<V>(acc, a.X, d, a.cr_idx + i * a.ck, a.cr_pf + i * a.ck, a.ck, lane);
+    gather_list<V, G>(acc, a.X, d, a.cr_idx + i * a.ck, a.cr_pf + i * a.ck, a.ck, lane, i);
     if (a.cr_rev_ptr) {
       const int b = a.cr_rev_ptr[i], e = a.cr_rev_ptr[i + 1];
-      gather_list<V>(acc, a.X, d, a.cr_rev_src + b, a.cr_pr + b, e - b, lane);
+      gather_list<V, G>(acc, a.X, d, a.cr_rev_src + b, a.cr_pr + b, e - b, lane, i);
     }
   }
   float ss = 0.f;

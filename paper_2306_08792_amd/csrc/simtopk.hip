@@ -415,130 +415,135 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     }
     __syncthreads();
 
-    // The lane's first tile column, hidden from the optimiser once per tile
-    // so that the per-element column offsets below are formed at their use
-    // instead of being hoisted out of the tile loop as 128 live registers.
-    int lcol = wc + 4 * half;
-    asm volatile("" : "+v"(lcol));
-    // keys of the whole tile in place (ineligible entries become +inf) and,
-    // per row and list, the mask of entries under the admission threshold:
-    // bit cb * 16 + i of pend[rb2][L]
-    uint64_t pend[2][NL];
-    float t0r[2], t1r[2], rsr[2];
-    int rcr[2], selfr[2];
-    bool rvr[2];
+    // Admission.  Each entry is screened with one multiply-add and one
+    // compare against its row's threshold (and, for the cross list, its
+    // camera), and passing entries are appended at once (an LDS atomic per
+    // entry reserves the slot): after the first tiles only a few entries of
+    // a tile pass, so the cost is about two instructions per entry.  An
+    // entry that finds its buffer full is marked in the lane's lost mask;
+    // then the full buffers are compacted (lower thresholds) and only the
+    // lost entries are screened again, until none is left.
+    {
+      int lc0 = wc + 4 * half;
+      asm volatile("" : "+v"(lc0));
+      const uint32_t cbase = (uint32_t)(ct0 - a.c0);
+      if (a.exclude_self && ct0 < row0 + BM && ct0 + BN > row0) {
+        // a tile holding rows' own columns: their similarities become
+        // -inf, i.e. an infinite key that no threshold admits
 #pragma unroll
-    for (int rb2 = 0; rb2 < 2; ++rb2) {
-      const int lr = wr + 32 * rb2 + l32;
-      // thresholds clamped to the largest finite float: ineligible entries
-      // (padding columns, the row itself) carry an infinite key and are
-      // never admitted, not even under an infinite threshold
-      t0r[rb2] = fminf(row_thr[0][lr], 3.40282347e38f);
-      t1r[rb2] = NL > 1 ? fminf(row_thr[NL - 1][lr], 3.40282347e38f) : -INFINITY;
-      rsr[rb2] = row_sc[lr];
-      rcr[rb2] = row_cam[lr];
-      rvr[rb2] = row0 + lr < a.r1;
-      // column offset (within the tile) of this row's own column, if any
-      const int64_t selfc = row0 + lr - ct0;
-      selfr[rb2] = (a.exclude_self && selfc >= 0 && selfc < BN) ? (int)selfc : -1;
+        for (int rb2 = 0; rb2 < 2; ++rb2) {
+          const int selfc = (int)(row0 + wr + 32 * rb2 + l32 - ct0);
 #pragma unroll
-      for (int L = 0; L < NL; ++L) pend[rb2][L] = 0ull;
-    }
+          for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      // the block's 16 columns of this lane are four runs of four: read
-      // them as vectors once for both row blocks
-      f32x4 n2v[4], scv[4];
-      i32x4 camv[4];
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int c4 = lcol + 32 * cb + 8 * g;
-        n2v[g] = *(const f32x4*)&col_n2[c4];
-        if (NL > 1) camv[g] = *(const i32x4*)&col_cam[c4];
-        if (PREC == GCR_PREC_FP8) scv[g] = *(const f32x4*)&col_sc[c4];
-      }
-#pragma unroll
-      for (int rb2 = 0; rb2 < 2; ++rb2) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int lc = lcol + 32 * cb + 8 * (i >> 2) + (i & 3);
-          float sv = acc[cb][rb2][i];
-          if (PREC == GCR_PREC_FP8) sv = sv * (rsr[rb2] * scv[i >> 2][i & 3]);
-          const bool valid = rvr[rb2] && lc != selfr[rb2];
-          const float key = valid ? n2v[i >> 2][i & 3] - 2.0f * sv : INFINITY;
-          acc[cb][rb2][i] = key;
-          const uint64_t bit = 1ull << (cb * 16 + i);
-          if (key <= t0r[rb2]) pend[rb2][0] |= bit;
-          if (NL > 1 && camv[i >> 2][i & 3] != rcr[rb2] && key <= t1r[rb2]) pend[rb2][NL - 1] |= bit;
+            for (int i = 0; i < 16; ++i)
+              if (lc0 + 32 * cb + 8 * (i >> 2) + (i & 3) == selfc) acc[cb][rb2][i] = -INFINITY;
         }
       }
-    }
-
-    // admission: one pass in the common case; when a buffer fills, the full
-    // buffers are compacted (lower thresholds) and the rest re-screened
-    for (int it = 0;; ++it) {
-      bool left = false;
+      uint64_t lost[2][NL];
 #pragma unroll
       for (int rb2 = 0; rb2 < 2; ++rb2) {
         const int lr = wr + 32 * rb2 + l32;
+        // thresholds clamped to the largest finite float: ineligible entries
+        // (padding columns, the row itself) carry an infinite key and are
+        // never admitted, not even under an infinite threshold; rows past
+        // the range have -inf thresholds
+        const float t0 = fminf(row_thr[0][lr], 3.40282347e38f);
+        const float t1 = NL > 1 ? fminf(row_thr[NL - 1][lr], 3.40282347e38f) : -INFINITY;
+        const float rs = row_sc[lr];
+        const int rc = row_cam[lr];
+        uint64_t* buf0 = a.cand + (((rrel0 + lr) * NL) * (int64_t)a.S + cs) * a.C;
+        uint64_t* buf1 = a.cand + (((rrel0 + lr) * NL + NL - 1) * (int64_t)a.S + cs) * a.C;
 #pragma unroll
-        for (int L = 0; L < NL; ++L) {
-          const uint64_t m = pend[rb2][L];
-          const int c = __popcll(m);
-          if (c == 0) continue;
-          // one atomic per (row, list) reserves all of this lane's slots;
-          // each pending entry goes to base + its rank among them
-          const int base = atomicAdd(&row_cnt[L][lr], c);
-          const int room = max(0, min(c, a.C - base));
-          uint64_t* rowbuf = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C + base;
-          uint64_t done = 0ull;
+        for (int L = 0; L < NL; ++L) lost[rb2][L] = 0ull;
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) {
+        for (int cb = 0; cb < 4; ++cb) {
+          f32x4 n2v[4], scv[4];
+          i32x4 camv[4];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-              const int bi = cb * 16 + i;
-              const uint64_t bit = 1ull << bi;
-              if (m & bit) {
-                const int rank = __popcll(m & (bit - 1ull));
-                if (rank < room) {
-                  const int lc = lcol + 32 * cb + 8 * (i >> 2) + (i & 3);
-                  rowbuf[rank] = pack_cand(acc[cb][rb2][i], (uint32_t)(ct0 - a.c0) + (uint32_t)lc);
-                  done |= bit;
+          for (int g = 0; g < 4; ++g) {
+            const int c4 = lc0 + 32 * cb + 8 * g;
+            n2v[g] = *(const f32x4*)&col_n2[c4];
+            if (NL > 1) camv[g] = *(const i32x4*)&col_cam[c4];
+            if (PREC == GCR_PREC_FP8) scv[g] = *(const f32x4*)&col_sc[c4];
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            float sv = acc[cb][rb2][i];
+            if (PREC == GCR_PREC_FP8) sv = sv * (rs * scv[i >> 2][i & 3]);
+            // n2 - 2 s with one rounding (2 s is exact)
+            const float key = fmaf(-2.0f, sv, n2v[i >> 2][i & 3]);
+            const int lc = lc0 + 32 * cb + 8 * (i >> 2) + (i & 3);
+            const uint64_t bit = 1ull << (cb * 16 + i);
+            if (key <= t0) {
+              const int pos = atomicAdd(&row_cnt[0][lr], 1);
+              if (pos < a.C) buf0[pos] = pack_cand(key, cbase + (uint32_t)lc);
+              else lost[rb2][0] |= bit;
+            }
+            if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1) {
+              const int pos = atomicAdd(&row_cnt[NL - 1][lr], 1);
+              if (pos < a.C) buf1[pos] = pack_cand(key, cbase + (uint32_t)lc);
+              else lost[rb2][NL - 1] |= bit;
+            }
+          }
+        }
+      }
+      for (int it = 0;; ++it) {
+        bool left = false;
+#pragma unroll
+        for (int rb2 = 0; rb2 < 2; ++rb2)
+#pragma unroll
+          for (int L = 0; L < NL; ++L) left |= lost[rb2][L] != 0ull;
+        if (__any(left) && lane == 0) any_flag[it & 1] = 1;
+        __syncthreads();
+        const int more = any_flag[it & 1];
+        if (tid == 0) any_flag[(it + 1) & 1] = 0;
+        if (!more) break;
+        // compact the full buffers (a count past C counts lost entries too)
+        for (int q = wave; q < NL * BM; q += NT / 64) {
+          const int L = q / BM, lr = q - L * BM;
+          if (row_cnt[L][lr] >= a.C) {
+            uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
+            compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
+            if (a.thr_shared && lane == 0)
+              atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
+          }
+        }
+        __syncthreads();
+        // the lost entries against the lowered thresholds
+#pragma unroll
+        for (int rb2 = 0; rb2 < 2; ++rb2) {
+          const int lr = wr + 32 * rb2 + l32;
+          const float rs = row_sc[lr];
+#pragma unroll
+          for (int L = 0; L < NL; ++L) {
+            uint64_t m = lost[rb2][L];
+            if (m == 0ull) continue;
+            const float t = row_thr[L][lr];
+            uint64_t* buf = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+              for (int i = 0; i < 16; ++i) {
+                const uint64_t bit = 1ull << (cb * 16 + i);
+                if (m & bit) {
+                  const int lc = lc0 + 32 * cb + 8 * (i >> 2) + (i & 3);
+                  float sv = acc[cb][rb2][i];
+                  if (PREC == GCR_PREC_FP8) sv = sv * (rs * col_sc[lc]);
+                  const float key = fmaf(-2.0f, sv, col_n2[lc]);
+                  if (!(key <= t)) {
+                    m &= ~bit;
+                  } else {
+                    const int pos = atomicAdd(&row_cnt[L][lr], 1);
+                    if (pos < a.C) {
+                      buf[pos] = pack_cand(key, cbase + (uint32_t)lc);
+                      m &= ~bit;
+                    }
+                  }
                 }
               }
             }
-          }
-          pend[rb2][L] = m & ~done;
-          if (pend[rb2][L]) left = true;
-        }
-      }
-      if (__any(left) && lane == 0) any_flag[it & 1] = 1;
-      __syncthreads();
-      const int more = any_flag[it & 1];
-      if (tid == 0) any_flag[(it + 1) & 1] = 0;
-      if (!more) break;
-      for (int q = wave; q < NL * BM; q += NT / 64) {
-        const int L = q / BM, lr = q - L * BM;
-        if (row_cnt[L][lr] >= a.C) {
-          uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
-          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
-          if (a.thr_shared && lane == 0)
-            atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int rb2 = 0; rb2 < 2; ++rb2) {
-        const int lr = wr + 32 * rb2 + l32;
-        const float t0 = row_thr[0][lr];
-        const float t1 = NL > 1 ? row_thr[NL - 1][lr] : -INFINITY;
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const uint64_t bit = 1ull << (cb * 16 + i);
-            if (!(acc[cb][rb2][i] <= t0)) pend[rb2][0] &= ~bit;
-            if (NL > 1 && !(acc[cb][rb2][i] <= t1)) pend[rb2][NL - 1] &= ~bit;
+            lost[rb2][L] = m;
           }
         }
       }

@@ -113,3 +113,104 @@ def oracle_round_from_lists(X, p, idx, cr_idx=None, cam=None, X_graph=None):
     Y, Dg, Dc = O.sparse_round_from_lists(X, p, np.asarray(idx, np.int64), dist, cam,
                                           None if cr_idx is None else np.asarray(cr_idx, np.int64), cdist)
     return Y, Dg, Dc
+
+
+def oracle_chain(X0, p, cam=None, rounds=None, tie=TIE):
+    """The oracle's rounds at sizes where N x N does not fit: lists by the
+    blocked exhaustive FP64 kNN (k + 1 per row, to see the gap at the cut),
+    then one sparse FP64 round with exactly those nonzeros, the graph
+    rebuilt from each round's features.  Returns per round t = 1..T the
+    dict(idx, dist, cr_idx, cr_dist, X, ties) where `ties` are the rows whose
+    k-th and (k+1)-th oracle distances are within `tie` (either list): rows
+    whose neighbour sets are not unique within the parity tie band."""
+    X = O.row_normalize(X0) if p.normalize_input else np.asarray(X0, np.float64)
+    k = p.k
+    kc = p.k if p.cross_k is None else p.cross_k
+    use_cr = cam is not None and p.alpha < 1.0
+    out = []
+    for _ in range(p.rounds if rounds is None else rounds):
+        gi, gd = O.knn_blocked(X, k + 1)
+        ties = np.abs(gd[:, k] - gd[:, k - 1]) <= tie
+        idx, dist = gi[:, :k], gd[:, :k]
+        cidx = cdist = None
+        if use_cr:
+            ci, cd = O.knn_blocked(X, kc + 1, cam=cam, cross=True)
+            ties |= np.abs(cd[:, kc] - cd[:, kc - 1]) <= tie
+            cidx, cdist = ci[:, :kc], cd[:, :kc]
+        Xn, _, _ = O.sparse_round_from_lists(X, p, idx, dist, cam, cidx, cdist)
+        out.append(dict(idx=idx, dist=dist, cr_idx=cidx, cr_dist=cdist, X=Xn, ties=np.nonzero(ties)[0]))
+        X = Xn
+    return out
+
+
+def expand_hops(rows, lists, hops):
+    """rows plus every node within `hops` edges of them in the symmetric
+    graph of the given forward lists (each an int array [n, k], -1 padded)."""
+    n = lists[0].shape[0]
+    adj_r, adj_c = [], []
+    for ix in lists:
+        ok = ix >= 0
+        r = np.broadcast_to(np.arange(n)[:, None], ix.shape)[ok]
+        adj_r += [r, ix[ok]]
+        adj_c += [ix[ok], r]
+    import scipy.sparse as sp
+    A = sp.coo_matrix((np.ones(sum(len(a) for a in adj_r)), (np.concatenate(adj_r), np.concatenate(adj_c))),
+                      shape=(n, n)).tocsr()
+    mark = np.zeros(n, dtype=bool)
+    mark[np.asarray(rows, dtype=np.int64)] = True
+    for _ in range(hops):
+        mark |= (A @ mark.astype(np.float64)) > 0
+    return np.nonzero(mark)[0]
+
+
+def closed_neighbourhood_round(X, ids, k, gamma, rows):
+    """One oracle round at `rows` of a graph too large to build whole, made
+    exact by closing the neighbourhood.  Every row's k-th distance is at most
+    U = the largest, over all rows, k-th distance to the row's own identity
+    group (any k other items bound it), so m lists j only if
+    ||x_m - x_j||^2 <= U.  The lists of `rows`, of their neighbours and of
+    every row within U of those are computed exactly (knn_blocked); rows
+    outside that closure get empty lists, which changes no degree or value
+    the round at `rows` reads.  Returns (X1[rows], exact lists of rows)."""
+    n = X.shape[0]
+    nr = np.sum(X * X, axis=1)
+    U = 0.0
+    for g in np.unique(ids):
+        M = np.nonzero(ids == g)[0]
+        if len(M) <= k:
+            return None  # no bound from this group
+        D = np.maximum(nr[M][:, None] + nr[M][None, :] - 2.0 * X[M] @ X[M].T, 0.0)
+        np.fill_diagonal(D, np.inf)
+        U = max(U, float(np.partition(D, k - 1, axis=1)[:, k - 1].max()))
+    U += 1e-9
+
+    def within_U(S):
+        out = set()
+        for a in range(0, len(S), 512):
+            b = S[a:a + 512]
+            D = nr[b][:, None] + nr[None, :] - 2.0 * (X[b] @ X.T)
+            out.update(np.nonzero(D <= U)[1].tolist())
+        return out
+
+    lists = {}
+
+    def ensure(S):
+        S = np.array(sorted(set(S) - set(lists)), dtype=np.int64)
+        if len(S):
+            li, ld = O.knn_blocked(X, k, rows=S)
+            for t, r in enumerate(S):
+                lists[int(r)] = (li[t], ld[t])
+
+    rows = np.asarray(rows, dtype=np.int64)
+    ensure(within_U(rows) | set(rows.tolist()))
+    S1 = set(rows.tolist())
+    for r in rows:
+        S1.update(int(j) for j in lists[int(r)][0] if j >= 0)
+    S1.update(m for m in list(lists) if set(lists[m][0].tolist()) & set(rows.tolist()))
+    ensure(within_U(np.array(sorted(S1))) | S1)
+    idx = np.full((n, k), -1, dtype=np.int64)
+    dist = np.full((n, k), np.inf)
+    for m, (li, ld) in lists.items():
+        idx[m], dist[m] = li, ld
+    Y, _, _ = O.sparse_round_from_lists(X, O.Params(k=k, gamma=gamma, rounds=1), idx, dist, rows=rows)
+    return Y, idx, sorted(lists)

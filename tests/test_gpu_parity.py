@@ -119,11 +119,13 @@ def test_knn_duplicates_force_fallback(ctx):
     assert st["knn_exhaustive_rows"] > 0
 
 
-def shell_workload(hubs=12, shell=1500, d=64, seed=5):
+def shell_workload(hubs=12, shell=1500, d=64, seed=5, shuffle=True):
     """Hubs with a shell of points whose squared distances to the hub are
     spread over [0.5, 0.51]: a hub's k-th neighbour sits inside a band of
     1,500 items narrower than the BF16 screening margin, more than one
-    candidate buffer (512) keeps.  Returns (X, hub row indices)."""
+    candidate buffer (256-512 entries) keeps.  Without shuffling, each hub's
+    shell is a contiguous index range, so it lands in one or two column
+    splits whatever the number of splits.  Returns (X, hub row indices)."""
     rng = np.random.default_rng(seed)
     H = datagen.random_unit(hubs, d, seed + 1).astype(np.float64)
     pts = []
@@ -134,7 +136,7 @@ def shell_workload(hubs=12, shell=1500, d=64, seed=5):
         rho = np.sqrt(rng.uniform(0.5, 0.51, shell))
         pts.append(np.vstack([h[None], h[None] + rho[:, None] * U]))
     X = np.vstack(pts).astype(np.float32)
-    perm = rng.permutation(len(X))
+    perm = rng.permutation(len(X)) if shuffle else np.arange(len(X))
     inv = np.empty_like(perm)
     inv[perm] = np.arange(len(X))
     return X[perm], np.sort(inv[np.arange(hubs) * (shell + 1)])
@@ -146,7 +148,7 @@ def test_knn_band_resweep(ctx, prec):
     in float32 against every column; their lists stay exact, and a band
     within the re-sweep capacity (2,048 items) needs no exhaustive pass."""
     print(f"knn band re-sweep prec={prec}", flush=True)
-    X, hub_rows = shell_workload()
+    X, hub_rows = shell_workload(shuffle=False)
     n = len(X)
     ctx.reset_stats()
     idx, dist = ctx.knn(dev(X), Params(k=20, precision=prec))

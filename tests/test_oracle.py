@@ -747,3 +747,48 @@ def test_mean_average_precision_hand_computed():
     # q1 (7): order g3, g5, g4, g2, g0, g1 -> hit at 1: 1.0
     assert mean_average_precision(dq2, np.array([5, 7]), gids2) == pytest.approx(0.75, abs=1e-15)
     assert mean_average_precision(dq[2:], qids[2:], gids) == 0.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_knn_blocked_equals_full_sort(seed):
+    """The blocked large-N kNN against brute force (math.fsum distances,
+    Python sort by (distance, index)), with exact ties planted at the cut
+    (duplicated rows), blocks smaller than the input, and the cross-camera
+    lists."""
+    rng = np.random.default_rng(seed)
+    n, d, k = 97, 6, 7
+    X = rng.standard_normal((n, d))
+    X[10] = X[3]
+    X[11] = X[3]
+    X[50] = X[40]
+    cam = rng.integers(0, 3, size=n)
+    gi, gd = O.knn_blocked(X, k, block=16, threads=3)
+    assert gi.tolist() == _brute_knn(X, k)
+    ci, _ = O.knn_blocked(X, k, cam=cam, cross=True, block=16, threads=3)
+    assert ci.tolist() == _brute_knn(X, k, cam=cam, cross=True)
+    rows = np.array([3, 10, 96, 0])
+    ri, rd = O.knn_blocked(X, k, rows=rows, block=2)
+    assert ri.tolist() == [_brute_knn(X, k)[r] for r in rows]
+    for t, r in enumerate(rows):
+        for s_, j in enumerate(ri[t]):
+            assert abs(rd[t, s_] - math.fsum((a - b) ** 2 for a, b in zip(X[r], X[j]))) < 1e-12
+    # fewer eligible items than k: padding
+    small = X[:5]
+    pi, pd = O.knn_blocked(small, k)
+    assert np.all(pi[:, 4:] == -1) and np.all(np.isinf(pd[:, 4:]))
+
+
+def test_closed_neighbourhood_round_equals_whole_graph():
+    """The closed-neighbourhood evaluation used at sizes where the whole
+    graph does not fit gives the whole-graph round at the chosen rows."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from parity import closed_neighbourhood_round
+
+    X, ids = datagen.clustered(40, 30, 24, 0.6, seed=9)
+    X = O.row_normalize(X)
+    whole = O.gcr(X, O.Params(k=8, gamma=0.3, rounds=1, normalize_input=False))["X"][1]
+    rows = np.nonzero(np.isin(ids, [3, 17, 29]))[0]
+    Y, _, closure = closed_neighbourhood_round(X, ids, 8, 0.3, rows)
+    assert len(closure) < len(X)
+    np.testing.assert_allclose(Y, whole[rows], rtol=0, atol=1e-13)
