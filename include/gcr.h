@@ -246,6 +246,22 @@ gcr_status gcr_build_graph(gcr_ctx* ctx, const float* X, int64_t n, int32_t d,
 gcr_status gcr_propagate(gcr_ctx* ctx, const gcr_graph* g, const float* X_in,
                          float* X_out, int64_t n, int32_t d, void* stream);
 
+/* One propagation round exactly as gcr_propagate (same kernels, bitwise the
+ * same output), for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * It uses neither the context workspace nor any allocation: its scratch (the
+ * locality order of the round, 24 bytes per node) lives in a fixed 32 MiB
+ * device array of the library, one per GPU, obtained once per device in
+ * gcr_create and held until the process ends.  n is limited to
+ * gcr_propagate_noalloc_max_nodes() (about 1.39M nodes); larger n returns
+ * UNSUPPORTED.  All calls on one GPU share that array: calls that overlap in
+ * time on one GPU (other streams, other contexts, other threads) race and
+ * must be ordered by the caller.  Arguments and errors as gcr_propagate. */
+gcr_status gcr_propagate_noalloc(gcr_ctx* ctx, const gcr_graph* g,
+                                 const float* X_in, float* X_out, int64_t n,
+                                 int32_t d, void* stream);
+size_t gcr_propagate_noalloc_max_nodes(void);
+
 /* Distances between the first nq rows (queries) and the next ng rows
  * (gallery) of X (float32 [nq+ng, d]):
  *   dist_out: float32 [nq, ng] dense squared distances, or NULL (inner

@@ -20,6 +20,7 @@ GCR_ERR_TIMEOUT = -5
 EXPORTS = [
     "gcr_params_default", "gcr_create", "gcr_destroy", "gcr_last_error", "gcr_get_stats",
     "gcr_reserve", "gcr_workspace_bytes", "gcr_workspace_size", "gcr_profile_workspace_size",
+    "gcr_propagate_noalloc", "gcr_propagate_noalloc_max_nodes",
     "gcr_reset_stats", "gcr_normalize_rows", "gcr_knn", "gcr_graph_bytes", "gcr_graph_bind",
     "gcr_build_graph", "gcr_propagate", "gcr_final_distances", "gcr_rerank",
     "gcr_profile_vectors", "gcr_set_timing", "gcr_get_timing",
@@ -122,6 +123,9 @@ def load(path: str = LIB_PATH):
     L.gcr_graph_bind.argtypes = [C.POINTER(GcrGraph), vp, i64, i32, i32, i32]
     L.gcr_build_graph.argtypes = [vp, vp, i64, i32, vp, pP, C.POINTER(GcrGraph), vp]
     L.gcr_propagate.argtypes = [vp, C.POINTER(GcrGraph), vp, vp, i64, i32, vp]
+    L.gcr_propagate_noalloc.argtypes = [vp, C.POINTER(GcrGraph), vp, vp, i64, i32, vp]
+    L.gcr_propagate_noalloc_max_nodes.argtypes = []
+    L.gcr_propagate_noalloc_max_nodes.restype = C.c_size_t
     L.gcr_final_distances.argtypes = [vp, vp, i64, i64, i32, pP, vp, vp, vp, vp]
     L.gcr_rerank.argtypes = [vp, vp, i64, i64, i32, vp, pP, vp, vp, vp, vp, C.POINTER(GcrGraph), vp]
     L.gcr_set_timing.argtypes = [vp, i32]

@@ -8,10 +8,22 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "host.h"
+
+// Scratch of gcr_propagate_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  In host code
+// its name is only a stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device in gcr_create with that device
+// current, and is kept in noalloc_scratch[device].
+#define GCR_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define GCR_NOALLOC_MAX_DEVICES 64
+static __device__ __align__(256) uint8_t scratch[GCR_NOALLOC_SCRATCH_BYTES];
+static std::mutex noalloc_mu;
+static void* noalloc_scratch[GCR_NOALLOC_MAX_DEVICES] = {};
 
 
 namespace gcr {
@@ -501,9 +513,25 @@ gcr_status gcr_create(gcr_ctx** out, int device, size_t workspace_bytes) {
     (void)hipGetLastError();
     return GCR_ERR_INVALID;
   }
+  if (hipSetDevice(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return GCR_ERR_HIP;
+  }
+  if (device < GCR_NOALLOC_MAX_DEVICES) {
+    // the no-allocation entry point's scratch on this device (device current)
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (!noalloc_scratch[device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return GCR_ERR_HIP;
+      }
+      noalloc_scratch[device] = ptr;
+    }
+  }
   gcr_ctx* c = new gcr_ctx();
   c->device = device;
-  if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
+  if (hipMalloc(&c->stats, 4 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->stats, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipGetLastError();
     if (c->stats) (void)hipFree(c->stats);
@@ -684,6 +712,49 @@ gcr_status gcr_propagate(gcr_ctx* c, const gcr_graph* g, const float* X_in, floa
   enqueue_propagate(c, g, X_in, X_out, n, d, (hipStream_t)stream, gt.order);
   HIP_TRY(c, hipGetLastError());
   return GCR_OK;
+}
+
+gcr_status gcr_propagate_noalloc(gcr_ctx* c, const gcr_graph* g, const float* X_in, float* X_out, int64_t n,
+                                 int32_t d, void* stream) {
+  if (!c) return GCR_ERR_INVALID;
+  if (!g || !X_in || !X_out || g->n != n || n < 1 || d <= 0)
+    return fail(c, GCR_ERR_INVALID, "bad propagate arguments");
+  if (X_in == X_out) return fail(c, GCR_ERR_INVALID, "in-place propagation is not allowed");
+  if (d > 2048) return fail(c, GCR_ERR_UNSUPPORTED, "d above 2048 is not supported by propagation");
+  GraphTmp gt;
+  Arena dry;
+  plan_graph_tmp(dry, gt, n);
+  if (dry.off > GCR_NOALLOC_SCRATCH_BYTES)
+    return fail(c, GCR_ERR_UNSUPPORTED,
+                "n = %lld needs %zu bytes of scratch; the no-allocation entry point holds %u (about %u nodes)",
+                (long long)n, dry.off, GCR_NOALLOC_SCRATCH_BYTES, GCR_NOALLOC_SCRATCH_BYTES / 24u);
+  void* base = c->device < GCR_NOALLOC_MAX_DEVICES ? noalloc_scratch[c->device] : nullptr;
+  if (!base) return fail(c, GCR_ERR_UNSUPPORTED, "no scratch for device %d", c->device);
+  HIP_TRY(c, hipSetDevice(c->device));
+  Arena ar{(char*)base, 0};
+  plan_graph_tmp(ar, gt, n);
+  // the locality order clears its counters with a fill kernel every call
+  if (g->k > 0) {
+    TimedScope ts(c, 2, (hipStream_t)stream);
+    launch_locality_order(n, g->idx, g->k, gt.label, gt.cnt, gt.blk, gt.order, (hipStream_t)stream);
+  }
+  enqueue_propagate(c, g, X_in, X_out, n, d, (hipStream_t)stream, gt.order);
+  HIP_TRY(c, hipGetLastError());
+  return GCR_OK;
+}
+
+size_t gcr_propagate_noalloc_max_nodes(void) {
+  // largest n whose locality-order arrays fit the scratch
+  int64_t lo = 1, hi = (int64_t)GCR_NOALLOC_SCRATCH_BYTES;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    GraphTmp gt;
+    Arena dry;
+    plan_graph_tmp(dry, gt, mid);
+    if (dry.off <= GCR_NOALLOC_SCRATCH_BYTES) lo = mid;
+    else hi = mid - 1;
+  }
+  return (size_t)lo;
 }
 
 struct FinalPlan {

@@ -256,6 +256,15 @@ class Context:
                                         _stream()), "gcr_propagate")
         return Y
 
+    def propagate_noalloc(self, g: Graph, X: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """gcr_propagate_noalloc: one round with the library's fixed per-GPU
+        scratch (no workspace, no allocation); `out` must be preallocated."""
+        _check(X, torch.float32, "X", self.device)
+        _check(out, torch.float32, "out", self.device)
+        self._ok(self.lib.gcr_propagate_noalloc(self.h, C.byref(g.g), _ptr(X), _ptr(out), X.shape[0], X.shape[1],
+                                                _stream()), "gcr_propagate_noalloc")
+        return out
+
     def final_distances(self, X: torch.Tensor, nq: int, p: Params, dense: bool = True, topk: bool = False):
         _check(X, torch.float32, "X", self.device)
         n, d = X.shape
