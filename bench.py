@@ -55,9 +55,9 @@ def parse():
                     help="large_retrieval: 20,000 + 200,000 x 512 whole re-ranking steps (default); "
                          "cross_camera / plain / video: the re-ID workloads; local: GCR_Local; "
                          "serving: resident 500,000 x 512 gallery and Poisson request traces")
-    ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
-    ap.add_argument("--load", type=float, default=0.7,
-                    help="serving: offered load of the Poisson phase as a fraction of the saturated throughput")
+    ap.add_argument("--requests", type=int, default=20000, help="serving: measured requests (after 1,000 warm-ups)")
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.7, 0.85, 1.0],
+                    help="serving: offered loads of the Poisson phases, as fractions of the saturated throughput")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (reference kernel for the HBM "
                          "byte counters) and exit")
@@ -513,92 +513,21 @@ def cpu_baseline_large(w, P, K: int, sample_rows: int):
     }
 
 
-def serving_bench(args):
-    """Resident 500,000 x 512 BF16 gallery (10,000 centres), k = 20, L = 2,
-    K = 100; requests of 1..512 queries (log-uniform).  Phase 1 queues the
-    whole trace at once (saturated throughput); phase 2 replays it with
-    Poisson arrivals at `load` x that throughput and records each request's
-    latency from arrival to result."""
+def _replay(srv, trace, rate_rps, t_scale=None):
+    """Submit `trace` with Poisson arrivals at rate_rps requests/s (None: all
+    at once) and return (latencies in ms from scheduled arrival to result on
+    the host, wall seconds).  A waiter thread collects results in order."""
     import threading
 
-    import torch
-
-    from paper_2306_08792_amd import datagen
-    from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params, Server
-
-    print("generating the serving gallery", file=sys.stderr, flush=True)
-    bits, vals, centres = datagen.serving_gallery()
-    ng, d = vals.shape
-    trace = datagen.serving_trace(centres, args.requests, 1000.0)
-    nq_total = sum(q.shape[0] for _, q, _ in trace)
-    ctx = Context(0)
-    g = torch.from_numpy(bits.view(np.int16)).cuda()
-    del vals
-    prec = {"fp32": FP32, "bf16": BF16, "fp8": FP8}[args.precision]
-    p = Params(k=20, rounds=2, gamma=0.2, topk_out=100, precision=prec, rebuild_each_round=False)
-    print(f"building the resident gallery state ({args.precision} screening)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    n_mut = 1000
-    srv = Server(ctx, g, p, slots=4, max_batch=512, max_recomputed=65536, gallery_capacity=ng + n_mut)
-    t_build = time.perf_counter() - t0
-
-    agreement = None
-    fp32 = None
-    if not args.no_agreement:
-        print("checking top-100 agreement against FP32 screening", file=sys.stderr, flush=True)
-        p32 = Params(**{**p.__dict__, "precision": FP32})
-        s32 = Server(ctx, g, p32, slots=4, max_batch=512, max_recomputed=65536)
-        same = 0
-        tot = 0
-        for _, q, _ in trace[:8]:
-            a = srv.query(q)
-            b = s32.query(q)
-            same += int(np.sum(np.all(a[0] == b[0], axis=1)))
-            tot += q.shape[0]
-        agreement = {"final_top100": same / max(1, tot), "queries_checked": tot}
-        # saturated throughput of the same server with float32 screening
-        sub = trace[:min(100, len(trace))]
-        nq_sub = sum(q.shape[0] for _, q, _ in sub)
-        print("timing float32 screening (saturated)", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        tk = [s32.submit(q) for _, q, _ in sub]
-        for t in tk:
-            s32.wait(t)
-        t32 = time.perf_counter() - t0
-        s32.close()
-        fp32 = {"queries_per_s": round(nq_sub / t32, 2), "requests": len(sub)}
-
-    for _, q, _ in trace[:4]:  # warm-up
-        srv.query(q)
-    print("phase 1: saturated", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    tickets = [srv.submit(q) for _, q, _ in trace]
-    for t in tickets:
-        srv.wait(t)
-    t_sat = time.perf_counter() - t0
-    qps_sat = nq_total / t_sat
-    if fp32 is not None:
-        # the BF16 server on the same request subset as the float32 timing
-        sub = trace[:fp32["requests"]]
-        t0 = time.perf_counter()
-        tk = [srv.submit(q) for _, q, _ in sub]
-        for t in tk:
-            srv.wait(t)
-        qps_sub = sum(q.shape[0] for _, q, _ in sub) / (time.perf_counter() - t0)
-        fp32["bf16_queries_per_s_same_requests"] = round(qps_sub, 2)
-        fp32["bf16_speedup"] = round(qps_sub / fp32["queries_per_s"], 3)
-
-    rate = args.load * qps_sat / (nq_total / len(trace))  # requests per second
+    n = len(trace)
     rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(trace)))
-    lat = [0.0] * len(trace)
-    done_at = [0.0] * len(trace)
-    tick = [None] * len(trace)
+    arrivals = np.zeros(n) if rate_rps is None else np.cumsum(rng.exponential(1.0 / rate_rps, size=n))
+    done_at = [0.0] * n
+    tick = [None] * n
     ready = threading.Semaphore(0)
-    print(f"phase 2: Poisson arrivals at {args.load:.0%} of saturation", file=sys.stderr, flush=True)
 
     def waiter():
-        for i in range(len(trace)):
+        for i in range(n):
             ready.acquire()
             srv.wait(tick[i])
             done_at[i] = time.perf_counter()
@@ -613,13 +542,84 @@ def serving_bench(args):
         tick[i] = srv.submit(q)
         ready.release()
     th.join()
-    for i in range(len(trace)):
-        lat[i] = (done_at[i] - (start + arrivals[i])) * 1e3
-    span = max(done_at) - start
+    lat = np.array([(done_at[i] - (start + arrivals[i])) * 1e3 for i in range(n)])
+    return lat, max(done_at) - start
 
-    # gallery mutations: 1,000 new items (near random centres, like the
-    # queries), then 1,000 random items removed; each call returns once the
-    # lists, graph, gallery rounds and operands are exact again
+
+def serving_bench(args):
+    """Resident 500,000 x 512 BF16 gallery (10,000 centres), k = 20, L = 2,
+    K = 100; requests of 1..512 queries (log-uniform, mean about 82).
+    Protocol: 1,000 warm-up requests, then 20,000 requests queued at once
+    (saturated throughput, the line's value), then the same 20,000 replayed
+    with Poisson arrivals at a sweep of offered loads (p50/p99 latency from
+    scheduled arrival to result on the host); the SLO point is the highest
+    load whose p99 stays at or below 100 ms.  The float32-screening server
+    runs the first 2,000 requests for the same-GPU comparison."""
+    import torch
+
+    from paper_2306_08792_amd import datagen
+    from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params, Server
+
+    n_warm, n_meas = 1000, args.requests
+    print("generating the serving gallery", file=sys.stderr, flush=True)
+    bits, vals, centres = datagen.serving_gallery()
+    ng, d = vals.shape
+    print(f"generating {n_warm} + {n_meas} requests", file=sys.stderr, flush=True)
+    trace = datagen.serving_trace(centres, n_warm + n_meas, 1000.0)
+    warm, meas = trace[:n_warm], trace[n_warm:]
+    nq_meas = sum(q.shape[0] for _, q, _ in meas)
+    mean_b = nq_meas / len(meas)
+    ctx = Context(0)
+    g = torch.from_numpy(bits.view(np.int16)).cuda()
+    del vals
+    prec = {"fp32": FP32, "bf16": BF16, "fp8": FP8}[args.precision]
+    p = Params(k=20, rounds=2, gamma=0.2, topk_out=100, precision=prec, rebuild_each_round=False)
+    cfg = dict(lanes=2, max_batch=512, max_requests=8, max_recomputed=65536)
+    print(f"building the resident gallery state ({args.precision} screening)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    n_mut = 1000
+    srv = Server(ctx, g, p, gallery_capacity=ng + n_mut, **cfg)
+    t_build = time.perf_counter() - t0
+
+    print("warm-up", file=sys.stderr, flush=True)
+    _replay(srv, warm, None)
+    print("saturated phase", file=sys.stderr, flush=True)
+    lat_sat, t_sat = _replay(srv, meas, None)
+    qps_sat = nq_meas / t_sat
+    sweep = []
+    for load in args.loads:
+        rate = load * qps_sat / mean_b
+        print(f"Poisson phase at {load:.0%} of saturation ({rate:.0f} requests/s)", file=sys.stderr, flush=True)
+        lat, span = _replay(srv, meas, rate)
+        sweep.append({"offered_load": load, "offered_queries_per_s": round(rate * mean_b, 1),
+                      "achieved_queries_per_s": round(nq_meas / span, 1),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3)})
+    ok = [s_ for s_ in sweep if s_["p99_ms"] <= 100.0]
+    slo = max(ok, key=lambda s_: s_["achieved_queries_per_s"]) if ok else None
+    st_main = srv.stats()
+
+    fp32 = None
+    agreement = None
+    if not args.no_agreement and args.precision != "fp32":
+        print("float32-screening server on the same requests", file=sys.stderr, flush=True)
+        sub = meas[:2000]
+        nq_sub = sum(q.shape[0] for _, q, _ in sub)
+        s32 = Server(ctx, g, Params(**{**p.__dict__, "precision": FP32}), **cfg)
+        _replay(s32, warm[:100], None)
+        _, t32 = _replay(s32, sub, None)
+        _, tlo = _replay(srv, sub, None)
+        fp32 = {"requests": len(sub), "queries": nq_sub, "queries_per_s": round(nq_sub / t32, 1),
+                "this_mode_queries_per_s": round(nq_sub / tlo, 1), "speedup": round(t32 / tlo, 3)}
+        same = tot = 0
+        for _, q, _ in meas[:50]:
+            a = srv.query(q)
+            b = s32.query(q)
+            same += int(np.sum(np.all(a[0] == b[0], axis=1)))
+            tot += q.shape[0]
+        agreement = {"final_top100_rows_equal": same / max(1, tot), "queries_checked": tot}
+        s32.close()
+
     print("gallery mutations", file=sys.stderr, flush=True)
     mrng = np.random.default_rng(11)
     rows = datagen._unit_rows_f32(centres[mrng.integers(0, len(centres), n_mut)]
@@ -631,39 +631,39 @@ def serving_bench(args):
     t0 = time.perf_counter()
     srv.remove(gone)
     t_rem = time.perf_counter() - t0
-    srv.query(trace[0][1])
-    st = srv.stats()
+    srv.query(meas[0][1])
     srv.close()
     ctx.close()
-    lat = np.array(lat)
     res = {
         "metric": METRIC,
         "value": round(qps_sat, 2),
         "unit": "queries/s",
         "n_gpus": 1,
-        "steps": len(trace),
-        "warmup": 4,
-        "ms_per_step": round(t_sat * 1e3 / len(trace), 3),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "steps": len(meas),
+        "warmup": n_warm,
+        "ms_per_step": round(t_sat * 1e3 / len(meas), 4),
+        "p50_ms": slo["p50_ms"] if slo else None,
+        "p99_ms": slo["p99_ms"] if slo else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"serving_gallery_{ng}x{d}_bf16", "gallery": ng, "d": d, "centres": 10000,
-                   "k": 20, "rounds": 2, "top_k": 100, "batch": "log-uniform 1..512",
-                   "requests": len(trace), "queries": nq_total, "slots": 4, "parallelism": "single GPU"},
+                   "k": 20, "rounds": 2, "top_k": 100, "batch": "log-uniform 1..512", "requests": len(meas),
+                   "warmup_requests": n_warm, "queries": nq_meas, **cfg, "parallelism": "single GPU"},
+        "saturated": {"seconds": round(t_sat, 3), "queries_per_s": round(qps_sat, 1),
+                      "p50_ms_queued": round(float(np.percentile(lat_sat, 50)), 3)},
+        "load_sweep": sweep,
+        "slo_p99_100ms": ({"queries_per_s": slo["achieved_queries_per_s"], "offered_load": slo["offered_load"],
+                           "p50_ms": slo["p50_ms"], "p99_ms": slo["p99_ms"]} if slo else None),
         "top_k_agreement": agreement,
         "fp32_screening_same_gpu": fp32,
-        "poisson_phase": {"offered_load": args.load, "requests_per_s": round(rate, 2),
-                          "queries_per_s": round(nq_total / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                          "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3)},
-        "saturated_phase": {"seconds": round(t_sat, 3), "queries_per_s": round(qps_sat, 2)},
         "gallery_build_s": round(t_build, 3),
         "mutation": {"insert_rows": n_mut, "insert_ms": round(t_ins * 1e3, 2), "remove_rows": n_mut,
                      "remove_ms": round(t_rem * 1e3, 2), "full_build_ms": round(t_build * 1e3, 1)},
-        "server": st,
+        "server": st_main,
+        "env": env_fingerprint(),
     }
     print(json.dumps(res), flush=True)
 

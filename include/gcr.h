@@ -346,7 +346,7 @@ gcr_status gcr_profile_vectors(gcr_ctx* ctx, const float* frames,
                                void* stream);
 
 /* ---------------------------------------------------------------------
- * Serving: a resident gallery and a request loop.
+ * Serving: a resident gallery and continuous batching of requests.
  *
  * The paper notes that the kNN graph of the database can be computed in
  * advance, leaving only the queries' part per request (Sec. IV-F).  A server
@@ -364,34 +364,54 @@ gcr_status gcr_profile_vectors(gcr_ctx* ctx, const float* frames,
  *
  * Only gallery rows within `rounds` hops of the gallery items the queries
  * touch change; the server recomputes exactly those rows (up to
- * cfg.max_recomputed per round) and reads the rest from the resident copy.
+ * cfg.max_recomputed per round and request) and reads the rest from the
+ * resident copy.
  *
- * A worker thread admits submitted requests, in order, into free slots; a
- * slot is a fixed partition of device memory (sized for cfg.max_batch
- * queries) with its own HIP stream, so up to cfg.slots requests run on the
- * device at once.  Cameras (Eq. (8), (9)) are not used in serving.
+ * Continuous batching: a worker thread keeps cfg.lanes batches on the
+ * device (one HIP stream each).  Whenever a lane is free it forms a batch
+ * from the queued requests in order, while their queries fit the lane's
+ * cfg.max_batch query rows, the batch holds at most cfg.max_requests
+ * requests, and a request scratch slot is free: admission is by memory (a
+ * 1-query request takes one row and one slot; the number of slots comes
+ * from cfg.mem_budget).  A batch shares its two gallery sweeps among all its
+ * queries (their kNN over the gallery, and the final top-K over the
+ * gallery's round-L rows, where each query leaves out the rows its own
+ * request recomputed); each request's propagation and recomputed rows use
+ * its own slot.  Cameras (Eq. (8), (9)) are not used in serving.
  * ------------------------------------------------------------------- */
 typedef struct gcr_server gcr_server;
 
 typedef struct {
-  int32_t slots;          /* requests in flight at once, 1..16 (default 4)    */
-  int32_t max_batch;      /* queries per request (default 512; capped so that
-                             max_batch * k <= 16384)                          */
-  int32_t max_recomputed; /* gallery rows recomputed per round and request
-                             (default 65536)                                  */
+  int32_t lanes;            /* batches on the device at once, 1..8 (default 2) */
+  int32_t max_batch;        /* query rows of one batch, which also bounds one
+                               request (default 512; capped so that
+                               max_batch * k <= 16384)                       */
+  int32_t max_requests;     /* requests co-batched into one batch, 1..256
+                               (default 16)                                  */
+  int32_t max_recomputed;   /* gallery rows recomputed per round and request
+                               (default 65536)                               */
   int32_t gallery_capacity; /* gallery rows reserved for inserts; 0: the
-                             initial gallery size (default 0)                 */
+                               initial gallery size (default 0)              */
+  int32_t reserved;         /* 0                                              */
+  uint64_t mem_budget;      /* device bytes for request scratch slots (the
+                               per-request hop sets and recomputed rows); 0:
+                               lanes x max_requests slots (default 0)        */
 } gcr_server_config;
 void gcr_server_config_default(gcr_server_config* cfg);
 
 typedef struct {
   int64_t requests_done;       /* requests finished (any status)             */
   int64_t queries_done;
+  int64_t batches_done;        /* batches finished                           */
+  int64_t max_batch_requests;  /* most requests seen in one batch            */
+  int64_t max_batch_rows;      /* most query rows seen in one batch          */
   int64_t max_recomputed_rows; /* largest per-round recomputed set seen      */
-  int64_t slots, max_batch, max_recomputed;
+  int64_t lanes, max_batch, max_requests, request_slots, max_recomputed;
   int64_t device_bytes;        /* device memory held by the server           */
+  int64_t slot_bytes;          /* device memory of one request slot          */
   int64_t gallery_size;        /* live gallery items                          */
   int64_t gallery_capacity;    /* gallery rows reserved                       */
+  int64_t enqueue_us;          /* host time spent enqueuing batches, in all   */
 } gcr_server_stats;
 
 /* Build a server on ctx's device.
@@ -413,7 +433,8 @@ gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery,
                              const gcr_params* p, const gcr_server_config* cfg,
                              gcr_server** out);
 /* Queue one request: q_host is a HOST array [b, d] float32, copied before
- * the call returns; 1 <= b <= max_batch.  *ticket identifies the request.
+ * the call returns; 1 <= b <= cfg.max_batch.  *ticket identifies the
+ * request.
  * Thread-safe.  Errors: INVALID. */
 gcr_status gcr_server_submit(gcr_server* srv, const float* q_host, int32_t b,
                              uint64_t* ticket);

@@ -203,6 +203,8 @@ def knn_blocked(X: np.ndarray, k: int, rows: Optional[np.ndarray] = None,
             idx[a + t, :len(take)] = take
             dist[a + t, :len(take)] = D[t, take]
 
+    # each block's distance rows stay within 256 MB
+    block = max(16, min(block, (1 << 28) // (8 * max(n, 1))))
     nt = threads or max(1, min(16, len(os.sched_getaffinity(0))))
     with ThreadPoolExecutor(nt) as ex:
         list(ex.map(one_block, range(0, len(rows), block)))

@@ -70,15 +70,18 @@ class GcrGraph(C.Structure):
 
 
 class GcrServerConfig(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("max_batch", C.c_int32), ("max_recomputed", C.c_int32),
-                ("gallery_capacity", C.c_int32)]
+    _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("max_requests", C.c_int32),
+                ("max_recomputed", C.c_int32), ("gallery_capacity", C.c_int32), ("reserved", C.c_int32),
+                ("mem_budget", C.c_uint64)]
 
 
 class GcrServerStats(C.Structure):
-    _fields_ = [("requests_done", C.c_int64), ("queries_done", C.c_int64),
-                ("max_recomputed_rows", C.c_int64), ("slots", C.c_int64), ("max_batch", C.c_int64),
-                ("max_recomputed", C.c_int64), ("device_bytes", C.c_int64), ("gallery_size", C.c_int64),
-                ("gallery_capacity", C.c_int64)]
+    _fields_ = [("requests_done", C.c_int64), ("queries_done", C.c_int64), ("batches_done", C.c_int64),
+                ("max_batch_requests", C.c_int64), ("max_batch_rows", C.c_int64),
+                ("max_recomputed_rows", C.c_int64), ("lanes", C.c_int64), ("max_batch", C.c_int64),
+                ("max_requests", C.c_int64), ("request_slots", C.c_int64), ("max_recomputed", C.c_int64),
+                ("device_bytes", C.c_int64), ("slot_bytes", C.c_int64), ("gallery_size", C.c_int64),
+                ("gallery_capacity", C.c_int64), ("enqueue_us", C.c_int64)]
 
 
 _lib = None

@@ -2,8 +2,9 @@
 
     python -m paper_2306_08792_amd.build
 
-Compiles every csrc/*.hip with hipcc for gfx950 and links the shared
-library next to this file.  Objects go to <repo>/_build/.
+Compiles every csrc/*.hip with hipcc for gfx950 (and the host-only
+csrc/*.cpp with the same compiler) and links the shared library next to
+this file.  Objects go to <repo>/_build/.
 """
 from __future__ import annotations
 
@@ -39,8 +40,12 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
+
+
 def _compile(src: str, obj: str) -> None:
-    cmd = [_hipcc(), *FLAGS, "-c", src, "-o", obj]
+    flags = FLAGS if src.endswith(".hip") else HOST_FLAGS
+    cmd = [_hipcc(), *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -48,8 +53,8 @@ def _compile(src: str, obj: str) -> None:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
-    objs = [os.path.join(BUILD, s[:-4] + ".o") for s in srcs]
+    srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") or f.endswith(".cpp"))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in srcs]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         futs = [ex.submit(_compile, os.path.join(CSRC, s), o) for s, o in zip(srcs, objs)]
         for f in futs:

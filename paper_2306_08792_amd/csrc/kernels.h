@@ -30,9 +30,19 @@ struct ColumnFilter {
   const uint32_t* stamp_of = nullptr;
   uint32_t stamp = 0;
   const int* count = nullptr;
+  // per-row masks: row r of the search (relative to its first row) leaves
+  // out column c when row_mark[r] is set and row_mark[r][c] == row_stamp[r]
+  // (rows of different serving requests in one batch skip different rows)
+  const uint32_t* const* row_mark = nullptr;
+  const uint32_t* row_stamp = nullptr;
 };
-__device__ __forceinline__ bool column_out(const ColumnFilter& f, int64_t c, int64_t c0) {
-  return (f.stamp_of && f.stamp_of[c] == f.stamp) || (f.count && c - c0 >= (int64_t)*f.count);
+__device__ __forceinline__ bool column_out(const ColumnFilter& f, int64_t c, int64_t c0, int64_t rrel) {
+  if ((f.stamp_of && f.stamp_of[c] == f.stamp) || (f.count && c - c0 >= (int64_t)*f.count)) return true;
+  if (f.row_mark) {
+    const uint32_t* m = f.row_mark[rrel];
+    if (m && m[c] == f.row_stamp[rrel]) return true;
+  }
+  return false;
 }
 
 // ---- simtopk.hip : fused MFMA similarity tiles + streaming per-row top-k

@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(RefineArgs a) {
     const int nj = (int)min<int64_t>(FB_CW, ncols - j0);
     for (int j = wave; j < nj; j += 4) {
       const int64_t col = a.c0 + j0 + j;
-      bool ok = !(a.exclude_self && col == row) && !column_out(a.filt, col, a.c0);
+      bool ok = !(a.exclude_self && col == row) && !column_out(a.filt, col, a.c0, row - a.r0);
       if (L == 1) ok = ok && a.cam[col] != rcam;
       uint64_t v = GCR_EMPTY;
       if (ok) v = wave_exact_sqdist_reg(xr, a.X + col * (int64_t)a.d, a.d);
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(FBT) void fallback_kernel(RefineArgs a) {
     const int rcam = a.cam ? a.cam[row] : 0;
     for (int64_t j = wave; j < ncols; j += NW) {
       const int64_t col = a.c0 + j;
-      bool ok = !(a.exclude_self && col == row) && !column_out(a.filt, col, a.c0);
+      bool ok = !(a.exclude_self && col == row) && !column_out(a.filt, col, a.c0, row - a.r0);
       if (L == 1) ok = ok && a.cam[col] != rcam;
       uint64_t v = GCR_EMPTY;
       if (ok) v = wave_exact_sqdist_reg(xr, a.X + col * (int64_t)a.d, a.d);
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void band_sweep_kernel(RefineArgs a) {
         if (jr >= ncols) continue;
         const int64_t col = a.c0 + jr;
         if (a.exclude_self && col == row) continue;
-        if (column_out(a.filt, col, a.c0)) continue;
+        if (column_out(a.filt, col, a.c0, row - a.r0)) continue;
         if (L == 1 && a.cam[col] == s_cam[pr]) continue;
         const float key = a.n2[col] - 2.0f * acc[i][j];
         if (key <= cut) {

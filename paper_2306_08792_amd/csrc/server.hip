@@ -1,11 +1,22 @@
 // Serving loop.  A gallery stays resident in HBM with its frozen kNN graph,
 // degrees and the gallery-only propagated features of every round (graphs
-// of the database computed in advance, Sec. IV-F).  A worker thread admits
-// query batches into slots as slots free up; a slot is a fixed partition of
-// device memory with its own HIP stream, so requests that arrive while
-// others run overlap on the device.  Each request is computed exactly over
-// the node set gallery + its queries (see serve.hip), independently of the
-// other requests in flight.
+// of the database computed in advance, Sec. IV-F).  Requests are batched
+// continuously: a worker thread hands the queued requests to a scheduler
+// (scheduler.h) that forms a batch whenever one of the server's lanes is
+// free, taking requests in order while their query rows fit the lane's
+// query region and a request scratch slot (the per-request device memory,
+// counted from the memory budget) is free.  A batch runs on its lane's HIP
+// stream, so batches overlap on the device while new requests queue.
+//
+// Within a batch the two gallery sweeps are shared by all its queries: one
+// screened kNN search of every query row over the gallery, and one final
+// top-K search over the gallery's round-L features in which every row
+// leaves out the gallery rows its own request recomputed (a per-row mask).
+// Between them each request is computed exactly over the node set
+// gallery + its own queries (see serve.hip), independently of the other
+// requests, in its own scratch slot; its recomputed rows get a small search
+// of their own and are merged into its rows' lists.  A query row's result
+// therefore does not depend on which requests share its batch.
 //
 // The gallery is mutable: rows are appended or removed between requests and
 // its kNN lists are maintained exactly (gallery.hip), after which the graph,
@@ -25,6 +36,7 @@
 #include <vector>
 
 #include "host.h"
+#include "scheduler.h"
 
 using namespace gcr;
 using namespace gcr::host;
@@ -150,21 +162,38 @@ struct Request {
   bool done = false;
 };
 
-struct Slot {
-  hipStream_t st = nullptr;
-  hipEvent_t ev = nullptr;
-  Request* req = nullptr;
-  uint32_t stamp = 0;
-  int64_t qbase = 0, pbase = 0;
-  KnnScratch kn0, knA, knB;
-  int32_t* q_idx; float* q_dist; float* q_w; float* Dq; uint64_t* keys;
-  uint32_t* touched; float* dD; int32_t* seg_start; int32_t* seg_len; int32_t* T_list;
+// Scratch of one request (a scheduler slot): its query edges, the hop sets
+// of every round (stamped marks and positions over the gallery) and the
+// rows it recomputes, which live in the slot's region [pbase, pbase + Rc)
+// of the feature arrays.
+struct ReqSlot {
+  int64_t pbase = 0;
+  float* q_w; float* Dq; uint64_t* keys; int32_t* T_list;
   int* counts;  // [0] touched items, [t] rows recomputed in round t
   std::vector<uint32_t*> mark;
   std::vector<int32_t*> pos, list;
-  int32_t* ia; float* da; int32_t* ib; float* db; int32_t* oi; float* od;
+};
+
+// A lane runs one batch at a time on its own stream: query rows
+// [qbase, qbase + max_batch) of the feature arrays, the shared sweeps'
+// scratch and outputs, and pinned host buffers for the batch's queries and
+// results.
+struct Lane {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  int64_t qbase = 0;
+  KnnScratch kn0, knA, knB;
+  int32_t* q_idx; float* q_dist;               // [max_batch, k] the queries' gallery lists
+  int32_t* ia; float* da; int32_t* ib; float* db;
+  int32_t* oi; float* od;                      // [max_batch, K]
+  uint32_t* touched; float* dD; int32_t* seg_start; int32_t* seg_len;  // [Gcap], stamped
   unsigned* maxL; unsigned* scratch_max;
+  const uint32_t** row_mark; uint32_t* row_stamp;  // [max_batch] final sweep masks
   float* h_q = nullptr; int32_t* h_idx = nullptr; float* h_dist = nullptr; int* h_counts = nullptr;
+  const uint32_t** h_row_mark = nullptr; uint32_t* h_row_stamp = nullptr;
+  bool busy = false;
+  SchedBatch batch;
+  std::vector<Request*> reqs;
 };
 
 }  // namespace
@@ -186,7 +215,13 @@ struct gcr_server {
   int32_t* map_b = nullptr;
   int32_t* repair = nullptr;       // [Gcap] rows whose lists are searched again
   int* mcount = nullptr;           // [64] device counters
-  int d = 0, k = 0, L = 0, K = 0, S = 0, Rq = 0, Rc = 0, P = 0, prec = 0;
+  int d = 0, k = 0, L = 0, K = 0, prec = 0;
+  int NL = 0;       // lanes (batches in flight)
+  int Rq = 0;       // query rows of one batch (= the largest request)
+  int MR = 0;       // requests of one batch
+  int NS = 0;       // request scratch slots
+  int Rc = 0;       // gallery rows recomputed per round and request
+  int P = 0;        // sort size of one request's query edges
   int64_t rows_total = 0;
   void* mem = nullptr;
   std::vector<float*> X;
@@ -194,12 +229,15 @@ struct gcr_server {
   unsigned* max0 = nullptr;
   unsigned* maxLg = nullptr;
   gcr_graph g;
-  std::vector<Slot> slots;
+  std::vector<ReqSlot> rslots;
+  std::vector<Lane> lanes;
+  std::unique_ptr<Scheduler> sched;
+  uint32_t next_stamp = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Request*> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   uint64_t next_ticket = 1;
+  int lanes_signalled = 0;  // completions reported by stream callbacks
   bool stop = false;
   std::thread worker;
   std::string err;
@@ -226,124 +264,183 @@ int pow2_at_least(int x) {
   return p;
 }
 
-// Enqueue one request on its slot's stream; returns "" or an error message.
-std::string enqueue_request(gcr_server* s, Slot& sl, Request& r) {
-  const hipStream_t st = sl.st;
-  const int b = r.b, d = s->d, k = s->k, K = s->K, L = s->L;
-  if (++sl.stamp == 0) sl.stamp = 1;
-  const uint32_t stamp = sl.stamp;
-  memcpy(sl.h_q, r.q.data(), (size_t)b * d * sizeof(float));
-  float* q0 = s->X[0] + sl.qbase * d;
-  SRV_HIP(hipMemcpyAsync(q0, sl.h_q, (size_t)b * d * sizeof(float), hipMemcpyHostToDevice, st));
-  if (s->p.normalize_input) launch_normalize_rows(q0, q0, b, d, st);
-  launch_screen_prep_rows(s->op0.prec, s->X[0], sl.qbase, b, nullptr, d, s->op0.Xs, s->op0.ld, s->op0.n2, s->op0.scale,
-                          s->op0.rn, sl.scratch_max, st);
+// Host callback at the end of a batch's stream work: wake the worker.
+void batch_done_cb(void* arg) {
+  gcr_server* s = (gcr_server*)arg;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->lanes_signalled += 1;
+  }
+  s->cv_work.notify_all();
+}
+
+// Enqueue one batch on its lane's stream; returns "" or an error message.
+std::string enqueue_batch(gcr_server* s, Lane& ln) {
+  const hipStream_t st = ln.st;
+  const SchedBatch& bt = ln.batch;
+  const int B = bt.rows, d = s->d, k = s->k, K = s->K, L = s->L;
+  for (size_t r = 0; r < bt.items.size(); ++r)
+    memcpy(ln.h_q + (size_t)bt.items[r].row0 * d, ln.reqs[r]->q.data(), (size_t)bt.items[r].b * d * sizeof(float));
+  float* q0 = s->X[0] + ln.qbase * d;
+  SRV_HIP(hipMemcpyAsync(q0, ln.h_q, (size_t)B * d * sizeof(float), hipMemcpyHostToDevice, st));
+  if (s->p.normalize_input) launch_normalize_rows(q0, q0, B, d, st);
+  launch_screen_prep_rows(s->op0.prec, s->X[0], ln.qbase, B, nullptr, d, s->op0.Xs, s->op0.ld, s->op0.n2,
+                          s->op0.scale, s->op0.rn, ln.scratch_max, st);
   if (L == 0) {
-    serve_knn(s->op0, (const float*)s->max0, s->X[0], d, sl.knA, sl.qbase, b, 0, s->G, K, sl.oi, sl.od,
+    // no rounds: the final top-K of every query over the gallery as given
+    serve_knn(s->op0, (const float*)s->max0, s->X[0], d, ln.knA, ln.qbase, B, 0, s->G, K, ln.oi, ln.od,
               ColumnFilter{}, st);
   } else {
-    serve_knn(s->op0, (const float*)s->max0, s->X[0], d, sl.kn0, sl.qbase, b, 0, s->G, k, sl.q_idx, sl.q_dist,
+    // the shared sweep: every query's k nearest gallery items
+    serve_knn(s->op0, (const float*)s->max0, s->X[0], d, ln.kn0, ln.qbase, B, 0, s->G, k, ln.q_idx, ln.q_dist,
               ColumnFilter{}, st);
-    const int P = pow2_at_least(b * k);
-    launch_serve_query_edges(b, k, sl.q_idx, sl.q_dist, s->p.gamma, sl.q_w, sl.Dq, sl.keys, P, st);
-    launch_serve_sort_pairs(sl.keys, P, st);
-    fill_u32(sl.counts, 0u, L + 1, st);
-    launch_serve_touched(sl.keys, b * k, sl.q_w, stamp, sl.touched, sl.dD, sl.seg_start, sl.seg_len, sl.T_list,
-                         sl.counts, st);
-    for (int t = 1; t <= L; ++t) {
-      const int32_t* src = t == 1 ? sl.T_list : sl.list[t - 1];
-      const int src_cap = t == 1 ? s->Rq * k : s->Rc;
-      launch_serve_expand(src, sl.counts + (t - 1), src_cap, s->g.idx, k, s->g.rev_ptr, s->g.rev_src, stamp,
-                          sl.mark[t], sl.pos[t], sl.list[t], sl.counts + t, s->Rc, st);
-      ServePropArgs a;
-      a.d = d; a.k = k; a.b = b;
-      a.Xprev = s->X[t - 1]; a.Xcur = s->X[t];
-      a.qbase = sl.qbase; a.pbase = sl.pbase;
-      a.gidx = s->g.idx; a.gw = s->g.w; a.rev_ptr = s->g.rev_ptr; a.rev_src = s->g.rev_src; a.rev_w = s->g.rev_w;
-      a.D0 = s->g.deg;
-      a.stamp = stamp;
-      a.touched = sl.touched; a.dD = sl.dD; a.seg_start = sl.seg_start; a.seg_len = sl.seg_len;
-      a.pair_keys = sl.keys; a.q_idx = sl.q_idx; a.q_w = sl.q_w; a.Dq = sl.Dq;
-      a.prev_mark = t > 1 ? sl.mark[t - 1] : nullptr;
-      a.prev_pos = t > 1 ? sl.pos[t - 1] : nullptr;
-      a.cur_list = sl.list[t]; a.cur_pos = sl.pos[t]; a.cur_count = sl.counts + t; a.cap = s->Rc;
-      launch_serve_propagate(a, st);
+    launch_copy_u32(s->maxLg, ln.maxL, 2, st);
+    // each request over gallery + its own queries, in its own slot
+    for (size_t r = 0; r < bt.items.size(); ++r) {
+      const SchedItem& it = bt.items[r];
+      ReqSlot& rs = s->rslots[it.slot];
+      const uint32_t stamp = ln.h_row_stamp[it.row0];
+      const int b = it.b;
+      const int P = pow2_at_least(b * k);
+      launch_serve_query_edges(b, k, ln.q_idx + (int64_t)it.row0 * k, ln.q_dist + (int64_t)it.row0 * k, s->p.gamma,
+                               rs.q_w, rs.Dq, rs.keys, P, st);
+      launch_serve_sort_pairs(rs.keys, P, st);
+      fill_u32(rs.counts, 0u, L + 1, st);
+      launch_serve_touched(rs.keys, b * k, rs.q_w, stamp, ln.touched, ln.dD, ln.seg_start, ln.seg_len, rs.T_list,
+                           rs.counts, st);
+      for (int t = 1; t <= L; ++t) {
+        const int32_t* src = t == 1 ? rs.T_list : rs.list[t - 1];
+        const int src_cap = t == 1 ? s->Rq * k : s->Rc;
+        launch_serve_expand(src, rs.counts + (t - 1), src_cap, s->g.idx, k, s->g.rev_ptr, s->g.rev_src, stamp,
+                            rs.mark[t], rs.pos[t], rs.list[t], rs.counts + t, s->Rc, st);
+        ServePropArgs a;
+        a.d = d; a.k = k; a.b = b;
+        a.Xprev = s->X[t - 1]; a.Xcur = s->X[t];
+        a.qbase = ln.qbase + it.row0; a.pbase = rs.pbase;
+        a.gidx = s->g.idx; a.gw = s->g.w; a.rev_ptr = s->g.rev_ptr; a.rev_src = s->g.rev_src; a.rev_w = s->g.rev_w;
+        a.D0 = s->g.deg;
+        a.stamp = stamp;
+        a.touched = ln.touched; a.dD = ln.dD; a.seg_start = ln.seg_start; a.seg_len = ln.seg_len;
+        a.pair_keys = rs.keys; a.q_idx = ln.q_idx + (int64_t)it.row0 * k; a.q_w = rs.q_w; a.Dq = rs.Dq;
+        a.prev_mark = t > 1 ? rs.mark[t - 1] : nullptr;
+        a.prev_pos = t > 1 ? rs.pos[t - 1] : nullptr;
+        a.cur_list = rs.list[t]; a.cur_pos = rs.pos[t]; a.cur_count = rs.counts + t; a.cap = s->Rc;
+        launch_serve_propagate(a, st);
+      }
+      // the request's recomputed rows into the round-L operand (their
+      // maxima widen the batch's screening margin)
+      launch_screen_prep_rows(s->opL.prec, s->X[L], rs.pbase, s->Rc, rs.counts + L, d, s->opL.Xs, s->opL.ld,
+                              s->opL.n2, s->opL.scale, s->opL.rn, ln.maxL, st);
+      SRV_HIP(hipMemcpyAsync(ln.h_counts + r * 64, rs.counts, (size_t)(L + 1) * sizeof(int), hipMemcpyDeviceToHost,
+                             st));
     }
-    // final top-K over the round-L features: unchanged gallery rows from the
-    // resident copy (recomputed ones masked out), recomputed rows from the
-    // slot, merged
-    launch_copy_u32(s->maxLg, sl.maxL, 2, st);
-    launch_screen_prep_rows(s->opL.prec, s->X[L], sl.qbase, b, nullptr, d, s->opL.Xs, s->opL.ld, s->opL.n2,
-                            s->opL.scale, s->opL.rn, sl.scratch_max, st);
-    launch_screen_prep_rows(s->opL.prec, s->X[L], sl.pbase, s->Rc, sl.counts + L, d, s->opL.Xs, s->opL.ld, s->opL.n2,
-                            s->opL.scale, s->opL.rn, sl.maxL, st);
+    // the shared final sweep over the unchanged gallery rows: every row
+    // leaves out the rows its own request recomputed
+    launch_screen_prep_rows(s->opL.prec, s->X[L], ln.qbase, B, nullptr, d, s->opL.Xs, s->opL.ld, s->opL.n2,
+                            s->opL.scale, s->opL.rn, ln.scratch_max, st);
+    SRV_HIP(hipMemcpyAsync(ln.row_mark, ln.h_row_mark, (size_t)B * sizeof(uint32_t*), hipMemcpyHostToDevice, st));
+    SRV_HIP(hipMemcpyAsync(ln.row_stamp, ln.h_row_stamp, (size_t)B * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     ColumnFilter fa;
-    fa.stamp_of = sl.mark[L];
-    fa.stamp = stamp;
-    serve_knn(s->opL, (const float*)sl.maxL, s->X[L], d, sl.knA, sl.qbase, b, 0, s->G, K, sl.ia, sl.da, fa, st);
-    ColumnFilter fb;
-    fb.count = sl.counts + L;
-    serve_knn(s->opL, (const float*)sl.maxL, s->X[L], d, sl.knB, sl.qbase, b, sl.pbase, sl.pbase + s->Rc, K, sl.ib,
-              sl.db, fb, st);
-    launch_serve_merge(b, K, sl.ia, sl.da, sl.ib, sl.db, sl.list[L], sl.oi, sl.od, st);
-    SRV_HIP(hipMemcpyAsync(sl.h_counts, sl.counts, (size_t)(L + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    fa.row_mark = ln.row_mark;
+    fa.row_stamp = ln.row_stamp;
+    serve_knn(s->opL, (const float*)ln.maxL, s->X[L], d, ln.knA, ln.qbase, B, 0, s->G, K, ln.ia, ln.da, fa, st);
+    // each request's recomputed rows, merged into its rows' lists
+    for (size_t r = 0; r < bt.items.size(); ++r) {
+      const SchedItem& it = bt.items[r];
+      ReqSlot& rs = s->rslots[it.slot];
+      ColumnFilter fb;
+      fb.count = rs.counts + L;
+      serve_knn(s->opL, (const float*)ln.maxL, s->X[L], d, ln.knB, ln.qbase + it.row0, it.b, rs.pbase,
+                rs.pbase + s->Rc, K, ln.ib, ln.db, fb, st);
+      launch_serve_merge(it.b, K, ln.ia + (int64_t)it.row0 * K, ln.da + (int64_t)it.row0 * K, ln.ib, ln.db,
+                         rs.list[L], ln.oi + (int64_t)it.row0 * K, ln.od + (int64_t)it.row0 * K, st);
+    }
   }
-  SRV_HIP(hipMemcpyAsync(sl.h_idx, sl.oi, (size_t)b * K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  SRV_HIP(hipMemcpyAsync(sl.h_dist, sl.od, (size_t)b * K * sizeof(float), hipMemcpyDeviceToHost, st));
+  SRV_HIP(hipMemcpyAsync(ln.h_idx, ln.oi, (size_t)B * K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SRV_HIP(hipMemcpyAsync(ln.h_dist, ln.od, (size_t)B * K * sizeof(float), hipMemcpyDeviceToHost, st));
   SRV_HIP(hipGetLastError());
-  SRV_HIP(hipEventRecord(sl.ev, st));
+  SRV_HIP(hipEventRecord(ln.ev, st));
+  SRV_HIP(hipLaunchHostFunc(st, batch_done_cb, s));
   return "";
 }
 
-// Results of a finished slot into its request (worker thread, unlocked).
-void collect(gcr_server* s, Slot& sl) {
-  Request& r = *sl.req;
-  const size_t m = (size_t)r.b * s->K;
-  r.idx.assign(sl.h_idx, sl.h_idx + m);
-  for (int32_t& v : r.idx)
-    if (v >= 0) v = s->ext[v];
-  r.dist.assign(sl.h_dist, sl.h_dist + m);
-  int worst = 0;
-  for (int t = 1; t <= s->L; ++t) worst = std::max(worst, sl.h_counts[t]);
-  if (worst > s->Rc) {
-    r.status = GCR_ERR_UNSUPPORTED;
-    r.err = "request touches " + std::to_string(worst) + " gallery rows within the propagation depth, more than the "
-            "slot capacity of " + std::to_string(s->Rc);
+// Results of a finished batch into its requests (worker thread, unlocked).
+void collect(gcr_server* s, Lane& ln) {
+  const int K = s->K;
+  for (size_t r = 0; r < ln.batch.items.size(); ++r) {
+    const SchedItem& it = ln.batch.items[r];
+    Request& q = *ln.reqs[r];
+    const size_t m = (size_t)it.b * K, o = (size_t)it.row0 * K;
+    q.idx.assign(ln.h_idx + o, ln.h_idx + o + m);
+    for (int32_t& v : q.idx)
+      if (v >= 0) v = s->ext[v];
+    q.dist.assign(ln.h_dist + o, ln.h_dist + o + m);
+    int worst = 0;
+    for (int t = 1; t <= s->L; ++t) worst = std::max(worst, ln.h_counts[r * 64 + t]);
+    if (worst > s->Rc) {
+      q.status = GCR_ERR_UNSUPPORTED;
+      q.err = "request touches " + std::to_string(worst) + " gallery rows within the propagation depth, more than "
+              "the per-request capacity of " + std::to_string(s->Rc);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stats.requests_done += 1;
+    s->stats.queries_done += it.b;
+    s->stats.max_recomputed_rows = std::max<int64_t>(s->stats.max_recomputed_rows, worst);
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  s->stats.requests_done += 1;
-  s->stats.queries_done += r.b;
-  s->stats.max_recomputed_rows = std::max<int64_t>(s->stats.max_recomputed_rows, worst);
+  s->stats.batches_done += 1;
+  s->stats.max_batch_requests = std::max<int64_t>(s->stats.max_batch_requests, (int64_t)ln.batch.items.size());
+  s->stats.max_batch_rows = std::max<int64_t>(s->stats.max_batch_rows, ln.batch.rows);
 }
 
 void worker_main(gcr_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    bool busy = false;
-    for (Slot& sl : s->slots) {
-      if (!sl.req && !s->pending.empty() && !s->stop && !s->paused) {
-        Request* r = s->pending.front();
-        s->pending.pop_front();
-        sl.req = r;
+    // start batches on the free lanes
+    while (!s->stop && !s->paused) {
+      SchedBatch bt;
+      if (!s->sched->next(&bt)) break;
+      Lane& ln = s->lanes[bt.lane];
+      ln.batch = bt;
+      ln.reqs.clear();
+      for (size_t r = 0; r < bt.items.size(); ++r) {
+        const SchedItem& it = bt.items[r];
+        ln.reqs.push_back(s->reqs.at(it.ticket).get());
+        // a stamp per request (never 0): marks of earlier requests in the
+        // same slot stay below it and need no clearing
+        if (++s->next_stamp == 0) s->next_stamp = 1;
+        for (int j = 0; j < it.b; ++j) {
+          ln.h_row_mark[it.row0 + j] = s->L > 0 ? s->rslots[it.slot].mark[s->L] : nullptr;
+          ln.h_row_stamp[it.row0 + j] = s->next_stamp;
+        }
+      }
+      ln.busy = true;
+      lk.unlock();
+      const auto te0 = std::chrono::steady_clock::now();
+      const std::string e = enqueue_batch(s, ln);
+      const auto te1 = std::chrono::steady_clock::now();
+      lk.lock();
+      s->stats.enqueue_us += std::chrono::duration_cast<std::chrono::microseconds>(te1 - te0).count();
+      if (!e.empty()) {
         lk.unlock();
-        const std::string e = enqueue_request(s, sl, *r);
+        (void)hipStreamSynchronize(ln.st);
         lk.lock();
-        if (!e.empty()) {
-          (void)hipStreamSynchronize(sl.st);
+        for (Request* r : ln.reqs) {
           r->status = GCR_ERR_HIP;
           r->err = e;
           r->done = true;
-          sl.req = nullptr;
-          s->cv_done.notify_all();
         }
+        ln.busy = false;
+        s->sched->finish(bt.lane);
+        s->cv_done.notify_all();
       }
-      if (sl.req) busy = true;
     }
+    bool busy = false;
+    for (const Lane& ln : s->lanes) busy = busy || ln.busy;
     if (s->stop) {
-      while (!s->pending.empty()) {
-        Request* r = s->pending.front();
-        s->pending.pop_front();
+      for (uint64_t t : s->sched->drain()) {
+        Request* r = s->reqs.at(t).get();
         r->status = GCR_ERR_INVALID;
         r->err = "server destroyed before the request started";
         r->done = true;
@@ -352,29 +449,56 @@ void worker_main(gcr_server* s) {
       if (!busy) break;
     }
     if (!busy) {
-      s->cv_work.wait(lk, [&] { return s->stop || (!s->pending.empty() && !s->paused); });
+      s->cv_work.wait(lk, [&] { return s->stop || (s->sched->pending() > 0 && !s->paused); });
       continue;
     }
+    // sleep until a stream callback reports a finished batch (or new work
+    // can start on a free lane); the timed wait only guards against a lost
+    // wake-up
+    s->cv_work.wait_for(lk, std::chrono::milliseconds(5), [&] {
+      return s->stop || s->lanes_signalled > 0 ||
+             (!s->paused && s->sched->pending() > 0 && s->sched->free_lanes() > 0);
+    });
+    s->lanes_signalled = 0;
     lk.unlock();
-    bool progressed = false;
-    for (Slot& sl : s->slots) {
-      if (!sl.req) continue;
-      const hipError_t q = hipEventQuery(sl.ev);
+    for (size_t l = 0; l < s->lanes.size(); ++l) {
+      Lane& ln = s->lanes[l];
+      if (!ln.busy) continue;
+      const hipError_t q = hipEventQuery(ln.ev);
       if (q == hipErrorNotReady) continue;
       if (q == hipSuccess) {
-        collect(s, sl);
+        collect(s, ln);
       } else {
-        sl.req->status = GCR_ERR_HIP;
-        sl.req->err = std::string("request failed on the device: ") + hipGetErrorString(q);
+        for (Request* r : ln.reqs) {
+          r->status = GCR_ERR_HIP;
+          r->err = std::string("request failed on the device: ") + hipGetErrorString(q);
+        }
       }
       std::lock_guard<std::mutex> g2(s->mu);
-      sl.req->done = true;
-      sl.req = nullptr;
+      for (Request* r : ln.reqs) r->done = true;
+      ln.busy = false;
+      s->sched->finish((int)l);
       s->cv_done.notify_all();
-      progressed = true;
     }
-    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     lk.lock();
+  }
+}
+
+// Device memory of one request scratch slot.
+void plan_req_slot(Arena& ar, const gcr_server* s, ReqSlot& rs) {
+  const int64_t qk = (int64_t)s->Rq * s->k;
+  rs.q_w = ar.take<float>((size_t)s->P);
+  rs.Dq = ar.take<float>((size_t)s->Rq);
+  rs.keys = ar.take<uint64_t>((size_t)s->P);
+  rs.T_list = ar.take<int32_t>((size_t)qk);
+  rs.counts = ar.take<int>(64);
+  rs.mark.assign(s->L + 1, nullptr);
+  rs.pos.assign(s->L + 1, nullptr);
+  rs.list.assign(s->L + 1, nullptr);
+  for (int t = 1; t <= s->L; ++t) {
+    rs.mark[t] = ar.take<uint32_t>((size_t)s->Gcap);
+    rs.pos[t] = ar.take<int32_t>((size_t)s->Gcap);
+    rs.list[t] = ar.take<int32_t>((size_t)s->Rc);
   }
 }
 
@@ -412,47 +536,39 @@ void plan_server(Arena& ar, gcr_server* s) {
   s->map_b = ar.take<int32_t>((size_t)s->Gcap);
   s->repair = ar.take<int32_t>((size_t)s->Gcap);
   s->mcount = ar.take<int>(64);
-  for (Slot& sl : s->slots) {
-    plan_scratch(ar, sl.kn0, s->Rq, s->Gcap, s->k);
-    plan_scratch(ar, sl.knA, s->Rq, s->Gcap, s->K);
-    plan_scratch(ar, sl.knB, s->Rq, s->Rc, s->K);
+  for (ReqSlot& rs : s->rslots) plan_req_slot(ar, s, rs);
+  for (Lane& ln : s->lanes) {
+    plan_scratch(ar, ln.kn0, s->Rq, s->Gcap, s->k);
+    plan_scratch(ar, ln.knA, s->Rq, s->Gcap, s->K);
+    plan_scratch(ar, ln.knB, s->Rq, s->Rc, s->K);
     const int64_t qk = (int64_t)s->Rq * s->k;
-    sl.q_idx = ar.take<int32_t>((size_t)qk);
-    sl.q_dist = ar.take<float>((size_t)qk);
-    sl.q_w = ar.take<float>((size_t)s->P);
-    sl.Dq = ar.take<float>((size_t)s->Rq);
-    sl.keys = ar.take<uint64_t>((size_t)s->P);
-    sl.touched = ar.take<uint32_t>((size_t)s->Gcap);
-    sl.dD = ar.take<float>((size_t)s->Gcap);
-    sl.seg_start = ar.take<int32_t>((size_t)s->Gcap);
-    sl.seg_len = ar.take<int32_t>((size_t)s->Gcap);
-    sl.T_list = ar.take<int32_t>((size_t)qk);
-    sl.counts = ar.take<int>(64);
-    sl.mark.assign(s->L + 1, nullptr);
-    sl.pos.assign(s->L + 1, nullptr);
-    sl.list.assign(s->L + 1, nullptr);
-    for (int t = 1; t <= s->L; ++t) {
-      sl.mark[t] = ar.take<uint32_t>((size_t)s->Gcap);
-      sl.pos[t] = ar.take<int32_t>((size_t)s->Gcap);
-      sl.list[t] = ar.take<int32_t>((size_t)s->Rc);
-    }
+    ln.q_idx = ar.take<int32_t>((size_t)qk);
+    ln.q_dist = ar.take<float>((size_t)qk);
+    ln.touched = ar.take<uint32_t>((size_t)s->Gcap);
+    ln.dD = ar.take<float>((size_t)s->Gcap);
+    ln.seg_start = ar.take<int32_t>((size_t)s->Gcap);
+    ln.seg_len = ar.take<int32_t>((size_t)s->Gcap);
     const int64_t qK = (int64_t)s->Rq * s->K;
-    sl.ia = ar.take<int32_t>((size_t)qK); sl.da = ar.take<float>((size_t)qK);
-    sl.ib = ar.take<int32_t>((size_t)qK); sl.db = ar.take<float>((size_t)qK);
-    sl.oi = ar.take<int32_t>((size_t)qK); sl.od = ar.take<float>((size_t)qK);
-    sl.maxL = ar.take<unsigned>(64);
-    sl.scratch_max = ar.take<unsigned>(64);
+    ln.ia = ar.take<int32_t>((size_t)qK); ln.da = ar.take<float>((size_t)qK);
+    ln.ib = ar.take<int32_t>((size_t)qK); ln.db = ar.take<float>((size_t)qK);
+    ln.oi = ar.take<int32_t>((size_t)qK); ln.od = ar.take<float>((size_t)qK);
+    ln.maxL = ar.take<unsigned>(64);
+    ln.scratch_max = ar.take<unsigned>(64);
+    ln.row_mark = (const uint32_t**)ar.take<uint64_t>((size_t)s->Rq);
+    ln.row_stamp = ar.take<uint32_t>((size_t)s->Rq);
   }
 }
 
 void release(gcr_server* s) {
-  for (Slot& sl : s->slots) {
-    if (sl.ev) (void)hipEventDestroy(sl.ev);
-    if (sl.st) (void)hipStreamDestroy(sl.st);
-    if (sl.h_q) (void)hipHostFree(sl.h_q);
-    if (sl.h_idx) (void)hipHostFree(sl.h_idx);
-    if (sl.h_dist) (void)hipHostFree(sl.h_dist);
-    if (sl.h_counts) (void)hipHostFree(sl.h_counts);
+  for (Lane& ln : s->lanes) {
+    if (ln.ev) (void)hipEventDestroy(ln.ev);
+    if (ln.st) (void)hipStreamDestroy(ln.st);
+    if (ln.h_q) (void)hipHostFree(ln.h_q);
+    if (ln.h_idx) (void)hipHostFree(ln.h_idx);
+    if (ln.h_dist) (void)hipHostFree(ln.h_dist);
+    if (ln.h_counts) (void)hipHostFree(ln.h_counts);
+    if (ln.h_row_mark) (void)hipHostFree(ln.h_row_mark);
+    if (ln.h_row_stamp) (void)hipHostFree(ln.h_row_stamp);
   }
   if (s->mst) (void)hipStreamDestroy(s->mst);
   if (s->mem) (void)hipFree(s->mem);
@@ -483,17 +599,13 @@ gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config
   gcr_server_config c;
   gcr_server_config_default(&c);
   if (cfg) c = *cfg;
-  if (c.slots < 1 || c.slots > 16) return fail(ctx, GCR_ERR_INVALID, "slots must be in 1..16");
-  if (c.max_batch < 1 || c.max_recomputed < 1) return fail(ctx, GCR_ERR_INVALID, "bad slot capacities");
+  if (c.lanes < 1 || c.lanes > 8) return fail(ctx, GCR_ERR_INVALID, "lanes must be in 1..8");
+  if (c.max_batch < 1 || c.max_requests < 1 || c.max_requests > 256 || c.max_recomputed < 1)
+    return fail(ctx, GCR_ERR_INVALID, "bad batch capacities (max_batch >= 1, max_requests in 1..256, "
+                                      "max_recomputed >= 1)");
   const int64_t cap = c.gallery_capacity > 0 ? c.gallery_capacity : ng;
   if (cap < ng) return fail(ctx, GCR_ERR_INVALID, "gallery_capacity is below the gallery size");
   if (cap > (int64_t)1 << 30) return fail(ctx, GCR_ERR_UNSUPPORTED, "galleries above 2^30 items are not supported");
-  {
-    // screening operands over the gallery capacity plus every slot's rows
-    const int64_t rq = std::min(c.max_batch, 16384 / p->k), rc = std::min<int64_t>(c.max_recomputed, cap);
-    const gcr_status ost = check_operand(ctx, p->precision, cap + (int64_t)c.slots * (rq + rc), d);
-    if (ost != GCR_OK) return ost;
-  }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
 
   gcr_server* s = new gcr_server();
@@ -506,22 +618,55 @@ gcr_status server_new(gcr_ctx* ctx, const gcr_params* p, const gcr_server_config
   s->L = p->rounds;
   s->K = p->topk_out;
   s->prec = p->precision;
-  s->S = c.slots;
+  s->NL = c.lanes;
   s->Rq = std::min(c.max_batch, 16384 / p->k);
+  s->MR = c.max_requests;
   s->Rc = (int)std::min<int64_t>(c.max_recomputed, cap);
   s->P = pow2_at_least(s->Rq * p->k);
-  s->rows_total = cap + (int64_t)s->S * (s->Rq + s->Rc);
-  s->slots.resize(s->S);
-  for (int i = 0; i < s->S; ++i) {
-    s->slots[i].qbase = cap + (int64_t)i * (s->Rq + s->Rc);
-    s->slots[i].pbase = s->slots[i].qbase + s->Rq;
+  // request scratch slots: as many as the memory budget holds (at most one
+  // per request a full set of lanes can carry), else lanes x max_requests
+  Arena one;
+  ReqSlot probe;
+  plan_req_slot(one, s, probe);
+  const int64_t slot_bytes = (int64_t)one.off + (int64_t)s->Rc * d * sizeof(float) * (s->L + 1);
+  const int64_t most = (int64_t)s->NL * s->MR;
+  int64_t ns = most;
+  if (c.mem_budget > 0) {
+    ns = std::min<int64_t>(most, (int64_t)(c.mem_budget / (uint64_t)slot_bytes));
+    if (ns < 1) {
+      delete s;
+      return fail(ctx, GCR_ERR_NOMEM, "memory budget of %llu bytes is below one request's scratch (%lld bytes)",
+                  (unsigned long long)c.mem_budget, (long long)slot_bytes);
+    }
   }
+  s->NS = (int)ns;
+  s->rows_total = cap + (int64_t)s->NL * s->Rq + (int64_t)s->NS * s->Rc;
+  {
+    const gcr_status ost = check_operand(ctx, p->precision, s->rows_total, d);
+    if (ost != GCR_OK) {
+      delete s;
+      return ost;
+    }
+  }
+  s->lanes.resize(s->NL);
+  for (int i = 0; i < s->NL; ++i) s->lanes[i].qbase = cap + (int64_t)i * s->Rq;
+  s->rslots.resize(s->NS);
+  for (int i = 0; i < s->NS; ++i) s->rslots[i].pbase = cap + (int64_t)s->NL * s->Rq + (int64_t)i * s->Rc;
+  SchedConfig sc;
+  sc.lanes = s->NL;
+  sc.max_batch = s->Rq;
+  sc.max_requests = s->MR;
+  sc.slots = s->NS;
+  s->sched.reset(new Scheduler(sc));
   s->ext.resize(ng);
   for (int64_t i = 0; i < ng; ++i) s->ext[i] = (int32_t)i;
   s->next_id = ng;
   memset(&s->stats, 0, sizeof s->stats);
-  s->stats.slots = s->S;
+  s->stats.lanes = s->NL;
   s->stats.max_batch = s->Rq;
+  s->stats.max_requests = s->MR;
+  s->stats.request_slots = s->NS;
+  s->stats.slot_bytes = slot_bytes;
   s->stats.max_recomputed = s->Rc;
 
   Arena dry;
@@ -601,25 +746,26 @@ std::string refresh_gallery(gcr_server* s) {
 // Slot state, streams and the worker thread (after the gallery is ready).
 std::string server_start(gcr_server* s) {
   // marks start clear; positions start in range, so a row marked in a
-  // request whose set overflowed still reads inside the slot (that request
+  // request whose set overflowed still reads inside its slot (that request
   // is reported as failed)
-  for (Slot& sl : s->slots) {
-    fill_u32(sl.touched, 0u, s->Gcap, s->mst);
+  for (ReqSlot& rs : s->rslots)
     for (int t = 1; t <= s->L; ++t) {
-      fill_u32(sl.mark[t], 0u, s->Gcap, s->mst);
-      fill_u32(sl.pos[t], 0u, s->Gcap, s->mst);
+      fill_u32(rs.mark[t], 0u, s->Gcap, s->mst);
+      fill_u32(rs.pos[t], 0u, s->Gcap, s->mst);
     }
-  }
+  for (Lane& ln : s->lanes) fill_u32(ln.touched, 0u, s->Gcap, s->mst);
   std::string e = refresh_gallery(s);
   if (!e.empty()) return e;
-  for (Slot& sl : s->slots) {
-    SRV_HIP(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
-    SRV_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
-    SRV_HIP(hipHostMalloc((void**)&sl.h_q, (size_t)s->Rq * s->d * sizeof(float), hipHostMallocDefault));
-    SRV_HIP(hipHostMalloc((void**)&sl.h_idx, (size_t)s->Rq * s->K * sizeof(int32_t), hipHostMallocDefault));
-    SRV_HIP(hipHostMalloc((void**)&sl.h_dist, (size_t)s->Rq * s->K * sizeof(float), hipHostMallocDefault));
-    SRV_HIP(hipHostMalloc((void**)&sl.h_counts, 64 * sizeof(int), hipHostMallocDefault));
-    memset(sl.h_counts, 0, 64 * sizeof(int));
+  for (Lane& ln : s->lanes) {
+    SRV_HIP(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
+    SRV_HIP(hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming));
+    SRV_HIP(hipHostMalloc((void**)&ln.h_q, (size_t)s->Rq * s->d * sizeof(float), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&ln.h_idx, (size_t)s->Rq * s->K * sizeof(int32_t), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&ln.h_dist, (size_t)s->Rq * s->K * sizeof(float), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&ln.h_counts, (size_t)s->MR * 64 * sizeof(int), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&ln.h_row_mark, (size_t)s->Rq * sizeof(uint32_t*), hipHostMallocDefault));
+    SRV_HIP(hipHostMalloc((void**)&ln.h_row_stamp, (size_t)s->Rq * sizeof(uint32_t), hipHostMallocDefault));
+    memset(ln.h_counts, 0, (size_t)s->MR * 64 * sizeof(int));
   }
   s->worker = std::thread(worker_main, s);
   return "";
@@ -630,8 +776,8 @@ void pause_and_drain(gcr_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   s->paused = true;
   s->cv_done.wait(lk, [&] {
-    for (const Slot& sl : s->slots)
-      if (sl.req) return false;
+    for (const Lane& ln : s->lanes)
+      if (ln.busy) return false;
     return true;
   });
 }
@@ -708,10 +854,13 @@ extern "C" {
 
 void gcr_server_config_default(gcr_server_config* c) {
   if (!c) return;
-  c->slots = 4;
+  c->lanes = 2;
   c->max_batch = 512;
+  c->max_requests = 16;
   c->max_recomputed = 65536;
   c->gallery_capacity = 0;
+  c->reserved = 0;
+  c->mem_budget = 0;
 }
 
 gcr_status gcr_server_create(gcr_ctx* ctx, const void* gallery, int32_t gallery_dtype, int64_t ng, int32_t d,
@@ -898,7 +1047,7 @@ gcr_status gcr_server_submit(gcr_server* s, const float* q_host, int32_t b, uint
   if (!s || !ticket) return GCR_ERR_INVALID;
   if (!q_host || b < 1) return sfail(s, GCR_ERR_INVALID, "queries must be a host array of b >= 1 rows");
   if (b > s->Rq)
-    return sfail(s, GCR_ERR_INVALID, "batch of " + std::to_string(b) + " queries exceeds the slot capacity of " +
+    return sfail(s, GCR_ERR_INVALID, "request of " + std::to_string(b) + " queries exceeds the batch capacity of " +
                                          std::to_string(s->Rq));
   auto r = std::make_unique<Request>();
   r->b = b;
@@ -910,7 +1059,7 @@ gcr_status gcr_server_submit(gcr_server* s, const float* q_host, int32_t b, uint
   }
   r->ticket = s->next_ticket++;
   *ticket = r->ticket;
-  s->pending.push_back(r.get());
+  s->sched->push(r->ticket, b);
   s->reqs.emplace(r->ticket, std::move(r));
   s->cv_work.notify_one();
   return GCR_OK;
@@ -961,8 +1110,8 @@ gcr_status gcr_server_destroy(gcr_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
-  for (Slot& sl : s->slots)
-    if (sl.st) (void)hipStreamSynchronize(sl.st);
+  for (Lane& ln : s->lanes)
+    if (ln.st) (void)hipStreamSynchronize(ln.st);
   release(s);
   return GCR_OK;
 }

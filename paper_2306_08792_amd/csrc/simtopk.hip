@@ -188,6 +188,11 @@ __device__ __forceinline__ void mma_chunk(const uint8_t* __restrict__ Rt, const 
   }
 }
 
+// A serving row's own mask: column c is left out when its stamp matches.
+__device__ __forceinline__ bool row_out(const uint32_t* mk, uint32_t stamp, int64_t c) {
+  return mk && mk[c] == stamp;
+}
+
 // Number of buffer entries whose ordered key is <= u (wave-uniform).
 template <int E>
 __device__ __forceinline__ int wave_count_le(const uint32_t (&key)[E], uint32_t u) {
@@ -264,6 +269,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ int row_cnt[NL][BM];
   __shared__ float row_twoE[BM], row_sc[BM];
   __shared__ int row_cam[BM];
+  __shared__ const uint32_t* row_mk[BM];  // per-row column masks (serving batches)
+  __shared__ uint32_t row_stp[BM];
   __shared__ int any_flag[2];
 
   // balanced mode: consecutive pieces (mostly the same row block) go to the
@@ -320,6 +327,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     const float n2r = rv ? a.n2[r] : 0.f;
     row_twoE[t] = 2.0f * screen_margin(n2r, rv ? a.rn[r] : 0.f, maxn2, a.maxn2[1], a.eps_s, a.eps_n);
     row_cam[t] = (a.cam && rv) ? a.cam[r] : 0;
+    row_mk[t] = (a.filt.row_mark && rv) ? a.filt.row_mark[r - a.r0] : nullptr;
+    row_stp[t] = (a.filt.row_mark && rv) ? a.filt.row_stamp[r - a.r0] : 0u;
     row_sc[t] = (PREC == GCR_PREC_FP8 && rv) ? a.scale[r] : 1.0f;
 #pragma unroll
     for (int L = 0; L < NL; ++L) {
@@ -475,12 +484,13 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
             const float key = fmaf(-2.0f, sv, n2v[i >> 2][i & 3]);
             const int lc = lc0 + 32 * cb + 8 * (i >> 2) + (i & 3);
             const uint64_t bit = 1ull << (cb * 16 + i);
-            if (key <= t0) {
+            if (key <= t0 && !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
               const int pos = atomicAdd(&row_cnt[0][lr], 1);
               if (pos < a.C) buf0[pos] = pack_cand(key, cbase + (uint32_t)lc);
               else lost[rb2][0] |= bit;
             }
-            if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1) {
+            if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1 &&
+                !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
               const int pos = atomicAdd(&row_cnt[NL - 1][lr], 1);
               if (pos < a.C) buf1[pos] = pack_cand(key, cbase + (uint32_t)lc);
               else lost[rb2][NL - 1] |= bit;

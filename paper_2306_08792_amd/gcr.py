@@ -395,12 +395,12 @@ class Server:
     wait() returns (indices int32 [b, K], distances float32 [b, K]).
     """
 
-    def __init__(self, ctx: Context, gallery: Optional[torch.Tensor], p: Optional[Params], slots: int = 4,
+    def __init__(self, ctx: Context, gallery: Optional[torch.Tensor], p: Optional[Params], lanes: int = 2,
                  max_batch: int = 512, max_recomputed: int = 65536, gallery_capacity: int = 0,
-                 _load_path: Optional[str] = None):
+                 max_requests: int = 16, mem_budget: int = 0, _load_path: Optional[str] = None):
         self.ctx = ctx
         self.lib = ctx.lib
-        cfg = L.GcrServerConfig(slots, max_batch, max_recomputed, gallery_capacity)
+        cfg = L.GcrServerConfig(lanes, max_batch, max_requests, max_recomputed, gallery_capacity, 0, mem_budget)
         if _load_path is not None:
             h = C.c_void_p()
             st = self.lib.gcr_server_load(ctx.h, _load_path.encode(), C.byref(cfg), C.byref(h))
@@ -465,10 +465,11 @@ class Server:
         return self.wait(self.submit(q))
 
     @classmethod
-    def load(cls, ctx: Context, path: str, slots: int = 4, max_batch: int = 512, max_recomputed: int = 65536,
-             gallery_capacity: int = 0) -> "Server":
+    def load(cls, ctx: Context, path: str, lanes: int = 2, max_batch: int = 512, max_recomputed: int = 65536,
+             gallery_capacity: int = 0, max_requests: int = 16, mem_budget: int = 0) -> "Server":
         """A server started from a state written by save()."""
-        return cls(ctx, None, None, slots, max_batch, max_recomputed, gallery_capacity, _load_path=path)
+        return cls(ctx, None, None, lanes, max_batch, max_recomputed, gallery_capacity, max_requests, mem_budget,
+                   _load_path=path)
 
     def _read_shape(self, path: str):
         import struct

@@ -50,8 +50,8 @@ def test_params_default(lib):
 def test_struct_sizes_match_header():
     assert C.sizeof(L.GcrParams) == 13 * 4
     assert C.sizeof(L.GcrGraph) == 8 + 4 * 4 + 19 * 8
-    assert C.sizeof(L.GcrServerConfig) == 4 * 4
-    assert C.sizeof(L.GcrServerStats) == 9 * 8
+    assert C.sizeof(L.GcrServerConfig) == 6 * 4 + 8
+    assert C.sizeof(L.GcrServerStats) == 16 * 8
 
 
 def test_graph_bytes_and_bind_layout(lib):

@@ -42,7 +42,7 @@ def test_insert_remove_equals_fresh_server(ctx, prec):
     rng = np.random.default_rng(7)
     k, K = 8, 10
     p = Params(k=k, rounds=2, gamma=0.2, topk_out=K, precision=prec, rebuild_each_round=False)
-    srv = Server(ctx, torch.from_numpy(Xall[:2500]).cuda(), p, slots=2, max_batch=64, max_recomputed=3200,
+    srv = Server(ctx, torch.from_numpy(Xall[:2500]).cuda(), p, lanes=2, max_batch=64, max_recomputed=3200,
                  gallery_capacity=3200)
     try:
         ids1 = srv.insert(Xall[2500:2700])
@@ -57,7 +57,7 @@ def test_insert_remove_equals_fresh_server(ctx, prec):
         st = srv.stats()
         assert st["gallery_size"] == len(live) and st["gallery_capacity"] == 3200
         Xlive = np.ascontiguousarray(Xall[live])
-        fresh = Server(ctx, torch.from_numpy(Xlive).cuda(), p, slots=2, max_batch=64, max_recomputed=3200)
+        fresh = Server(ctx, torch.from_numpy(Xlive).cuda(), p, lanes=2, max_batch=64, max_recomputed=3200)
         try:
             same_answers(srv, fresh, live, reqs)
         finally:
@@ -81,7 +81,7 @@ def test_remove_everything_a_row_knows(ctx):
     k = 6
     p = Params(k=k, rounds=1, gamma=0.2, topk_out=12, precision=BF16, rebuild_each_round=False)
     n = Xall.shape[0]
-    srv = Server(ctx, torch.from_numpy(Xall).cuda(), p, slots=2, max_batch=64, max_recomputed=n, gallery_capacity=n)
+    srv = Server(ctx, torch.from_numpy(Xall).cuda(), p, lanes=2, max_batch=64, max_recomputed=n, gallery_capacity=n)
     try:
         g_idx, _ = oracle_gallery_lists(Xall, k)
         gone = np.unique(np.concatenate([g_idx[5], g_idx[77], np.arange(100, 125)]))
@@ -92,7 +92,7 @@ def test_remove_everything_a_row_knows(ctx):
         for j, i in enumerate(back):
             Xmap[int(i)] = Xall[100 + j]
         Xlive = np.stack([Xmap[int(i)] for i in live])
-        fresh = Server(ctx, torch.from_numpy(Xlive).cuda(), p, slots=2, max_batch=64, max_recomputed=n)
+        fresh = Server(ctx, torch.from_numpy(Xlive).cuda(), p, lanes=2, max_batch=64, max_recomputed=n)
         try:
             same_answers(srv, fresh, live, reqs)
         finally:
@@ -105,7 +105,7 @@ def test_save_load_roundtrip(ctx):
     print("mutable gallery: save / load", flush=True)
     Xall, reqs = gallery_and_queries(seed=9, n_ids=100, per=20, nreq=3, sizes=(3, 20, 50))
     p = Params(k=8, rounds=2, gamma=0.2, topk_out=10, precision=BF16, rebuild_each_round=False)
-    srv = Server(ctx, torch.from_numpy(Xall[:1800]).cuda(), p, slots=2, max_batch=64, max_recomputed=2000,
+    srv = Server(ctx, torch.from_numpy(Xall[:1800]).cuda(), p, lanes=2, max_batch=64, max_recomputed=2000,
                  gallery_capacity=2000)
     try:
         srv.insert(Xall[1800:1900])
@@ -113,7 +113,7 @@ def test_save_load_roundtrip(ctx):
         with tempfile.TemporaryDirectory() as td:
             path = os.path.join(td, "gallery.gcr")
             srv.save(path)
-            two = Server.load(ctx, path, slots=3, max_batch=64, max_recomputed=2000, gallery_capacity=2000)
+            two = Server.load(ctx, path, lanes=3, max_batch=64, max_recomputed=2000, gallery_capacity=2000)
             try:
                 assert np.array_equal(two.ids(), srv.ids())
                 for Q in reqs:
@@ -138,7 +138,7 @@ def test_mutation_errors_and_inflight_requests(ctx):
     p = Params(k=8, rounds=2, gamma=0.2, topk_out=10, precision=BF16, rebuild_each_round=False)
     with pytest.raises(GcrError, match="INVALID"):
         Server(ctx, torch.from_numpy(Xall[:900]).cuda(), p, gallery_capacity=800)
-    srv = Server(ctx, torch.from_numpy(Xall[:900]).cuda(), p, slots=2, max_batch=64, max_recomputed=1000,
+    srv = Server(ctx, torch.from_numpy(Xall[:900]).cuda(), p, lanes=2, max_batch=64, max_recomputed=1000,
                  gallery_capacity=950)
     try:
         with pytest.raises(GcrError, match="UNSUPPORTED"):
@@ -162,13 +162,13 @@ def test_zero_rounds_and_near_empty_gallery(ctx):
     print("mutable gallery: rounds 0, two items left", flush=True)
     Xall, reqs = gallery_and_queries(seed=11, n_ids=20, per=10, nreq=2, sizes=(3, 7))
     p = Params(k=4, rounds=0, gamma=0.2, topk_out=6, precision=BF16, rebuild_each_round=False)
-    srv = Server(ctx, torch.from_numpy(Xall[:150]).cuda(), p, slots=1, max_batch=16, max_recomputed=200,
+    srv = Server(ctx, torch.from_numpy(Xall[:150]).cuda(), p, lanes=1, max_batch=16, max_recomputed=200,
                  gallery_capacity=200)
     try:
         srv.insert(Xall[150:200])
         srv.remove(np.arange(0, 200, 3))
         live = srv.ids()
-        fresh = Server(ctx, torch.from_numpy(np.ascontiguousarray(Xall[live])).cuda(), p, slots=1, max_batch=16,
+        fresh = Server(ctx, torch.from_numpy(np.ascontiguousarray(Xall[live])).cuda(), p, lanes=1, max_batch=16,
                        max_recomputed=200)
         try:
             same_answers(srv, fresh, live, reqs)

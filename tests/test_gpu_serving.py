@@ -66,7 +66,7 @@ def test_serving_matches_oracle(ctx, prec):
     p = Params(k=k, rounds=2, gamma=0.2, topk_out=K, precision=prec, rebuild_each_round=False)
     op = O.Params(k=k, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
     g_idx, g_dist = oracle_gallery_lists(X, k)
-    srv = Server(ctx, torch.from_numpy(X).cuda(), p, slots=3, max_batch=64, max_recomputed=3000)
+    srv = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=3, max_batch=64, max_recomputed=3000)
     try:
         for Q in reqs:
             gi, gd = srv.query(Q)
@@ -86,7 +86,7 @@ def test_serving_one_round_and_zero_rounds(ctx):
     for rounds in (1, 0):
         p = Params(k=k, rounds=rounds, topk_out=K, precision=BF16, rebuild_each_round=False)
         op = O.Params(k=k, gamma=0.2, rounds=rounds, alpha=1.0, rebuild_each_round=False)
-        srv = Server(ctx, torch.from_numpy(X).cuda(), p, slots=2, max_batch=64, max_recomputed=3000)
+        srv = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=2, max_batch=64, max_recomputed=3000)
         try:
             for Q in reqs:
                 gi, gd = srv.query(Q)
@@ -97,21 +97,61 @@ def test_serving_one_round_and_zero_rounds(ctx):
 
 def test_serving_alone_equals_mix(ctx):
     """Each request's result is bitwise the same when it runs alone and when
-    it is admitted among others (4 slots, 12 requests queued at once)."""
+    it is co-batched with others (12 requests queued at once on 2 lanes:
+    batches of up to 64 query rows share their gallery sweeps)."""
     print("serving alone vs mix", flush=True)
     sizes = (1, 64, 7, 33, 2, 50, 16, 5, 64, 9, 21, 3)
     X, reqs = gallery_and_queries(seed=5, nreq=len(sizes), sizes=sizes)
     p = Params(k=8, rounds=2, topk_out=10, precision=BF16, rebuild_each_round=False)
-    srv = Server(ctx, torch.from_numpy(X).cuda(), p, slots=4, max_batch=64, max_recomputed=3000)
+    op = O.Params(k=8, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
+    g_idx, g_dist = oracle_gallery_lists(X, 8)
+    srv = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=2, max_batch=64, max_recomputed=3000)
     try:
         alone = [srv.query(Q) for Q in reqs]
+        assert srv.stats()["max_batch_requests"] == 1
         tickets = [srv.submit(Q) for Q in reqs]
         mixed = [srv.wait(t) for t in reversed(tickets)][::-1]
+        st = srv.stats()
+        assert st["max_batch_requests"] > 1, st  # the queued requests were co-batched
+        assert st["max_batch_rows"] <= 64, st
+        for (ai, ad), (mi, md), Q in zip(alone, mixed, reqs):
+            assert np.array_equal(ai, mi)
+            assert np.array_equal(ad.view(np.uint32), md.view(np.uint32))
+            check_request(mi, md, X, g_idx, g_dist, Q, op, 10)
+    finally:
+        srv.close()
+
+
+def test_serving_memory_based_admission(ctx):
+    """The request scratch comes from the memory budget: with room for two
+    request slots, batches hold at most two requests, every result still
+    equals the request run alone, and a budget below one slot is refused."""
+    print("serving memory budget", flush=True)
+    sizes = (3, 1, 20, 8, 2, 40, 5, 11)
+    X, reqs = gallery_and_queries(seed=7, nreq=len(sizes), sizes=sizes)
+    p = Params(k=8, rounds=2, topk_out=10, precision=BF16, rebuild_each_round=False)
+    ref = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=1, max_batch=64, max_recomputed=3000)
+    slot = ref.stats()["slot_bytes"]
+    try:
+        alone = [ref.query(Q) for Q in reqs]
+    finally:
+        ref.close()
+    srv = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=2, max_batch=64, max_requests=16, max_recomputed=3000,
+                 mem_budget=2 * slot + slot // 2)
+    try:
+        st = srv.stats()
+        assert st["request_slots"] == 2, st
+        tickets = [srv.submit(Q) for Q in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        assert 1 <= st["max_batch_requests"] <= 2, st
         for (ai, ad), (mi, md) in zip(alone, mixed):
             assert np.array_equal(ai, mi)
             assert np.array_equal(ad.view(np.uint32), md.view(np.uint32))
     finally:
         srv.close()
+    with pytest.raises(GcrError, match="NOMEM"):
+        Server(ctx, torch.from_numpy(X).cuda(), p, lanes=1, max_batch=64, max_recomputed=3000, mem_budget=slot // 2)
 
 
 def test_serving_bf16_gallery(ctx):
@@ -123,8 +163,8 @@ def test_serving_bf16_gallery(ctx):
     p = Params(k=8, rounds=2, topk_out=10, precision=BF16, rebuild_each_round=False)
     op = O.Params(k=8, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
     g_idx, g_dist = oracle_gallery_lists(vals, 8)
-    s16 = Server(ctx, torch.from_numpy(bits.view(np.int16)).cuda(), p, slots=2, max_batch=64, max_recomputed=3000)
-    s32 = Server(ctx, torch.from_numpy(vals).cuda(), p, slots=2, max_batch=64, max_recomputed=3000)
+    s16 = Server(ctx, torch.from_numpy(bits.view(np.int16)).cuda(), p, lanes=2, max_batch=64, max_recomputed=3000)
+    s32 = Server(ctx, torch.from_numpy(vals).cuda(), p, lanes=2, max_batch=64, max_recomputed=3000)
     try:
         for _, Q, _ in trace:
             a = s16.query(Q)
@@ -143,13 +183,13 @@ def test_serving_errors(ctx):
     with pytest.raises(GcrError):
         Server(ctx, torch.from_numpy(X).cuda(), Params(k=8, rebuild_each_round=True))
     with pytest.raises(GcrError):
-        Server(ctx, torch.from_numpy(X).cuda(), p, slots=0)
-    srv = Server(ctx, torch.from_numpy(X).cuda(), p, slots=2, max_batch=16, max_recomputed=20)
+        Server(ctx, torch.from_numpy(X).cuda(), p, lanes=0)
+    srv = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=2, max_batch=16, max_recomputed=20)
     try:
         with pytest.raises(GcrError):
             srv.submit(reqs[1])  # 40 queries > 16
         t = srv.submit(reqs[0])
-        with pytest.raises(GcrError, match="slot capacity"):
+        with pytest.raises(GcrError, match="per-request capacity"):
             srv.wait(t)  # five queries touch more than 20 rows
     finally:
         srv.close()
@@ -164,7 +204,7 @@ def test_serving_gallery_smaller_than_k(ctx):
     p = Params(k=k, rounds=2, gamma=0.2, topk_out=K, precision=BF16, rebuild_each_round=False)
     op = O.Params(k=k, gamma=0.2, rounds=2, alpha=1.0, rebuild_each_round=False)
     g_idx, g_dist = oracle_gallery_lists(X, k)
-    srv = Server(ctx, torch.from_numpy(X).cuda(), p, slots=1, max_batch=8, max_recomputed=6)
+    srv = Server(ctx, torch.from_numpy(X).cuda(), p, lanes=1, max_batch=8, max_recomputed=6)
     try:
         for Q in reqs:
             gi, gd = srv.query(Q)
