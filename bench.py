@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=20000, help="serving: measured requests (after 1,000 warm-ups)")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.7, 0.85, 1.0],
                     help="serving: offered loads of the Poisson phases, as fractions of the saturated throughput")
+    ap.add_argument("--no-clocks", action="store_true",
+                    help="do not read the device clocks with rocm-smi (for runs under a profiler)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy a device buffer of BYTES five times (reference kernel for the HBM "
                          "byte counters) and exit")
@@ -157,10 +159,30 @@ def cpu_baseline(w, p, sample_rows: int):
     }
 
 
-def env_fingerprint() -> dict:
-    """Software and device the numbers were taken on."""
+_CLOCKS = None
+
+
+def probe_clocks(skip: bool) -> None:
+    """Read the device clocks with rocm-smi.  Runs before this process first
+    touches the GPU (a child process started after that is refused on some
+    hosts, and under a profiler that initialises the GPU early), or not at
+    all with --no-clocks."""
+    global _CLOCKS
+    if skip:
+        return
     import subprocess
 
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        if r.returncode == 0:
+            card = next(iter(json.loads(r.stdout).values()))
+            _CLOCKS = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:  # rocm-smi is optional
+        pass
+
+
+def env_fingerprint() -> dict:
+    """Software and device the numbers were taken on."""
     import torch
 
     env = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None)}
@@ -172,13 +194,7 @@ def env_fingerprint() -> dict:
         pr = torch.cuda.get_device_properties(0)
         env.update(gpu=pr.name, arch=getattr(pr, "gcnArchName", None), compute_units=pr.multi_processor_count,
                    hbm_gib=round(pr.total_memory / 2**30, 1))
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
-        if r.returncode == 0:
-            card = next(iter(json.loads(r.stdout).values()))
-            env["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
-    except Exception:  # rocm-smi is optional
-        pass
+    env["clocks"] = _CLOCKS
     env["host_cores"] = len(os.sched_getaffinity(0))
     return env
 
@@ -767,6 +783,7 @@ def local_bench(args):
 
 def main():
     args = parse()
+    probe_clocks(args.no_clocks or bool(args.calibrate_copy))
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return

@@ -45,6 +45,8 @@ constexpr int SMEM = NSTAGE * STAGE;       // 144 KB
 constexpr int DMA_PER_WAVE = (BM + BN) / 8 / 4;  // 1 KB wave loads per chunk per wave
 // s_waitcnt immediate (gfx9 layout) that waits for vmcnt <= n only
 constexpr int waitcnt_vm(int n) { return 0xF70 | (n & 0xF) | (((n >> 4) & 3) << 14); }
+// ... and for lgkmcnt == 0 (this wave's LDS reads have returned)
+constexpr int waitcnt_vm_lgkm0(int n) { return 0x070 | (n & 0xF) | (((n >> 4) & 3) << 14); }
 }  // namespace
 
 int sim_topk_grid(int RB, int S) { return RB * S; }
@@ -105,86 +107,72 @@ __device__ __forceinline__ const uint8_t* frag(const uint8_t* base, int r, int l
   return base + r * 128 + ((lp ^ (r & 7)) << 4);
 }
 
+// Fragments of one MFMA step: 2 row blocks and 4 column blocks of 32.
 // acc[cb][rb]: 4 column blocks x 2 row blocks of 32 x 32 (transposed
 // orientation: lane l holds row l & 31 of its row block and 16 columns).
+// A 128-byte chunk is 4 steps of 16 BF16 / 4 x 4 MFMAs of 2 float32 / 2
+// steps of 64 FP8 elements.
+template <int PREC> struct Frag;
+template <> struct Frag<GCR_PREC_FP32> { f32x4 r[2], c[4]; };
+template <> struct Frag<GCR_PREC_BF16> { bf16x8 r[2], c[4]; };
+template <> struct Frag<GCR_PREC_FP8> { i32x8 r[2], c[4]; };
 template <int PREC>
-__device__ __forceinline__ void mma_chunk(const uint8_t* __restrict__ Rt, const uint8_t* __restrict__ Ct, int wr,
-                                          int wc, int lane, f32x16 (&acc)[4][2]) {
+constexpr int steps_per_chunk() { return PREC == GCR_PREC_FP8 ? 2 : 4; }
+
+template <int PREC>
+__device__ __forceinline__ void frag_load(Frag<PREC>& f, const uint8_t* __restrict__ S, int q, int wr, int wc,
+                                          int lane) {
+  const uint8_t* Rt = S;
+  const uint8_t* Ct = S + RBYTES;
   const int l32 = lane & 31, half = lane >> 5;
+  if constexpr (PREC == GCR_PREC_FP8) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int r = wr + 32 * b + l32;
+      const i32x4 lo = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q);
+      const i32x4 hi = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q + 1);
+      f.r[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = wc + 32 * b + l32;
+      const i32x4 lo = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q);
+      const i32x4 hi = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q + 1);
+      f.c[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    }
+  } else {
+    using T = decltype(f.r[0]);
+    using V = typename std::remove_reference<T>::type;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) f.r[b] = *(const V*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) f.c[b] = *(const V*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void frag_mma(const Frag<PREC>& f, f32x16 (&acc)[4][2]) {
   if constexpr (PREC == GCR_PREC_FP32) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      f32x4 vr[2], vc[4];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) vr[b] = *(const f32x4*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) vc[b] = *(const f32x4*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[cb][s], vr[rb][s], acc[cb][rb], 0, 0, 0);
-    }
-  } else if constexpr (PREC == GCR_PREC_BF16) {
-    // fragments of step q + 1 are read while the 8 MFMAs of step q run
-    bf16x8 fr[2][2], fc[2][4];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      if (q < 4) {
-#pragma unroll
-        for (int b = 0; b < 2; ++b) fr[q & 1][b] = *(const bf16x8*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) fc[q & 1][b] = *(const bf16x8*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
-      }
-      if (q > 0) {
-        const int p = (q - 1) & 1;
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fc[p][cb], fr[p][rb], acc[cb][rb], 0, 0, 0);
-      }
-    }
-    // issue order: the first step's 6 reads, then per step its 8 MFMAs with
-    // the next step's 6 reads interleaved
-    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      i32x8 fr[2], fc[4];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int r = wr + 32 * b + l32;
-        const i32x4 lo = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q);
-        const i32x4 hi = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q + 1);
-        fr[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = wc + 32 * b + l32;
-        const i32x4 lo = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q);
-        const i32x4 hi = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q + 1);
-        fc[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-      }
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
-          acc[cb][rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fc[cb], fr[rb], acc[cb][rb], 0, 0, 0, 127,
-                                                                         0, 127);
-    }
+          acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.c[cb][s], f.r[rb][s], acc[cb][rb], 0, 0, 0);
+  } else if constexpr (PREC == GCR_PREC_BF16) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.c[cb], f.r[rb], acc[cb][rb], 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        acc[cb][rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.c[cb], f.r[rb], acc[cb][rb], 0, 0, 0, 127,
+                                                                       0, 127);
   }
 }
 
@@ -353,19 +341,39 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
 
   f32x16 acc[4][2];
 
-  // the chunk to prefetch next: tile pt, chunk pc, ring stage ps
+  // Ring: chunk g of the piece (tile g / kch, 128-byte chunk g % kch of the
+  // feature dimension) lands in stage g % NSTAGE.  issue() sends the next
+  // chunk (tile pt, chunk pc) to stage ps; past the piece's last chunk it
+  // sends the last chunk again (into a stage no live chunk uses), so every
+  // step has the same number of loads in flight behind it.
   int pt = 0, pc = 0, ps = 0;
-#define GCR_ISSUE_NEXT()                                                                              \
-  do {                                                                                               \
-    issue_chunk(smem + ps * STAGE, res, voff, roff0 + (uint32_t)pc * 128u,                           \
-                (uint32_t)(sc0 + (int64_t)pt * BN) * ld + (uint32_t)pc * 128u, step, wave);          \
-    ps = ps + 1 == NSTAGE ? 0 : ps + 1;                                                              \
-    if (++pc == kch) { pc = 0; ++pt; }                                                              \
-  } while (0)
+  const int last_g = total > 0 ? total - 1 : 0;
+  const int last_t = last_g / kch, last_c = last_g - last_t * kch;
+  auto issue = [&]() {
+    issue_chunk(smem + ps * STAGE, res, voff, roff0 + (uint32_t)pc * 128u,
+                (uint32_t)(sc0 + (int64_t)pt * BN) * ld + (uint32_t)pc * 128u, step, wave);
+    ps = ps + 1 == NSTAGE ? 0 : ps + 1;
+    const bool at_end = pt == last_t && pc == last_c;
+    const int npc = pc + 1 == kch ? 0 : pc + 1;
+    const int npt = pc + 1 == kch ? pt + 1 : pt;
+    pc = at_end ? pc : npc;
+    pt = at_end ? pt : npt;
+  };
 
-  // prologue: chunks 0 and 1 in flight
-  if (total > 0) GCR_ISSUE_NEXT();
-  if (total > 1) GCR_ISSUE_NEXT();
+  constexpr int NSTEP = steps_per_chunk<PREC>();
+  Frag<PREC> f[2];
+  // The vector-memory counter also counts the epilogue's candidate stores,
+  // which may complete out of order with the loads: after a wave has stored
+  // (or compacted), its next ring wait drains everything.
+  bool dirty = false;
+  if (total > 0) {
+    issue();
+    issue();
+    issue();
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * DMA_PER_WAVE));
+    asm volatile("s_barrier" ::: "memory");
+    frag_load<PREC>(f[0], smem, 0, wr, wc, lane);
+  }
 
   int g = 0, gs = 0;  // chunk being multiplied and its stage
   for (int tile = 0; tile < ntiles; ++tile) {
@@ -381,35 +389,40 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     uint32_t pf_stamp = 0u;
     uint32_t pf_sh = 0xffffffffu;  // shared threshold of (row, list) tid (ordered bits)
     for (int ch = 0; ch < kch; ++ch, ++g) {
-      // chunk g has landed once at most the next chunk's loads are pending;
-      // right after an epilogue (candidate stores, compaction loads) and at
-      // the end drain everything
-      if (ch == 0 || g + 1 >= total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-      else __builtin_amdgcn_s_waitcnt(waitcnt_vm(DMA_PER_WAVE));
-      // Every wave has waited for its own part of chunk g above; a plain
-      // barrier (no fence: a fence would also wait for the chunks still in
-      // flight) then makes the whole chunk visible.  The stage refilled next
-      // was last read by fragment loads that completed before the previous
-      // chunk's MFMAs issued.
-      asm volatile("s_barrier" ::: "memory");
-      if (g + 2 < total) GCR_ISSUE_NEXT();
-      if (ch == 0) {
-        // column data of this tile for the epilogue: independent loads
-        // issued after the chunk loads above, so their latency hides under
-        // the multiplies (the device-side column count is already in sc1)
-        const int64_t c = ct0 + tid;  // NT == BN
-        if (c < sc1) {
-          pf_n2 = a.n2[c];
-          if (a.cam) pf_cam = a.cam[c];
-          if (PREC == GCR_PREC_FP8) pf_sc = a.scale[c];
-          if (a.filt.stamp_of) pf_stamp = a.filt.stamp_of[c];
-        }
-        if (a.thr_shared && tid < BM * NL && row0 + (tid % BM) < a.r1)
-          pf_sh = a.thr_shared[(rrel0 + tid % BM) * NL + tid / BM];
-      }
       const uint8_t* S = smem + gs * STAGE;
-      gs = gs + 1 == NSTAGE ? 0 : gs + 1;
-      mma_chunk<PREC>(S, S + RBYTES, wr, wc, lane, acc);
+      const int gn = gs + 1 == NSTAGE ? 0 : gs + 1;
+#pragma unroll
+      for (int q = 0; q < NSTEP; ++q) {
+        if (q + 1 < NSTEP) {
+          frag_load<PREC>(f[(q + 1) & 1], S, q + 1, wr, wc, lane);
+        } else {
+          // Every fragment of chunk g has reached the registers (lgkmcnt
+          // 0), and chunk g + 1 has landed once at most the next chunk's
+          // loads are pending (all loads, after a store); the barrier then
+          // makes chunk g + 1 visible and frees stage gs, which receives
+          // chunk g + 3 while the last step's MFMAs run.
+          if (ch == 0 && __any(dirty)) __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+          else __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(DMA_PER_WAVE));
+          asm volatile("s_barrier" ::: "memory");
+          issue();
+          if (ch == 0) {
+            dirty = false;
+            // column data of this tile for the epilogue
+            const int64_t c = ct0 + tid;  // NT == BN
+            if (c < sc1) {
+              pf_n2 = a.n2[c];
+              if (a.cam) pf_cam = a.cam[c];
+              if (PREC == GCR_PREC_FP8) pf_sc = a.scale[c];
+              if (a.filt.stamp_of) pf_stamp = a.filt.stamp_of[c];
+            }
+            if (a.thr_shared && tid < BM * NL && row0 + (tid % BM) < a.r1)
+              pf_sh = a.thr_shared[(rrel0 + tid % BM) * NL + tid / BM];
+          }
+          frag_load<PREC>(f[(q + 1) & 1], smem + gn * STAGE, 0, wr, wc, lane);
+        }
+        frag_mma<PREC>(f[q & 1], acc);
+      }
+      gs = gn;
     }
 
     // ---------------- epilogue of one 128 x 256 tile ----------------
@@ -465,23 +478,40 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         uint64_t* buf1 = a.cand + (((rrel0 + lr) * NL + NL - 1) * (int64_t)a.S + cs) * a.C;
 #pragma unroll
         for (int L = 0; L < NL; ++L) lost[rb2][L] = 0ull;
+        // either list admits an entry only if its key is <= the larger of
+        // the two thresholds: a block of 16 entries whose smallest key is
+        // above it (nearly every block once the thresholds are tight) is
+        // dismissed with one compare
+        const float tmax = NL > 1 ? fmaxf(t0, t1) : t0;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           f32x4 n2v[4], scv[4];
-          i32x4 camv[4];
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
             const int c4 = lc0 + 32 * cb + 8 * g;
             n2v[g] = *(const f32x4*)&col_n2[c4];
-            if (NL > 1) camv[g] = *(const i32x4*)&col_cam[c4];
             if (PREC == GCR_PREC_FP8) scv[g] = *(const f32x4*)&col_sc[c4];
           }
+          float keys[16];
+          float kmin = INFINITY;
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             float sv = acc[cb][rb2][i];
             if (PREC == GCR_PREC_FP8) sv = sv * (rs * scv[i >> 2][i & 3]);
             // n2 - 2 s with one rounding (2 s is exact)
-            const float key = fmaf(-2.0f, sv, n2v[i >> 2][i & 3]);
+            keys[i] = fmaf(-2.0f, sv, n2v[i >> 2][i & 3]);
+            kmin = fminf(kmin, keys[i]);
+          }
+          if (!(kmin <= tmax)) continue;
+          dirty = true;
+          i32x4 camv[4];
+          if (NL > 1) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) camv[g] = *(const i32x4*)&col_cam[lc0 + 32 * cb + 8 * g];
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const float key = keys[i];
             const int lc = lc0 + 32 * cb + 8 * (i >> 2) + (i & 3);
             const uint64_t bit = 1ull << (cb * 16 + i);
             if (key <= t0 && !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
@@ -509,6 +539,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         const int more = any_flag[it & 1];
         if (tid == 0) any_flag[(it + 1) & 1] = 0;
         if (!more) break;
+        dirty = true;
         // compact the full buffers (a count past C counts lost entries too)
         for (int q = wave; q < NL * BM; q += NT / 64) {
           const int L = q / BM, lr = q - L * BM;
@@ -561,6 +592,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     if (tile == 0) {
       // set every row's threshold from its first tile instead of waiting
       // for its buffer to fill
+      dirty = true;
       for (int q = wave; q < NL * BM; q += NT / 64) {
         const int L = q / BM, lr = q - L * BM;
         const int kk = L == 0 ? a.k0 : a.k1;
@@ -574,8 +606,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       __syncthreads();
     }
   }
-#undef GCR_ISSUE_NEXT
-
+  // the loads of the chunks past the end are still landing in the ring
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
   __syncthreads();
   for (int t = tid; t < BM * NL; t += NT) {
     const int L = t / BM, lr = t - L * BM;
