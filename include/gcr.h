@@ -153,6 +153,9 @@ typedef struct {
   int64_t splits;             /* column splits of the last similarity sweep    */
   int64_t knn_exhaustive_rows;/* (row, list) pairs whose float32 band exceeded
                                  2,048 items, scored exactly over all columns */
+  int64_t tile_rows;          /* rows per workgroup tile of the last similarity
+                                 sweep: 128, or 256 for sweeps of one list over
+                                 many row blocks in float32 or BF16 */
 } gcr_stats;
 gcr_status gcr_get_stats(gcr_ctx* ctx, gcr_stats* out);
 gcr_status gcr_reset_stats(gcr_ctx* ctx);

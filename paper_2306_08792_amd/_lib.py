@@ -47,7 +47,7 @@ class GcrParams(C.Structure):
 class GcrStats(C.Structure):
     _fields_ = [("knn_rows", C.c_int64), ("knn_candidates", C.c_int64),
                 ("knn_fallback_rows", C.c_int64), ("splits", C.c_int64),
-                ("knn_exhaustive_rows", C.c_int64)]
+                ("knn_exhaustive_rows", C.c_int64), ("tile_rows", C.c_int64)]
 
 
 _P = C.c_void_p

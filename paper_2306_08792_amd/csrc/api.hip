@@ -132,7 +132,8 @@ int final_screen_prec(int precision) { return precision == GCR_FP8 ? GCR_BF16 : 
 gcr_status check_operand(gcr_ctx* c, int precision, int64_t rows, int d) {
   const int64_t npad = roundup(rows, 128) + 128;
   const int64_t ld = roundup((int64_t)d * esize_of(screen_prec_of(precision)), 128);
-  if (npad * ld >= ((int64_t)1 << 32))
+  // a 256-row tile of the last row block reads up to 128 rows past npad
+  if ((npad + 128) * ld >= ((int64_t)1 << 32))
     return fail(c, GCR_ERR_UNSUPPORTED,
                 "%lld rows of width %d exceed the 4 GiB screening operand of the similarity kernel",
                 (long long)rows, d);
@@ -204,16 +205,26 @@ void plan_knn(Arena& ar, KnnPlan& kp, int precision, int64_t n, int d, int64_t r
   while ((int64_t)kp.RB * S < 128 && (int64_t)S * 2 * TC <= kp.ncols && S * 2 * kp.C <= 2048 && S < 64) S *= 2;
   // With many row blocks the sweep is cut evenly over one workgroup per
   // compute unit instead (a row block split over workgroups becomes extra
-  // splits), so that no unit idles behind the last row blocks.
+  // splits), so that no unit idles behind the last row blocks; it uses
+  // 256-row tiles when there are enough of them.
   const int G = compute_units();
-  const int Sb = sim_topk_balanced_splits(kp.rows, kp.ncols, G);
   kp.balanced = 0;
-  if (Sb > 0 && Sb * kp.C <= 2048) {
-    S = Sb;
-    kp.balanced = 1;
-    kp.grid = G;
-    kp.ntr = (int)((kp.ncols + TC - 1) / TC);
-    kp.total_tiles = (int64_t)kp.RB * kp.ntr;
+  kp.bm = 128;
+  for (const int bm : {256, 128}) {
+    // (the 256-row kernel keeps room for a whole 256-column tile in every
+    // candidate buffer, so it needs C >= 512)
+    if (bm == 256 && (!sim_topk_large_tile(prec, kp.nl) || kp.C < 2 * TC)) continue;
+    const int Sb = sim_topk_balanced_splits(kp.rows, kp.ncols, G, bm);
+    if (Sb > 0 && Sb * kp.C <= 2048) {
+      S = Sb;
+      kp.balanced = 1;
+      kp.bm = bm;
+      kp.RB = (int)((kp.rows + bm - 1) / bm);
+      kp.grid = G;
+      kp.ntr = (int)((kp.ncols + TC - 1) / TC);
+      kp.total_tiles = (int64_t)kp.RB * kp.ntr;
+      break;
+    }
   }
   kp.S = S;
   kp.W = roundup((kp.ncols + S - 1) / S, TC);
@@ -269,7 +280,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
     launch_screen_prep(kp.prec, X, kp.n, d, kp.npad, kp.Xs, kp.ld, kp.n2, kp.scale, kp.rn, kp.maxn2, st);
   }
   SimArgs sa;
-  sa.Xs = kp.Xs; sa.npad = kp.npad; sa.ld_bytes = kp.ld; sa.kchunks = kp.kch; sa.n2 = kp.n2;
+  sa.Xs = kp.Xs; sa.npad = kp.npad; sa.ld_bytes = kp.ld; sa.n2 = kp.n2;
   sa.scale = kp.prec == GCR_PREC_FP8 ? kp.scale : nullptr;
   sa.cam = cam; sa.maxn2 = (const float*)kp.maxn2; sa.rn = kp.rn;
   sa.r0 = r0; sa.r1 = r1; sa.c0 = c0; sa.c1 = c1; sa.W = kp.W; sa.S = kp.S; sa.RB = kp.RB;
@@ -277,7 +288,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   sa.eps_s = eps_accumulation(kp.prec, d); sa.eps_n = eps_norm(d);
   sa.cand = kp.cand; sa.cnt = kp.cnt; sa.thr = kp.thr;
   sa.thr_init = nullptr;
-  sa.balanced = kp.balanced; sa.grid = kp.grid; sa.ntr = kp.ntr; sa.total_tiles = kp.total_tiles;
+  sa.balanced = kp.balanced; sa.grid = kp.grid; sa.ntr = kp.ntr; sa.total_tiles = kp.total_tiles; sa.bm = kp.bm;
   sa.thr_shared = nullptr;
   if (kp.S > 1) {
     fill_u32(kp.thr_shared, 0xffffffffu, kp.rows * kp.nl, st);
@@ -322,6 +333,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
     launch_raw_select(ra, st);
     c->knn_rows += kp.rows;
     c->splits = kp.S;
+    c->tile_rows = kp.bm;
     return;
   }
   if (kp.ord && r0 == 0 && c0 == 0 && r1 == c1 && k0 > 0) {
@@ -337,6 +349,7 @@ void run_knn(gcr_ctx* c, const KnnPlan& kp, const float* X, int d, const int* ca
   hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(1), 0, st, c->stats + 2, kp.fb_count + 1);
   c->knn_rows += kp.rows;
   c->splits = kp.S;
+  c->tile_rows = kp.bm;
 }
 
 gcr_status check_params(gcr_ctx* c, const gcr_params* p) {
@@ -582,6 +595,7 @@ gcr_status gcr_get_stats(gcr_ctx* c, gcr_stats* out) {
   out->knn_fallback_rows = (int64_t)h[1];
   out->knn_exhaustive_rows = (int64_t)h[2];
   out->splits = c->splits;
+  out->tile_rows = c->tile_rows;
   return GCR_OK;
 }
 

@@ -25,6 +25,7 @@ struct gcr_ctx {
   unsigned long long* stats = nullptr;  // device: [0] candidates, [1] re-swept pairs, [2] exhaustive pairs
   int64_t knn_rows = 0;
   int64_t splits = 0;
+  int64_t tile_rows = 0;
 };
 
 namespace gcr {
@@ -48,7 +49,7 @@ struct Arena {
 
 struct KnnPlan {
   int prec, nl, C, S, RB, kch, fb_grid;
-  int balanced = 0, grid = 0, ntr = 0;  // balanced similarity schedule
+  int balanced = 0, grid = 0, ntr = 0, bm = 128;  // balanced similarity schedule, tile rows
   int64_t total_tiles = 0;
   int64_t n, npad, ld, W, rows, ncols;
   uint8_t* Xs; float* n2; float* scale; float* rn; unsigned* maxn2;

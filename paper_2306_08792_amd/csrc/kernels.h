@@ -50,7 +50,6 @@ struct SimArgs {
   const uint8_t* Xs;  // screening operand, [npad, ld_bytes]
   int64_t npad;       // rows of Xs (reads beyond return zero)
   int64_t ld_bytes;   // multiple of 128
-  int kchunks;        // ld_bytes / 128
   const float* n2;    // [npad]
   const float* scale; // [npad] FP8 row scales or nullptr
   const int* cam;     // [n] or nullptr
@@ -60,7 +59,8 @@ struct SimArgs {
   int64_t c0, c1;     // columns [c0, c1)
   int64_t W;          // split width (multiple of the 256-column tile)
   int S;              // number of column splits (multiple of 8)
-  int RB;             // row blocks of 128
+  int RB;             // row blocks of bm rows
+  int bm = 128;       // rows per workgroup tile: 128, or 256 (see sim_topk_large_tile)
   int exclude_self;   // skip column == row
   int k0, k1;         // list sizes (global, cross)
   int C;              // candidate capacity per (row, list, split)
@@ -79,7 +79,10 @@ struct SimArgs {
   int64_t total_tiles = 0;  // balanced: RB * ntr
 };
 int sim_topk_grid(int RB, int S);
-int sim_topk_balanced_splits(int64_t rows, int64_t ncols, int G);
+int sim_topk_balanced_splits(int64_t rows, int64_t ncols, int G, int bm);
+// Whether the 256-row workgroup tile exists for a screening precision and
+// number of lists.
+int sim_topk_large_tile(int prec, int nl);
 // Initial admission thresholds from earlier neighbour lists (any k items give
 // an upper bound on the k-th distance): out[row * nl + L].
 void launch_seed_thresholds(const float* X, int d, int64_t n, const int32_t* idx0, int k0, const int32_t* idx1,

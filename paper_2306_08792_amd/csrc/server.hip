@@ -107,7 +107,7 @@ void serve_knn(const Operand& op, const float* maxn2, const float* X, int d, con
   fill_u32(s.fb_count, 0u, 3, st);
   fill_u32(s.band_cnt, 0u, s.band_max, st);
   SimArgs sa;
-  sa.Xs = op.Xs; sa.npad = op.npad; sa.ld_bytes = op.ld; sa.kchunks = op.kch; sa.n2 = op.n2;
+  sa.Xs = op.Xs; sa.npad = op.npad; sa.ld_bytes = op.ld; sa.n2 = op.n2;
   sa.scale = op.prec == GCR_PREC_FP8 ? op.scale : nullptr;
   sa.cam = nullptr; sa.maxn2 = maxn2; sa.rn = op.rn;
   sa.r0 = r0; sa.r1 = r0 + b; sa.c0 = c0; sa.c1 = c1;

@@ -36,17 +36,34 @@
 namespace gcr {
 
 namespace {
-constexpr int BM = 128, BN = 256, NT = 256;
-constexpr int RBYTES = BM * 128;           // row tile of one chunk in LDS
-constexpr int CBYTES = BN * 128;           // column tile of one chunk
-constexpr int STAGE = RBYTES + CBYTES;     // 48 KB
-constexpr int NSTAGE = 3;
-constexpr int SMEM = NSTAGE * STAGE;       // 144 KB
-constexpr int DMA_PER_WAVE = (BM + BN) / 8 / 4;  // 1 KB wave loads per chunk per wave
+constexpr int BN = 256, NT = 256;
 // s_waitcnt immediate (gfx9 layout) that waits for vmcnt <= n only
 constexpr int waitcnt_vm(int n) { return 0xF70 | (n & 0xF) | (((n >> 4) & 3) << 14); }
 // ... and for lgkmcnt == 0 (this wave's LDS reads have returned)
 constexpr int waitcnt_vm_lgkm0(int n) { return 0x070 | (n & 0xF) | (((n >> 4) & 3) << 14); }
+
+// Workgroup tiles.  BMT = 128: 128 rows x 256 columns (waves of 64 x 128),
+// 128-byte chunks of the feature dimension in a 3-stage ring (144 KB).
+// BMT = 256: 256 x 256 (waves of 128 x 128), 64-byte chunks in a 4-stage
+// ring (128 KB): per multiply-add it moves two thirds of the operand bytes
+// and reads two thirds of the LDS fragments of the smaller tile, for sweeps
+// with many row blocks.  A row of a chunk is P 16-byte parts, XOR-swizzled
+// in LDS so that the 8 rows one 128-byte bank window serves fall on
+// distinct parts.
+template <int BMT>
+struct Tile {
+  static constexpr int BM = BMT;
+  static constexpr int CHB = BMT == 256 ? 64 : 128;   // chunk bytes per row
+  static constexpr int P = CHB / 16;                   // 16-byte parts per chunk row
+  static constexpr int NSTAGE = BMT == 256 ? 4 : 3;
+  static constexpr int RBYTES = BM * CHB;              // row tile of one chunk
+  static constexpr int STAGE = RBYTES + BN * CHB;
+  static constexpr int SMEM = NSTAGE * STAGE;
+  static constexpr int RPL = 1024 / CHB;               // rows per 1 KB wave load
+  static constexpr int DMA_PER_WAVE = (BM + BN) / RPL / 4;
+  static constexpr int RBW = BM / 64;                  // 32-row blocks per wave
+  __device__ static int swz(int r) { return CHB == 128 ? (r & 7) : ((r >> 1) & 3); }
+};
 }  // namespace
 
 int sim_topk_grid(int RB, int S) { return RB * S; }
@@ -54,8 +71,8 @@ int sim_topk_grid(int RB, int S) { return RB * S; }
 // Balanced schedule for rows [r0, r0 + rows) x ncols columns on G
 // workgroups: the largest number of pieces (splits) one row block can be
 // cut into, or 0 when the rows are too few for it.
-int sim_topk_balanced_splits(int64_t rows, int64_t ncols, int G) {
-  const int64_t RB = (rows + BM - 1) / BM, nt = (ncols + BN - 1) / BN;
+int sim_topk_balanced_splits(int64_t rows, int64_t ncols, int G, int bm) {
+  const int64_t RB = (rows + bm - 1) / bm, nt = (ncols + BN - 1) / BN;
   if (RB < 64 || nt < 1) return 0;
   const int64_t T = RB * nt;
   if (T < G) return 0;
@@ -84,93 +101,101 @@ __device__ __forceinline__ i32x4 make_res(const void* p, uint64_t range) {
   return v;
 }
 
-// Issue this wave's share of one chunk: 1 KB blocks of 8 rows, lane l
-// bringing logical 16-byte part (l & 7) ^ (row & 7) of row blk*8 + l/8 so the
-// data lands swizzled.  Block blk = wave + 4 i has row & 7 == l / 8, so the
-// per-lane offset voff is the same for every block and chunk; the byte
-// offsets of the row tile, the column tile, the chunk and the block are
-// wave-uniform and go into the scalar offset of one descriptor that spans
-// the whole operand.
+// Issue this wave's share of one chunk: 1 KB blocks of RPL rows, lane l
+// bringing logical part (l % P) ^ swz(row) of row blk * RPL + l / P so the
+// data lands swizzled.  Block blk = wave + 4 i has the same swizzle for
+// every i, so the per-lane offset voff is the same for every block and
+// chunk; the byte offsets of the row tile, the column tile, the chunk and
+// the block are wave-uniform and go into the scalar offset of one
+// descriptor that spans the whole operand.
+template <int BMT>
 __device__ __forceinline__ void issue_chunk(uint8_t* stage, i32x4 res, int voff, uint32_t roff, uint32_t coff,
                                             uint32_t step, int wave) {
+  using T = Tile<BMT>;
 #pragma unroll
-  for (int i = 0; i < BM / 32; ++i)
+  for (int i = 0; i < T::BM / (4 * T::RPL); ++i)
     gcr_buffer_load_lds(res, (lds_u32_ptr)(stage + (wave + 4 * i) * 1024), 16, voff,
                         __builtin_amdgcn_readfirstlane(roff + i * step), 0, 0);
 #pragma unroll
-  for (int i = 0; i < BN / 32; ++i)
-    gcr_buffer_load_lds(res, (lds_u32_ptr)(stage + RBYTES + (wave + 4 * i) * 1024), 16, voff,
+  for (int i = 0; i < BN / (4 * T::RPL); ++i)
+    gcr_buffer_load_lds(res, (lds_u32_ptr)(stage + T::RBYTES + (wave + 4 * i) * 1024), 16, voff,
                         __builtin_amdgcn_readfirstlane(coff + i * step), 0, 0);
 }
 
+template <int BMT>
 __device__ __forceinline__ const uint8_t* frag(const uint8_t* base, int r, int lp) {
-  return base + r * 128 + ((lp ^ (r & 7)) << 4);
+  return base + r * Tile<BMT>::CHB + ((lp ^ Tile<BMT>::swz(r)) << 4);
 }
 
-// Fragments of one MFMA step: 2 row blocks and 4 column blocks of 32.
-// acc[cb][rb]: 4 column blocks x 2 row blocks of 32 x 32 (transposed
+// Fragments of one MFMA step: RBW row blocks and 4 column blocks of 32.
+// acc[cb][rb]: 4 column blocks x RBW row blocks of 32 x 32 (transposed
 // orientation: lane l holds row l & 31 of its row block and 16 columns).
-// A 128-byte chunk is 4 steps of 16 BF16 / 4 x 4 MFMAs of 2 float32 / 2
-// steps of 64 FP8 elements.
-template <int PREC> struct Frag;
-template <> struct Frag<GCR_PREC_FP32> { f32x4 r[2], c[4]; };
-template <> struct Frag<GCR_PREC_BF16> { bf16x8 r[2], c[4]; };
-template <> struct Frag<GCR_PREC_FP8> { i32x8 r[2], c[4]; };
+// A chunk row of P parts is P / 2 steps of 8 BF16 or 4 float32 values per
+// lane (float32: 4 MFMAs of 2 per step) or P / 4 steps of 32 FP8 values.
 template <int PREC>
-constexpr int steps_per_chunk() { return PREC == GCR_PREC_FP8 ? 2 : 4; }
+using FragT = typename std::conditional<PREC == GCR_PREC_FP32, f32x4,
+                                        typename std::conditional<PREC == GCR_PREC_BF16, bf16x8, i32x8>::type>::type;
+template <int PREC, int RBW>
+struct Frag {
+  FragT<PREC> r[RBW], c[4];
+};
+template <int PREC, int BMT>
+constexpr int steps_per_chunk() { return PREC == GCR_PREC_FP8 ? Tile<BMT>::P / 4 : Tile<BMT>::P / 2; }
 
-template <int PREC>
-__device__ __forceinline__ void frag_load(Frag<PREC>& f, const uint8_t* __restrict__ S, int q, int wr, int wc,
-                                          int lane) {
+template <int PREC, int BMT>
+__device__ __forceinline__ void frag_load(Frag<PREC, Tile<BMT>::RBW>& f, const uint8_t* __restrict__ S, int q,
+                                          int wr, int wc, int lane) {
+  using T = Tile<BMT>;
   const uint8_t* Rt = S;
-  const uint8_t* Ct = S + RBYTES;
+  const uint8_t* Ct = S + T::RBYTES;
   const int l32 = lane & 31, half = lane >> 5;
   if constexpr (PREC == GCR_PREC_FP8) {
+    const int p0 = half * (T::P / 2) + 2 * q;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < T::RBW; ++b) {
       const int r = wr + 32 * b + l32;
-      const i32x4 lo = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q);
-      const i32x4 hi = *(const i32x4*)frag(Rt, r, half * 4 + 2 * q + 1);
+      const i32x4 lo = *(const i32x4*)frag<BMT>(Rt, r, p0);
+      const i32x4 hi = *(const i32x4*)frag<BMT>(Rt, r, p0 + 1);
       f.r[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int r = wc + 32 * b + l32;
-      const i32x4 lo = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q);
-      const i32x4 hi = *(const i32x4*)frag(Ct, r, half * 4 + 2 * q + 1);
+      const i32x4 lo = *(const i32x4*)frag<BMT>(Ct, r, p0);
+      const i32x4 hi = *(const i32x4*)frag<BMT>(Ct, r, p0 + 1);
       f.c[b] = i32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     }
   } else {
-    using T = decltype(f.r[0]);
-    using V = typename std::remove_reference<T>::type;
+    using V = FragT<PREC>;
+    const int p0 = half * (T::P / 2) + q;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) f.r[b] = *(const V*)frag(Rt, wr + 32 * b + l32, half * 4 + q);
+    for (int b = 0; b < T::RBW; ++b) f.r[b] = *(const V*)frag<BMT>(Rt, wr + 32 * b + l32, p0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) f.c[b] = *(const V*)frag(Ct, wc + 32 * b + l32, half * 4 + q);
+    for (int b = 0; b < 4; ++b) f.c[b] = *(const V*)frag<BMT>(Ct, wc + 32 * b + l32, p0);
   }
 }
 
-template <int PREC>
-__device__ __forceinline__ void frag_mma(const Frag<PREC>& f, f32x16 (&acc)[4][2]) {
+template <int PREC, int RBW>
+__device__ __forceinline__ void frag_mma(const Frag<PREC, RBW>& f, f32x16 (&acc)[4][RBW]) {
   if constexpr (PREC == GCR_PREC_FP32) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RBW; ++rb)
           acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.c[cb][s], f.r[rb][s], acc[cb][rb], 0, 0, 0);
   } else if constexpr (PREC == GCR_PREC_BF16) {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RBW; ++rb)
         acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.c[cb], f.r[rb], acc[cb][rb], 0, 0, 0);
   } else {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RBW; ++rb)
         acc[cb][rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.c[cb], f.r[rb], acc[cb][rb], 0, 0, 0, 127,
                                                                        0, 127);
   }
@@ -203,15 +228,16 @@ __device__ __forceinline__ uint32_t wave_select(const uint32_t (&key)[E], int r)
 }
 
 // One wave compacts the candidate buffer of (list L, local row lr):
-// tau = k-th smallest key, keep the keys <= tau + 2E.  When that band does
-// not fit, keep only the keys below the (m+1)-th smallest, m = max(C/2, k),
-// and lower the admission threshold below that key, so the buffer still
-// holds every item of the split whose key is <= the threshold.  Order
+// tau = k-th smallest key, keep the keys <= tau + 2E.  When that band leaves
+// fewer than `room` free slots, keep only the keys below the (m+1)-th
+// smallest, m = max(C/2, k), and lower the admission threshold below that
+// key, so the buffer still holds every item of the split whose key is <=
+// the threshold.  Order
 // statistics come from a radix select on the ordered keys (ballots and
 // popcounts), not from sorting; the kept entries are written back densely
 // in no particular order.
 template <int E>
-__device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk, float twoE) {
+__device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk, float twoE, int room) {
   const int lane = threadIdx.x & 63;
   const int n = min(*cnt, C);
   uint64_t v[E];
@@ -225,7 +251,7 @@ __device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk,
   float th = *thr;
   if (n >= kk && kk > 0) th = fminf(th, unord_f32(wave_select<E>(key, kk)) + twoE);
   int newn = wave_count_le<E>(key, ord_f32(th));
-  if (newn > C - 16) {
+  if (newn > C - room) {
     const int m = max(C / 2, kk);
     if (m < newn) {
       // admit only keys strictly below the (m+1)-th smallest
@@ -247,8 +273,15 @@ __device__ void compact_row(uint64_t* base, int* cnt, float* thr, int C, int kk,
   if (lane == 0) { *cnt = off; *thr = th; }
 }
 
-template <int PREC, int NL, int E>
+template <int PREC, int NL, int E, int BMT>
 __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
+  using T = Tile<BMT>;
+  constexpr int BM = T::BM, RBW = T::RBW, NSTAGE = T::NSTAGE, STAGE = T::STAGE, DMA = T::DMA_PER_WAVE;
+  constexpr int SH = (BM * NL + NT - 1) / NT;  // shared thresholds prefetched per thread
+  // Candidate buffers with room for a whole tile before each admission (C
+  // >= 2 BN, 256-row tiles) instead of lost entries screened again after a
+  // compaction: the accumulators are then read once, in the admission.
+  constexpr bool ROOM = BMT == 256;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ __align__(16) float col_n2[BN];
   __shared__ __align__(16) float col_sc[BN];
@@ -327,22 +360,22 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     }
   }
 
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
-  const int kch = a.kchunks;
+  const int wr = (wave >> 1) * (BM / 2), wc = (wave & 1) * 128;
+  const int kch = (int)(a.ld_bytes / T::CHB);
   const int total = ntiles * kch;
   const uint32_t ld = (uint32_t)a.ld_bytes;
   const int l32 = lane & 31, half = lane >> 5;
   const int64_t rrel0 = row0 - a.r0;
   // one descriptor over the whole operand (its size is below 4 GiB)
   const i32x4 res = make_res(a.Xs, (uint64_t)a.npad * ld);
-  const int voff = (wave * 8 + (lane >> 3)) * (int)ld + (((lane & 7) ^ (lane >> 3)) << 4);
+  const int voff = (wave * T::RPL + lane / T::P) * (int)ld + (((lane % T::P) ^ T::swz(lane / T::P)) << 4);
   const uint32_t roff0 = (uint32_t)row0 * ld;
-  const uint32_t step = 32u * ld;
+  const uint32_t step = (uint32_t)(4 * T::RPL) * ld;
 
-  f32x16 acc[4][2];
+  f32x16 acc[4][RBW];
 
-  // Ring: chunk g of the piece (tile g / kch, 128-byte chunk g % kch of the
-  // feature dimension) lands in stage g % NSTAGE.  issue() sends the next
+  // Ring: chunk g of the piece (tile g / kch, chunk g % kch of the feature
+  // dimension) lands in stage g % NSTAGE.  issue() sends the next
   // chunk (tile pt, chunk pc) to stage ps; past the piece's last chunk it
   // sends the last chunk again (into a stage no live chunk uses), so every
   // step has the same number of loads in flight behind it.
@@ -350,8 +383,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   const int last_g = total > 0 ? total - 1 : 0;
   const int last_t = last_g / kch, last_c = last_g - last_t * kch;
   auto issue = [&]() {
-    issue_chunk(smem + ps * STAGE, res, voff, roff0 + (uint32_t)pc * 128u,
-                (uint32_t)(sc0 + (int64_t)pt * BN) * ld + (uint32_t)pc * 128u, step, wave);
+    issue_chunk<BMT>(smem + ps * STAGE, res, voff, roff0 + (uint32_t)(pc * T::CHB),
+                     (uint32_t)(sc0 + (int64_t)pt * BN) * ld + (uint32_t)(pc * T::CHB), step, wave);
     ps = ps + 1 == NSTAGE ? 0 : ps + 1;
     const bool at_end = pt == last_t && pc == last_c;
     const int npc = pc + 1 == kch ? 0 : pc + 1;
@@ -360,19 +393,18 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     pt = at_end ? pt : npt;
   };
 
-  constexpr int NSTEP = steps_per_chunk<PREC>();
-  Frag<PREC> f[2];
+  constexpr int NSTEP = steps_per_chunk<PREC, BMT>();
+  Frag<PREC, RBW> f[2];
   // The vector-memory counter also counts the epilogue's candidate stores,
   // which may complete out of order with the loads: after a wave has stored
   // (or compacted), its next ring wait drains everything.
   bool dirty = false;
   if (total > 0) {
-    issue();
-    issue();
-    issue();
-    __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * DMA_PER_WAVE));
+#pragma unroll
+    for (int i = 0; i < NSTAGE; ++i) issue();
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm((NSTAGE - 1) * DMA));
     asm volatile("s_barrier" ::: "memory");
-    frag_load<PREC>(f[0], smem, 0, wr, wc, lane);
+    frag_load<PREC, BMT>(f[0], smem, 0, wr, wc, lane);
   }
 
   int g = 0, gs = 0;  // chunk being multiplied and its stage
@@ -381,28 +413,31 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int rb2 = 0; rb2 < 2; ++rb2)
+      for (int rb2 = 0; rb2 < RBW; ++rb2)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[cb][rb2][i] = 0.f;
     float pf_n2 = INFINITY, pf_sc = 1.0f;
     int pf_cam = 0;
     uint32_t pf_stamp = 0u;
-    uint32_t pf_sh = 0xffffffffu;  // shared threshold of (row, list) tid (ordered bits)
+    uint32_t pf_sh[SH];  // shared thresholds of (row, list) tid + NT j (ordered bits)
+#pragma unroll
+    for (int j = 0; j < SH; ++j) pf_sh[j] = 0xffffffffu;
     for (int ch = 0; ch < kch; ++ch, ++g) {
       const uint8_t* S = smem + gs * STAGE;
       const int gn = gs + 1 == NSTAGE ? 0 : gs + 1;
 #pragma unroll
       for (int q = 0; q < NSTEP; ++q) {
         if (q + 1 < NSTEP) {
-          frag_load<PREC>(f[(q + 1) & 1], S, q + 1, wr, wc, lane);
+          frag_load<PREC, BMT>(f[(q + 1) & 1], S, q + 1, wr, wc, lane);
         } else {
           // Every fragment of chunk g has reached the registers (lgkmcnt
-          // 0), and chunk g + 1 has landed once at most the next chunk's
-          // loads are pending (all loads, after a store); the barrier then
-          // makes chunk g + 1 visible and frees stage gs, which receives
-          // chunk g + 3 while the last step's MFMAs run.
+          // 0), and chunk g + 1 has landed once at most the loads of the
+          // NSTAGE - 2 chunks issued after it are pending (all loads, after
+          // a store); the barrier then makes chunk g + 1 visible and frees
+          // stage gs, which receives chunk g + NSTAGE while the last step's
+          // MFMAs run.
           if (ch == 0 && __any(dirty)) __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-          else __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(DMA_PER_WAVE));
+          else __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * DMA));
           asm volatile("s_barrier" ::: "memory");
           issue();
           if (ch == 0) {
@@ -415,10 +450,15 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
               if (PREC == GCR_PREC_FP8) pf_sc = a.scale[c];
               if (a.filt.stamp_of) pf_stamp = a.filt.stamp_of[c];
             }
-            if (a.thr_shared && tid < BM * NL && row0 + (tid % BM) < a.r1)
-              pf_sh = a.thr_shared[(rrel0 + tid % BM) * NL + tid / BM];
+            if (a.thr_shared) {
+#pragma unroll
+              for (int j = 0; j < SH; ++j) {
+                const int e = tid + NT * j;
+                if (e < BM * NL && row0 + (e % BM) < a.r1) pf_sh[j] = a.thr_shared[(rrel0 + e % BM) * NL + e / BM];
+              }
+            }
           }
-          frag_load<PREC>(f[(q + 1) & 1], smem + gn * STAGE, 0, wr, wc, lane);
+          frag_load<PREC, BMT>(f[(q + 1) & 1], smem + gn * STAGE, 0, wr, wc, lane);
         }
         frag_mma<PREC>(f[q & 1], acc);
       }
@@ -431,9 +471,15 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     col_sc[tid] = pf_sc;
     // adopt the row's threshold published by the other splits of the row
     // (every split's k-th key + 2E bounds the row's k-th key + 2E from above)
-    if (a.thr_shared && tid < BM * NL && pf_sh != 0xffffffffu) {
-      float& t = row_thr[tid / BM][tid % BM];
-      t = fminf(t, unord_f32(pf_sh));
+    if (a.thr_shared) {
+#pragma unroll
+      for (int j = 0; j < SH; ++j) {
+        const int e = tid + NT * j;
+        if (e < BM * NL && pf_sh[j] != 0xffffffffu) {
+          float& t = row_thr[e / BM][e % BM];
+          t = fminf(t, unord_f32(pf_sh[j]));
+        }
+      }
     }
     __syncthreads();
 
@@ -441,30 +487,18 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     // compare against its row's threshold (and, for the cross list, its
     // camera), and passing entries are appended at once (an LDS atomic per
     // entry reserves the slot): after the first tiles only a few entries of
-    // a tile pass, so the cost is about two instructions per entry.  An
-    // entry that finds its buffer full is marked in the lane's lost mask;
-    // then the full buffers are compacted (lower thresholds) and only the
-    // lost entries are screened again, until none is left.
+    // a tile pass, so the cost is about two instructions per entry.  With
+    // 128-row tiles an entry that finds its buffer full is marked in the
+    // lane's lost mask; then the full buffers are compacted (lower
+    // thresholds) and only the lost entries are screened again, until none
+    // is left.  256-row tiles keep room for a whole tile instead (below).
     {
       int lc0 = wc + 4 * half;
       asm volatile("" : "+v"(lc0));
       const uint32_t cbase = (uint32_t)(ct0 - a.c0);
-      if (a.exclude_self && ct0 < row0 + BM && ct0 + BN > row0) {
-        // a tile holding rows' own columns: their similarities become
-        // -inf, i.e. an infinite key that no threshold admits
+      uint64_t lost[RBW][NL];
 #pragma unroll
-        for (int rb2 = 0; rb2 < 2; ++rb2) {
-          const int selfc = (int)(row0 + wr + 32 * rb2 + l32 - ct0);
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-              if (lc0 + 32 * cb + 8 * (i >> 2) + (i & 3) == selfc) acc[cb][rb2][i] = -INFINITY;
-        }
-      }
-      uint64_t lost[2][NL];
-#pragma unroll
-      for (int rb2 = 0; rb2 < 2; ++rb2) {
+      for (int rb2 = 0; rb2 < RBW; ++rb2) {
         const int lr = wr + 32 * rb2 + l32;
         // thresholds clamped to the largest finite float: ineligible entries
         // (padding columns, the row itself) carry an infinite key and are
@@ -474,6 +508,11 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         const float t1 = NL > 1 ? fminf(row_thr[NL - 1][lr], 3.40282347e38f) : -INFINITY;
         const float rs = row_sc[lr];
         const int rc = row_cam[lr];
+        // the row's own column in this tile, if it is left out (its key is
+        // the smallest of the row, so its block always reaches the
+        // per-entry test below)
+        const int64_t selfc64 = row0 + lr - ct0;
+        const int selfc = (a.exclude_self && selfc64 >= 0 && selfc64 < BN) ? (int)selfc64 : -1;
         uint64_t* buf0 = a.cand + (((rrel0 + lr) * NL) * (int64_t)a.S + cs) * a.C;
         uint64_t* buf1 = a.cand + (((rrel0 + lr) * NL + NL - 1) * (int64_t)a.S + cs) * a.C;
 #pragma unroll
@@ -494,6 +533,9 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
           }
           float keys[16];
           float kmin = INFINITY;
+          // the block's accumulators are read here and not earlier (an
+          // early copy of all of them would not fit in the registers)
+          asm volatile("" : "+a"(acc[cb][rb2]));
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             float sv = acc[cb][rb2][i];
@@ -514,24 +556,45 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
             const float key = keys[i];
             const int lc = lc0 + 32 * cb + 8 * (i >> 2) + (i & 3);
             const uint64_t bit = 1ull << (cb * 16 + i);
-            if (key <= t0 && !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
+            if (key <= t0 && lc != selfc && !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
               const int pos = atomicAdd(&row_cnt[0][lr], 1);
               if (pos < a.C) buf0[pos] = pack_cand(key, cbase + (uint32_t)lc);
-              else lost[rb2][0] |= bit;
+              else if constexpr (!ROOM) lost[rb2][0] |= bit;
             }
-            if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1 &&
+            if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1 && lc != selfc &&
                 !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
               const int pos = atomicAdd(&row_cnt[NL - 1][lr], 1);
               if (pos < a.C) buf1[pos] = pack_cand(key, cbase + (uint32_t)lc);
-              else lost[rb2][NL - 1] |= bit;
+              else if constexpr (!ROOM) lost[rb2][NL - 1] |= bit;
             }
           }
         }
       }
+      if constexpr (ROOM) {
+        // Room scheme: every buffer entered this tile with at least BN free
+        // slots (a row gets at most BN entries per list per tile), so no
+        // entry was lost.  Buffers past C - BN entries are compacted for the
+        // next tile, and at the first tile every buffer with k entries, to
+        // set its threshold; the next epilogue's barrier orders this before
+        // its admissions.
+        __syncthreads();
+        for (int q = wave; q < NL * BM; q += NT / 64) {
+          const int L = q / BM, lr = q - L * BM;
+          const int kk = L == 0 ? a.k0 : a.k1;
+          const int n = row_cnt[L][lr];
+          if (kk > 0 && (n > a.C - BN || (tile == 0 && n >= kk))) {
+            dirty = true;
+            uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
+            compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, kk, row_twoE[lr], BN);
+            if (a.thr_shared && lane == 0)
+              atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
+          }
+        }
+      } else
       for (int it = 0;; ++it) {
         bool left = false;
 #pragma unroll
-        for (int rb2 = 0; rb2 < 2; ++rb2)
+        for (int rb2 = 0; rb2 < RBW; ++rb2)
 #pragma unroll
           for (int L = 0; L < NL; ++L) left |= lost[rb2][L] != 0ull;
         if (__any(left) && lane == 0) any_flag[it & 1] = 1;
@@ -545,7 +608,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
           const int L = q / BM, lr = q - L * BM;
           if (row_cnt[L][lr] >= a.C) {
             uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
-            compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr]);
+            compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, L == 0 ? a.k0 : a.k1, row_twoE[lr], 16);
             if (a.thr_shared && lane == 0)
               atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
           }
@@ -553,7 +616,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         __syncthreads();
         // the lost entries against the lowered thresholds
 #pragma unroll
-        for (int rb2 = 0; rb2 < 2; ++rb2) {
+        for (int rb2 = 0; rb2 < RBW; ++rb2) {
           const int lr = wr + 32 * rb2 + l32;
           const float rs = row_sc[lr];
 #pragma unroll
@@ -589,7 +652,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         }
       }
     }
-    if (tile == 0) {
+    if (!ROOM && tile == 0) {
       // set every row's threshold from its first tile instead of waiting
       // for its buffer to fill
       dirty = true;
@@ -598,7 +661,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         const int kk = L == 0 ? a.k0 : a.k1;
         if (kk > 0 && row_cnt[L][lr] >= kk) {
           uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
-          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, kk, row_twoE[lr]);
+          compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, kk, row_twoE[lr], 16);
           if (a.thr_shared && lane == 0)
             atomicMin(&a.thr_shared[(rrel0 + lr) * NL + L], ord_f32(row_thr[L][lr]));
         }
@@ -620,35 +683,41 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   }  // pieces
 }
 
-template <int PREC, int NL>
-static void launch_prec_nl(const SimArgs& a, hipStream_t st) {
+template <int PREC, int NL, int E, int BMT>
+static void launch_one(const SimArgs& a, hipStream_t st) {
   const dim3 grid(a.balanced ? a.grid : sim_topk_grid(a.RB, a.S)), block(NT);
-  if (a.C <= 64) {
-    auto k = sim_topk_kernel<PREC, NL, 1>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
-    hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
-  } else if (a.C <= 128) {
-    auto k = sim_topk_kernel<PREC, NL, 2>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
-    hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
-  } else if (a.C <= 256) {
-    auto k = sim_topk_kernel<PREC, NL, 4>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
-    hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
-  } else {
-    auto k = sim_topk_kernel<PREC, NL, 8>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, SMEM);
-    hipLaunchKernelGGL(k, grid, block, SMEM, st, a);
-  }
+  auto k = sim_topk_kernel<PREC, NL, E, BMT>;
+  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, Tile<BMT>::SMEM);
+  hipLaunchKernelGGL(k, grid, block, Tile<BMT>::SMEM, st, a);
 }
 
+template <int PREC, int NL, int BMT>
+static void launch_prec_nl(const SimArgs& a, hipStream_t st) {
+  if (a.C <= 64) launch_one<PREC, NL, 1, BMT>(a, st);
+  else if (a.C <= 128) launch_one<PREC, NL, 2, BMT>(a, st);
+  else if (a.C <= 256) launch_one<PREC, NL, 4, BMT>(a, st);
+  else launch_one<PREC, NL, 8, BMT>(a, st);
+}
+
+template <int PREC, int BMT>
+static void launch_prec(int nl, const SimArgs& a, hipStream_t st) {
+  if (nl == 1) launch_prec_nl<PREC, 1, BMT>(a, st);
+  else launch_prec_nl<PREC, 2, BMT>(a, st);
+}
+
+// 256-row tiles exist for float32 and BF16 screening of one list (the FP8
+// fragments and a second list's state do not fit beside the 256
+// accumulators of a 128 x 128 wave tile).
+int sim_topk_large_tile(int prec, int nl) { return prec != GCR_PREC_FP8 && nl == 1; }
+
 void launch_sim_topk(int prec, int nl, const SimArgs& a, hipStream_t st) {
+  const bool big = a.bm == 256 && sim_topk_large_tile(prec, nl);
   if (prec == GCR_PREC_FP32) {
-    if (nl == 1) launch_prec_nl<GCR_PREC_FP32, 1>(a, st); else launch_prec_nl<GCR_PREC_FP32, 2>(a, st);
+    if (big) launch_prec_nl<GCR_PREC_FP32, 1, 256>(a, st); else launch_prec<GCR_PREC_FP32, 128>(nl, a, st);
   } else if (prec == GCR_PREC_BF16) {
-    if (nl == 1) launch_prec_nl<GCR_PREC_BF16, 1>(a, st); else launch_prec_nl<GCR_PREC_BF16, 2>(a, st);
+    if (big) launch_prec_nl<GCR_PREC_BF16, 1, 256>(a, st); else launch_prec<GCR_PREC_BF16, 128>(nl, a, st);
   } else {
-    if (nl == 1) launch_prec_nl<GCR_PREC_FP8, 1>(a, st); else launch_prec_nl<GCR_PREC_FP8, 2>(a, st);
+    launch_prec<GCR_PREC_FP8, 128>(nl, a, st);
   }
 }
 

@@ -193,7 +193,7 @@ class Context:
         self._ok(self.lib.gcr_get_stats(self.h, C.byref(s)), "gcr_get_stats")
         return dict(knn_rows=s.knn_rows, knn_candidates=s.knn_candidates,
                     knn_fallback_rows=s.knn_fallback_rows, splits=s.splits,
-                    knn_exhaustive_rows=s.knn_exhaustive_rows)
+                    knn_exhaustive_rows=s.knn_exhaustive_rows, tile_rows=s.tile_rows)
 
     def set_timing(self, on: bool):
         self._ok(self.lib.gcr_set_timing(self.h, int(on)), "gcr_set_timing")

@@ -214,3 +214,49 @@ def closed_neighbourhood_round(X, ids, k, gamma, rows):
         idx[m], dist[m] = li, ld
     Y, _, _ = O.sparse_round_from_lists(X, O.Params(k=k, gamma=gamma, rounds=1), idx, dist, rows=rows)
     return Y, idx, sorted(lists)
+
+
+def chain_compare(ctx, w, p, op, cam_d, what, dense_last=True):
+    """GPU features of every round t = 1..T (each a whole re-ranking with t
+    rounds, its last graph kept) against the oracle chain.  Where the
+    library's neighbour set of a row differs from the oracle's, the row must
+    sit in the oracle's tie band (or next to a row already set aside), and
+    the rows within two hops of it are set aside from then on: a legitimate
+    tie choice changes the weights there.  Every other row is compared.
+    Returns (oracle chain, rows compared at round T, last GPU output)."""
+    import torch
+
+    def host(t):
+        torch.cuda.synchronize()
+        return t.cpu().numpy()
+
+    n = w.X.shape[0]
+    cross = cam_d is not None and op.alpha < 1.0
+    chain = oracle_chain(w.X, op, w.cams if cam_d is not None else None)
+    excl = np.zeros(0, dtype=np.int64)
+    Xd = torch.from_numpy(np.ascontiguousarray(w.X)).to("cuda", torch.float32)
+    out = None
+    for t in range(1, op.rounds + 1):
+        pt = type(p)(**{**p.__dict__, "rounds": t})
+        g = ctx.new_graph(n, pt, has_cross=cross)
+        out = ctx.rerank(Xd, w.nq, pt, cam_d, dense=dense_last and t == op.rounds, keep_features=True,
+                         last_graph=g)
+        ch = chain[t - 1]
+        gi = host(g.field("idx"))
+        diff = np.array([r for r in range(n) if set(gi[r].tolist()) != set(ch["idx"][r].tolist())], dtype=np.int64)
+        lists = [ch["idx"]]
+        if cross:
+            gc = host(g.field("cr_idx"))
+            dc = [r for r in range(n) if set(gc[r].tolist()) != set(ch["cr_idx"][r].tolist())]
+            diff = np.union1d(diff, np.array(dc, dtype=np.int64))
+            lists.append(ch["cr_idx"])
+        allowed = np.union1d(ch["ties"], expand_hops(excl, lists, 1) if len(excl) else excl)
+        stray = np.setdiff1d(diff, allowed)
+        assert len(stray) == 0, f"{what} round {t}: lists differ outside the tie band at rows {stray[:8]}"
+        excl = expand_hops(np.union1d(excl, diff), lists, 2) if len(diff) or len(excl) else excl
+        assert len(excl) <= 0.02 * n, f"{what}: {len(excl)} rows set aside by round {t}"
+        keep = np.setdiff1d(np.arange(n), excl)
+        check_features(host(out["X"])[keep], ch["X"][keep], what=f"{what} round {t}")
+        print(f"{what}: round {t}: {len(diff)} tie-band list differences, features equal on {len(keep)} of {n}",
+              flush=True)
+    return chain, np.setdiff1d(np.arange(n), excl), out

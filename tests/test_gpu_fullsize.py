@@ -13,8 +13,8 @@ from oracle import gcr_oracle as O
 from paper_2306_08792_amd import datagen
 from paper_2306_08792_amd.gcr import BF16, FP8, FP32, Context, Params
 
-from parity import (check_distances, check_features, check_knn_rows, closed_neighbourhood_round, expand_hops,
-                    oracle_chain)
+from parity import (chain_compare, check_distances, check_features, check_knn_rows, closed_neighbourhood_round,
+                    expand_hops, oracle_chain)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,46 +32,6 @@ def sample(n, m, seed):
     return np.sort(np.random.default_rng(seed).choice(n, size=m, replace=False))
 
 
-def _chain_compare(ctx, w, p, op, cam_d, what, dense_last=True):
-    """GPU features of every round t = 1..T (each a whole re-ranking with t
-    rounds, its last graph kept) against the oracle chain.  Where the
-    library's neighbour set of a row differs from the oracle's, the row must
-    sit in the oracle's tie band (or next to a row already set aside), and
-    the rows within two hops of it are set aside from then on: a legitimate
-    tie choice changes the weights there.  Every other row is compared.
-    Returns (oracle chain, rows compared at round T, last GPU output)."""
-    n = w.X.shape[0]
-    cross = cam_d is not None and op.alpha < 1.0
-    chain = oracle_chain(w.X, op, w.cams if cam_d is not None else None)
-    excl = np.zeros(0, dtype=np.int64)
-    Xd = dev(w.X)
-    out = None
-    for t in range(1, op.rounds + 1):
-        pt = Params(**{**p.__dict__, "rounds": t})
-        g = ctx.new_graph(n, pt, has_cross=cross)
-        out = ctx.rerank(Xd, w.nq, pt, cam_d, dense=dense_last and t == op.rounds, keep_features=True,
-                         last_graph=g)
-        ch = chain[t - 1]
-        gi = host(g.field("idx"))
-        diff = np.array([r for r in range(n) if set(gi[r].tolist()) != set(ch["idx"][r].tolist())], dtype=np.int64)
-        lists = [ch["idx"]]
-        if cross:
-            gc = host(g.field("cr_idx"))
-            dc = [r for r in range(n) if set(gc[r].tolist()) != set(ch["cr_idx"][r].tolist())]
-            diff = np.union1d(diff, np.array(dc, dtype=np.int64))
-            lists.append(ch["cr_idx"])
-        allowed = np.union1d(ch["ties"], expand_hops(excl, lists, 1) if len(excl) else excl)
-        stray = np.setdiff1d(diff, allowed)
-        assert len(stray) == 0, f"{what} round {t}: lists differ outside the tie band at rows {stray[:8]}"
-        excl = expand_hops(np.union1d(excl, diff), lists, 2) if len(diff) or len(excl) else excl
-        assert len(excl) <= 0.02 * n, f"{what}: {len(excl)} rows set aside by round {t}"
-        keep = np.setdiff1d(np.arange(n), excl)
-        check_features(host(out["X"])[keep], ch["X"][keep], what=f"{what} round {t}")
-        print(f"{what}: round {t}: {len(diff)} tie-band list differences, features equal on {len(keep)} of {n}",
-              flush=True)
-    return chain, np.setdiff1d(np.arange(n), excl), out
-
-
 def test_cross_camera_full_size():
     """3,368 + 15,913 x 2,048, 6 cameras, k = 20 (both lists), alpha = 0.5,
     L = 3, BF16 screening: the features of all three rounds on every row
@@ -84,7 +44,7 @@ def test_cross_camera_full_size():
     cam = dev(w.cams, torch.int32)
     p = Params(k=20, gamma=0.2, rounds=3, alpha=0.5, precision=BF16, rebuild_each_round=True)
     op = O.Params(k=20, gamma=0.2, rounds=3, alpha=0.5)
-    chain, keep, out = _chain_compare(ctx, w, p, op, cam, "cross-camera")
+    chain, keep, out = chain_compare(ctx, w, p, op, cam, "cross-camera")
     Xn = O.row_normalize(w.X)
     idx, dist, cidx, cdist = ctx.knn(dev(Xn.astype(np.float32)), p, cam, cross=True)
     rows = sample(n, 2000, 1)
@@ -132,7 +92,7 @@ def test_video_full_size():
     check_knn_rows(host(idx)[rows], host(dist)[rows], Wo.astype(np.float32), rows, 15)
     # the rounds on the oracle's profiles (float32), both sides from the same input
     wv = datagen.Workload("video_profiles", w.nq, w.ng, Wo.shape[1], Wo.astype(np.float32), w.ids, None, {})
-    _chain_compare(ctx, wv, p, O.Params(k=15, gamma=0.2, rounds=2), None, "video")
+    chain_compare(ctx, wv, p, O.Params(k=15, gamma=0.2, rounds=2), None, "video")
     ctx.close()
 
 
