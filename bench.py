@@ -66,25 +66,30 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_file(tag: str) -> str:
-    return os.path.join(ROOT, "profiles", f"sim_topk_{tag}_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_08792_amd", "csrc", f) for f in ("simtopk.hip", "common.h", "kernels.h")]
+KERNEL_SOURCES = {k: [os.path.join(ROOT, "paper_2306_08792_amd", "csrc", f) for f in v] for k, v in {
+    "sim_topk": ("simtopk.hip", "common.h", "kernels.h"),
+    "propagate": ("propagate.hip", "common.h", "kernels.h"),
+}.items()}
 
 
-def kernel_source_hash() -> str:
+def traffic_file(kernel: str, tag: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_{tag}_traffic.md")
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(tag: str):
-    """HBM bytes per similarity/top-k launch from the committed counter
-    summary of workload `tag`, or None when the summary is missing or was
-    taken on other kernel sources."""
+def recorded_traffic(kernel: str, tag: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    of workload `tag`, or None when the summary is missing or was taken on
+    other kernel sources."""
     try:
-        lines = open(traffic_file(tag)).read().splitlines()
+        lines = open(traffic_file(kernel, tag)).read().splitlines()
     except OSError:
         return None
     kv = {}
@@ -92,7 +97,7 @@ def recorded_traffic(tag: str):
         if ln.startswith("- ") and ": " in ln:
             k, v = ln[2:].split(": ", 1)
             kv[k.strip()] = v.strip().strip("`")
-    if kv.get("source_sha256") != kernel_source_hash():
+    if kv.get("source_sha256") != kernel_source_hash(kernel):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -382,11 +387,12 @@ def large_retrieval_bench(args):
         "precision_modes_same_gpu": res_modes,
         "raw_mode_errors_vs_fp64_oracle": raw,
         "roofline": {"bound": "mfma", "kernel": "sim_topk", "achieved": round(achieved, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic("large_retrieval"),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic("sim_topk", "large_retrieval"),
                      "avg_launch_ms": round(sim_avg, 4), "launches": int(sim_n), "flops_per_launch": flops},
         "roofline_propagate": {"bound": "hbm", "kernel": "propagate", "achieved": round(pbytes / (pr_avg * 1e-3) / 1e9, 1),
                                "peak": 8000.0, "unit": "GB/s",
-                               "frac": round(pbytes / (pr_avg * 1e-3) / 1e9 / 8000.0, 4), "traffic": None,
+                               "frac": round(pbytes / (pr_avg * 1e-3) / 1e9 / 8000.0, 4),
+                               "traffic": recorded_traffic("propagate", "large_retrieval"),
                                "avg_launch_ms": round(pr_avg, 4), "launches": int(pr_n),
                                "compulsory_bytes_per_launch": pbytes},
         "stage_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in tim.items()},
@@ -909,7 +915,7 @@ def main():
         "top_k_agreement": agreement,
         "fp32_screening_same_gpu": fp32,
         "roofline": {"bound": "mfma", "kernel": "sim_topk", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic("cross_camera"),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": recorded_traffic("sim_topk", "cross_camera"),
                      "avg_launch_ms": round(sim_avg, 4), "launches": int(sim_n),
                      "flops_per_launch": flops},
         "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},

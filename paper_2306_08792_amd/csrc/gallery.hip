@@ -1,12 +1,17 @@
 // Maintenance of a resident gallery's kNN lists under inserts and removals.
 //
-// The lists stay exactly the lists a fresh build on the current gallery
-// would produce: k nearest other items by exact squared distance, ordered by
+// The lists stay the lists a fresh build on the current gallery would
+// produce: k nearest other items by exact squared distance, ordered by
 // (distance, index).
 //   Insert (rows appended at the end): an old row's new list is the merge of
-//     its list with its nearest items among the appended rows; equal
-//     distances keep the smaller index first, and every appended index is
-//     larger than every old one.
+//     its list with its nearest items among the appended rows.  Entries carry
+//     float32 distances; where an old and an appended entry round to the same
+//     float32 value their float64 distances decide, recomputed from the
+//     features, and only exactly equal float64 values fall back to the index
+//     (every appended index is larger than every old one).  A fresh build
+//     orders by float64 distances summed in another order, so the two can
+//     differ only for items whose distances agree to the rounding of that
+//     sum (about 2^-42 relative at d = 2048).
 //   Removal (gallery compacted in place, surviving items keep their relative
 //     order): relabelling is monotone, so every list keeps its order; a list
 //     that contained a removed item is searched again.
@@ -16,9 +21,21 @@ namespace gcr {
 
 namespace {
 
-// (distance, index) order; invalid entries (index < 0) sort last
-__device__ __forceinline__ bool before(float da, int32_t ia, float db, int32_t ib) {
-  return da < db || (da == db && ia < ib);
+// Exact squared distance between gallery rows r and j (float64 sum).
+__device__ double exact_d2(const float* __restrict__ X, int d, int64_t r, int64_t j) {
+  double s = 0.0;
+  for (int e = 0; e < d; ++e) s = sqdiff_acc(s, X[r * d + e], X[j * d + e]);
+  return s;
+}
+
+// Row r's (distance, index) order between an old entry a and an appended
+// entry b, with float32 ties decided in float64.
+__device__ __forceinline__ bool before(const float* __restrict__ X, int d, int64_t r, float da, int32_t ia,
+                                       float db, int32_t ib) {
+  if (da != db) return da < db;
+  const double ea = exact_d2(X, d, r, ia), eb = exact_d2(X, d, r, ib);
+  if (ea != eb) return ea < eb;
+  return ia < ib;
 }
 
 // Row r's list (k entries) merged with its m nearest appended items (column
@@ -28,7 +45,7 @@ __device__ __forceinline__ bool before(float da, int32_t ia, float db, int32_t i
 // overwrites an old entry that is still to be read (p >= the old read index).
 __global__ void merge_appended_kernel(int64_t rows, int k, int32_t* __restrict__ idx, float* __restrict__ dist, int m,
                                       const int32_t* __restrict__ nidx, const float* __restrict__ ndist,
-                                      int32_t col_offset) {
+                                      int32_t col_offset, const float* __restrict__ X, int d) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   int32_t* li = idx + r * k;
@@ -40,7 +57,7 @@ __global__ void merge_appended_kernel(int64_t rows, int k, int32_t* __restrict__
     const bool va = x < k && li[x] >= 0;
     const bool vb = y < m && ni[y] >= 0;
     if (va && vb) {
-      if (before(ld[x], li[x], nd[y], ni[y] + col_offset)) ++x;
+      if (before(X, d, r, ld[x], li[x], nd[y], ni[y] + col_offset)) ++x;
       else ++y;
     } else if (va) {
       ++x;
@@ -54,7 +71,7 @@ __global__ void merge_appended_kernel(int64_t rows, int k, int32_t* __restrict__
   int xi = x - 1, yi = y - 1;
   for (int p = nv - 1; p >= 0; --p) {
     bool take_old;
-    if (xi >= 0 && yi >= 0) take_old = !before(ld[xi], li[xi], nd[yi], ni[yi] + col_offset);
+    if (xi >= 0 && yi >= 0) take_old = !before(X, d, r, ld[xi], li[xi], nd[yi], ni[yi] + col_offset);
     else take_old = xi >= 0;
     if (take_old) {
       li[p] = li[xi];
@@ -138,10 +155,10 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
 void launch_merge_appended(int64_t rows, int k, int32_t* idx, float* dist, int m, const int32_t* nidx,
-                           const float* ndist, int32_t col_offset, hipStream_t st) {
+                           const float* ndist, int32_t col_offset, const float* X, int d, hipStream_t st) {
   if (rows <= 0 || k <= 0) return;
   hipLaunchKernelGGL(merge_appended_kernel, dim3(nblk(rows, 64)), dim3(64), 0, st, rows, k, idx, dist, m, nidx, ndist,
-                     col_offset);
+                     col_offset, X, d);
 }
 
 void launch_relabel_lists(int64_t rows_old, int k, const int32_t* new_of_old, const int32_t* idx_old,

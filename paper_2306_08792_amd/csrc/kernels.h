@@ -252,9 +252,11 @@ void launch_serve_merge(int b, int K, const int32_t* ia, const float* da, const 
                         const int32_t* list, int32_t* oi, float* od, hipStream_t st);
 // Gallery list maintenance (exact under inserts and removals).
 // Merge each of `rows` lists [rows, k] with its m nearest appended items
-// (indices + col_offset), keeping the k smallest by (distance, index).
+// (indices + col_offset), keeping the k smallest by (distance, index);
+// float32 ties between the two sides are decided by float64 distances from
+// the gallery features X [*, d].
 void launch_merge_appended(int64_t rows, int k, int32_t* idx, float* dist, int m, const int32_t* nidx,
-                           const float* ndist, int32_t col_offset, hipStream_t st);
+                           const float* ndist, int32_t col_offset, const float* X, int d, hipStream_t st);
 // Lists of the surviving rows renumbered by new_of_old (-1: removed) into
 // distinct buffers; rows that lost a neighbour are appended to repair.
 void launch_relabel_lists(int64_t rows_old, int k, const int32_t* new_of_old, const int32_t* idx_old,

@@ -968,8 +968,9 @@ void launch_merge_splits(const MergeArgs& m, hipStream_t st) {
 // One wave per (row, list).  If the previous list of the row has k valid
 // members j, the k-th smallest exact key of the row is at most
 // U = max_j ||x_i - x_j||^2 - n2_i (up to the float32 error of n2_i), so the
-// final screened k-th key is <= U + E and the screening never needs to keep
-// keys above U + 3E, E being the row's screening margin.
+// final screened k-th key tau is <= U + E and the refine's cut tau + 2E is
+// <= U + 3E, E being the row's screening margin: the screening never needs
+// to keep keys above U + 3E.
 template <int V>
 __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __restrict__ X, int d, int64_t n,
                                                               const int32_t* __restrict__ idx0, int k0,
@@ -1037,8 +1038,10 @@ __global__ __launch_bounds__(256) void seed_thresholds_kernel(const float* __res
 // The same bound from the BF16 screening operand (half the bytes of the
 // float32 rows): every member's screened key n2_j - 2 x~_i.x~_j lies within
 // E of its exact key (screen_margin holds for any float32 summation order),
-// so the largest member key is at most the largest screened key + E, and a
-// true neighbour's screened key in the sweep is at most that + E again.
+// so the k-th exact key is at most the largest screened member key kmax + E,
+// the sweep's final k-th screened key tau at most kmax + 2E, and the refine's
+// cut tau + 2E at most kmax + 4E: seeding there keeps every split's recorded
+// threshold at or above the cut, so a seeded row never needs the re-sweep.
 // NV: 16-byte operand parts per lane (ld = 1024 NV bytes).
 template <int NV>
 __global__ __launch_bounds__(256) void seed_thresholds_bf16_kernel(const uint8_t* __restrict__ Xs, int64_t ld,
@@ -1106,7 +1109,7 @@ __global__ __launch_bounds__(256) void seed_thresholds_bf16_kernel(const uint8_t
   if (kk > 0 && valid == kk) {
     const float mx = *maxn2, n2r = n2[row];
     const float E = screen_margin(n2r, rn[row], mx, maxn2[1], eps_s, eps_n);
-    res = kmax + 3.0f * E + 4e-7f * (fabsf(kmax) + n2r + 1.0f);
+    res = kmax + 4.0f * E + 4e-7f * (fabsf(kmax) + n2r + 1.0f);
   }
   out[row * nl + L] = res;
 }

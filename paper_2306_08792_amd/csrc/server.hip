@@ -802,7 +802,7 @@ std::string insert_rows(gcr_server* s, const float* rows, int32_t m) {
   const int km = (int)std::min<int64_t>(k, m);
   e = gallery_knn(s, G1, 0, G0, G0, G1, 0, km, s->tmp_idx, s->tmp_dist);
   if (!e.empty()) return e;
-  launch_merge_appended(G0, k, s->g.idx, s->g.dist, km, s->tmp_idx, s->tmp_dist, (int32_t)G0, st);
+  launch_merge_appended(G0, k, s->g.idx, s->g.dist, km, s->tmp_idx, s->tmp_dist, (int32_t)G0, s->X[0], d, st);
   SRV_HIP(hipGetLastError());
   s->G = G1;
   return refresh_gallery(s);

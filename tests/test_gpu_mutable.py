@@ -183,3 +183,38 @@ def test_zero_rounds_and_near_empty_gallery(ctx):
         assert np.all(gi[:, 2:] == -1)
     finally:
         srv.close()
+
+
+def test_insert_float32_tie_decided_in_float64(ctx):
+    """An appended item whose distance to a row rounds to the same float32
+    value as the row's old neighbour but is smaller in float64 (1 against
+    1 + 2^-30) replaces it, as in a fresh build (k = 1)."""
+    print("mutable gallery: float32 tie", flush=True)
+    d = 16
+    rng = np.random.default_rng(9)
+    far = (10.0 * rng.standard_normal((38, d))).astype(np.float32)
+    r = np.zeros(d, np.float32)
+    r[0] = 1.0
+    a = r.copy()
+    a[1], a[2] = 1.0, 2.0 ** -15  # |r - a|^2 = 1 + 2^-30
+    b = r.copy()
+    b[3] = 1.0  # |r - b|^2 = 1
+    assert np.float32(1.0 + 2.0 ** -30) == np.float32(1.0)
+    G = np.vstack([r, a, far]).astype(np.float32)
+    q = r.copy()
+    q[4] = 0.01
+    reqs = [q[None, :], np.vstack([q, a + 0.01, b + 0.01]).astype(np.float32)]
+    p = Params(k=1, rounds=1, gamma=0.2, topk_out=3, precision=FP32, rebuild_each_round=False)
+    srv = Server(ctx, torch.from_numpy(G).cuda(), p, lanes=1, max_batch=8, max_recomputed=64, gallery_capacity=48)
+    try:
+        ids = srv.insert(b[None, :])
+        assert np.array_equal(ids, [40])
+        live = srv.ids()
+        fresh = Server(ctx, torch.from_numpy(np.vstack([G, b[None, :]])).cuda(), p, lanes=1, max_batch=8,
+                       max_recomputed=64)
+        try:
+            same_answers(srv, fresh, live, reqs)
+        finally:
+            fresh.close()
+    finally:
+        srv.close()
