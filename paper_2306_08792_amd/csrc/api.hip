@@ -1025,7 +1025,7 @@ static int profile_ksplit(int64_t nf) { return (int)std::min<int64_t>(64, std::m
 // member and frame row lists, split-K Gram partials and the Gram, and the
 // Chebyshev iterates of the largest group (maxm members).
 struct ProfileLayout {
-  float *mu_c, *mu, *part, *G, *B, *Wt, *P, *R, *tr;
+  float *mu_c, *mu, *part, *G, *B, *Wt, *P, *R, *tr, *gm;
   int32_t *dm, *dr;
 };
 static void layout_profile(Arena& ar, ProfileLayout& L, int64_t nt, int64_t nf, int64_t maxm, int d, int mode,
@@ -1041,6 +1041,7 @@ static void layout_profile(Arena& ar, ProfileLayout& L, int64_t nt, int64_t nf, 
   L.P = ar.take<float>((size_t)maxm * d);
   L.R = ar.take<float>((size_t)maxm * d);
   L.tr = ar.take<float>(64);
+  L.gm = mode == 0 ? ar.take<float>((size_t)group_mean_scratch_floats(d)) : nullptr;
 }
 
 size_t gcr_profile_workspace_size(int32_t nt, int64_t nf, int32_t d, int32_t mode) {
@@ -1156,7 +1157,7 @@ gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* o
     const int64_t nr = rstart[q + 1] - rstart[q];
     const int32_t* mem = dm + mstart[q];
     const int32_t* rw = dr + rstart[q];
-    launch_group_mean(mu_c, offsets, mem, nm, d, mu, st);
+    launch_group_mean(mu_c, offsets, mem, nm, d, nr, L.gm, mu, st);
     const float shift = lambda * (float)nr;
     const int ks = (int)std::min<int64_t>(ksplit, std::max<int64_t>(1, nr / 32));
     launch_gram(frames, rw, nr, d, part, ks, G, shift, st);

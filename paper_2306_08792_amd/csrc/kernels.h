@@ -208,8 +208,10 @@ void launch_dense_dist(const uint8_t* Xs, int64_t ld_bytes, int kchunks, const f
 // ---- pvg.hip : tracklet profile vectors
 void launch_segment_means(const float* frames, const int32_t* offsets, int nt, int d,
                           float* mu_c, hipStream_t st);
+// scratch: group_mean_scratch_floats(d) floats
 void launch_group_mean(const float* mu_c, const int32_t* offsets, const int32_t* members,
-                       int nm, int d, float* mu, hipStream_t st);
+                       int nm, int d, int64_t nframes, float* scratch, float* mu, hipStream_t st);
+int group_mean_scratch_floats(int d);
 void launch_gram(const float* frames, const int32_t* rows, int64_t nrows, int d, float* partial,
                  int ksplit, float* G, float shift, hipStream_t st);
 void launch_gemm_nn_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,

@@ -410,6 +410,19 @@ def test_profile_vectors(ctx, mode, groups):
     check_features(host(W), Wo, what="profiles")
 
 
+@pytest.mark.parametrize("d", [3, 130, 132, 260])
+def test_profile_vectors_widths(ctx, d):
+    """Feature widths off the 16-byte path (3, 130: the scalar Gram and GEMM)
+    and on it with a ragged last 128-column tile (132, 260), three groups."""
+    print(f"pvg d={d}", flush=True)
+    w = datagen.video_tracklets(seed=6, nq=20, ng=60, d=d, n_ids=20)
+    nt = len(w.offsets) - 1
+    grp = (np.arange(nt) % 3).astype(np.int32)
+    W = ctx.profile_vectors(dev(w.frames), torch.from_numpy(w.offsets), torch.from_numpy(grp), mode="pvg", lam=10.0)
+    Wo = O.profile_vectors(w.frames, w.offsets, grp, lam=10.0, mode="pvg")
+    check_features(host(W), Wo, what="profiles")
+
+
 def test_profile_vectors_small_lambda(ctx):
     w = datagen.video_tracklets(seed=4, nq=10, ng=30, d=64, n_ids=10)
     W = ctx.profile_vectors(dev(w.frames), torch.from_numpy(w.offsets), None, mode="pvg", lam=0.05)
