@@ -276,6 +276,24 @@ def test_propagate_one_round(ctx, d):
     check_features(host(Y), Yo)
 
 
+@pytest.mark.parametrize("d,k", [(256, 20), (512, 20), (512, 3)])
+def test_propagate_larger_graphs(ctx, d, k):
+    """One round on 6,001 clustered nodes (many workgroups, a ragged last
+    one, reverse lists of every length) against the oracle's sparse round,
+    and bitwise the same on a second run."""
+    print(f"propagate n=6001 d={d} k={k}", flush=True)
+    n = 6001
+    X = case(n, d, 40 + d + k)
+    p = Params(k=k, gamma=0.2)
+    Xd = dev(X)
+    g = ctx.build_graph(Xd, p)
+    Y = ctx.propagate(g, Xd)
+    Yo, _, _ = oracle_round_from_lists(X, O.Params(k=k, gamma=0.2), host(g.field("idx")))
+    check_features(host(Y), Yo)
+    Y2 = ctx.propagate(g, Xd)
+    assert np.array_equal(host(Y).view(np.uint32), host(Y2).view(np.uint32))
+
+
 def test_propagate_rejects_in_place(ctx):
     X = dev(case(40, 8, 1))
     g = ctx.build_graph(X, Params(k=3))
