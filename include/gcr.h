@@ -340,6 +340,9 @@ gcr_status gcr_rerank_local(gcr_ctx* ctx, const float* X, int64_t nq,
  *   W_out: float32 [nt, d], each row L2-normalised.
  * Host-side reads of offsets/group: offsets_host and group_host are HOST
  * copies of the same arrays (the solver plans per-group work on the host).
+ * Mode 0 synchronises the stream once per group, to read the trace of the
+ * group's Gram (it fixes the Chebyshev iteration count); the last group's
+ * solve is left running on the stream.  Mode 1 does not synchronise.
  * Errors: INVALID, NOMEM, HIP. */
 gcr_status gcr_profile_vectors(gcr_ctx* ctx, const float* frames,
                                const int32_t* offsets, const int32_t* group,

@@ -1148,7 +1148,6 @@ gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* o
   launch_segment_means(frames, offsets, nt, d, mu_c, st);
   if (mode == 1) {
     launch_normalize_rows(mu_c, W_out, nt, d, st);
-    HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, hipGetLastError());
     return GCR_OK;
   }
@@ -1162,12 +1161,10 @@ gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* o
     const int ks = (int)std::min<int64_t>(ksplit, std::max<int64_t>(1, nr / 32));
     launch_gram(frames, rw, nr, d, part, ks, G, shift, st);
     // spectrum bounds of M = F^T F + lambda n I: [lambda n, lambda n + tr(F^T F)]
-    std::vector<float> diag(d);
-    HIP_TRY(c, hipMemcpy2DAsync(diag.data(), sizeof(float), G, (size_t)(d + 1) * sizeof(float), sizeof(float), d,
-                                hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipStreamSynchronize(st));
+    launch_gram_trace(G, d, shift, (double*)L.tr, st);
     double trace = 0.0;
-    for (int e = 0; e < d; ++e) trace += (double)diag[e] - shift;
+    HIP_TRY(c, hipMemcpyAsync(&trace, L.tr, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
     trace = std::max(trace, 0.0) * 1.0001 + 1e-6 * shift;
     const double lmin = shift, lmax = shift + trace;
     const double dd = 0.5 * (lmax + lmin), cc = 0.5 * (lmax - lmin);
@@ -1200,7 +1197,8 @@ gcr_status gcr_profile_vectors(gcr_ctx* c, const float* frames, const int32_t* o
     launch_normalize_rows(Wt, Wt, nm, d, st);
     launch_scatter_profiles(Wt, mem, nm, d, W_out, st);
   }
-  HIP_TRY(c, hipStreamSynchronize(st));
+  // no synchronisation at the end: the host arrays were consumed by the
+  // copies above (complete at the first group's trace read)
   HIP_TRY(c, hipGetLastError());
   return GCR_OK;
 }

@@ -217,6 +217,8 @@ void launch_gram(const float* frames, const int32_t* rows, int64_t nrows, int d,
 void launch_gemm_nn_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,
                         int64_t ldc, int M, int N, int K, float alpha, float beta,
                         const float* Cin, int64_t ldcin, hipStream_t st);
+// out[0] = trace of the d x d Gram G minus d * shift (float64)
+void launch_gram_trace(const float* G, int d, float shift, double* out, hipStream_t st);
 void launch_build_rhs(const float* mu_c, const float* mu, const int32_t* members, int nm, int d,
                       float* B, hipStream_t st);
 void launch_scatter_profiles(const float* Wt, const int32_t* members, int nm, int d, float* W,

@@ -353,6 +353,19 @@ __global__ __launch_bounds__(PNT, 2) void mfma_f32_pipe_kernel(const float* __re
       }
 }
 
+// tr(F^T F) = sum over the diagonal of G minus the shift (one workgroup,
+// float64 sum)
+__global__ __launch_bounds__(256) void gram_trace_kernel(const float* __restrict__ G, int d, float shift,
+                                                         double* __restrict__ out) {
+  __shared__ double part[4];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < d; e += 256) s += (double)G[(int64_t)e * (d + 1)] - (double)shift;
+  s = wave_sum_f64(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = part[0] + part[1] + part[2] + part[3];
+}
+
 __global__ void build_rhs_kernel(const float* __restrict__ mu_c, const float* __restrict__ mu,
                                  const int32_t* __restrict__ members, int nm, int d, float* B) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -425,6 +438,9 @@ void launch_gemm_nn_f32(const float* A, int64_t lda, const float* B, int64_t ldb
   else
     hipLaunchKernelGGL(gemm_nn_f32_kernel, dim3(grid), dim3(MNT), 0, st, A, lda, B, ldb, Cm, ldc, M, N, K,
                        alpha, beta, Cin, ldcin);
+}
+void launch_gram_trace(const float* G, int d, float shift, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(gram_trace_kernel, dim3(1), dim3(256), 0, st, G, d, shift, out);
 }
 void launch_build_rhs(const float* mu_c, const float* mu, const int32_t* members, int nm, int d, float* B,
                       hipStream_t st) {
