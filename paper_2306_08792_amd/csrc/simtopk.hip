@@ -293,6 +293,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __shared__ const uint32_t* row_mk[BM];  // per-row column masks (serving batches)
   __shared__ uint32_t row_stp[BM];
   __shared__ int any_flag[2];
+  __shared__ int room_flag[2];  // a buffer passed C - BN in the tile of that parity (room scheme)
 
   // balanced mode: consecutive pieces (mostly the same row block) go to the
   // same XCD, so its L2 serves the row tile to both workgroups sweeping it
@@ -341,7 +342,10 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   __syncthreads();  // the previous piece is done with the shared state
   const int64_t row0 = a.r0 + (int64_t)rb * BM;
 
-  if (tid < 2) any_flag[tid] = 0;
+  if (tid < 2) {
+    any_flag[tid] = 0;
+    room_flag[tid] = 0;
+  }
   for (int t = tid; t < BM; t += NT) {
     const int64_t r = row0 + t;
     const bool rv = r < a.r1;
@@ -482,6 +486,9 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       }
     }
     __syncthreads();
+    // every wave read the flag of tile - 1 before this barrier; it is the
+    // flag the next tile sets
+    if (ROOM && tid == 0) room_flag[(tile + 1) & 1] = 0;
 
     // Admission.  Each entry is screened with one multiply-add and one
     // compare against its row's threshold (and, for the cross list, its
@@ -497,6 +504,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       asm volatile("" : "+v"(lc0));
       const uint32_t cbase = (uint32_t)(ct0 - a.c0);
       uint64_t lost[RBW][NL];
+      bool near_full = false;  // room scheme: an admission of this lane passed C - BN
 #pragma unroll
       for (int rb2 = 0; rb2 < RBW; ++rb2) {
         const int lr = wr + 32 * rb2 + l32;
@@ -560,12 +568,14 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
               const int pos = atomicAdd(&row_cnt[0][lr], 1);
               if (pos < a.C) buf0[pos] = pack_cand(key, cbase + (uint32_t)lc);
               else if constexpr (!ROOM) lost[rb2][0] |= bit;
+              if constexpr (ROOM) near_full |= pos >= a.C - BN;
             }
             if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1 && lc != selfc &&
                 !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
               const int pos = atomicAdd(&row_cnt[NL - 1][lr], 1);
               if (pos < a.C) buf1[pos] = pack_cand(key, cbase + (uint32_t)lc);
               else if constexpr (!ROOM) lost[rb2][NL - 1] |= bit;
+              if constexpr (ROOM) near_full |= pos >= a.C - BN;
             }
           }
         }
@@ -577,8 +587,12 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         // next tile, and at the first tile every buffer with k entries, to
         // set its threshold; the next epilogue's barrier orders this before
         // its admissions.
+        if (__any(near_full) && lane == 0) room_flag[tile & 1] = 1;
         __syncthreads();
-        for (int q = wave; q < NL * BM; q += NT / 64) {
+        // (rows are scanned only at the first tile and when an admission of
+        // this tile reached past C - BN)
+        const bool scan = tile == 0 || room_flag[tile & 1];
+        for (int q = wave; scan && q < NL * BM; q += NT / 64) {
           const int L = q / BM, lr = q - L * BM;
           const int kk = L == 0 ? a.k0 : a.k1;
           const int n = row_cnt[L][lr];
