@@ -59,6 +59,10 @@ struct Tile {
   static constexpr int RBYTES = BM * CHB;              // row tile of one chunk
   static constexpr int STAGE = RBYTES + BN * CHB;
   static constexpr int SMEM = NSTAGE * STAGE;
+  // 256-row tiles: after the ring, each wave's admission queue (64 blocks of
+  // 16 float32 accumulators, then 64 block tags)
+  static constexpr int QBYTES = BMT == 256 ? NT * 16 * 4 + NT * 4 : 0;
+  static constexpr int DSMEM = SMEM + QBYTES;
   static constexpr int RPL = 1024 / CHB;               // rows per 1 KB wave load
   static constexpr int DMA_PER_WAVE = (BM + BN) / RPL / 4;
   static constexpr int RBW = BM / 64;                  // 32-row blocks per wave
@@ -490,21 +494,136 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     // flag the next tile sets
     if (ROOM && tid == 0) room_flag[(tile + 1) & 1] = 0;
 
-    // Admission.  Each entry is screened with one multiply-add and one
-    // compare against its row's threshold (and, for the cross list, its
-    // camera), and passing entries are appended at once (an LDS atomic per
-    // entry reserves the slot): after the first tiles only a few entries of
-    // a tile pass, so the cost is about two instructions per entry.  With
-    // 128-row tiles an entry that finds its buffer full is marked in the
-    // lane's lost mask; then the full buffers are compacted (lower
-    // thresholds) and only the lost entries are screened again, until none
-    // is left.  256-row tiles keep room for a whole tile instead (below).
+    // Admission.  A lane's entries come in blocks of 16 (one row, 16
+    // columns); a block whose lower bound n2_min - 2 s_max is above the row's
+    // threshold admits nothing and is dismissed with one max per entry.  The
+    // other blocks are screened entry by entry (one multiply-add and one
+    // compare against the row's threshold and, for the cross list, its
+    // camera), and passing entries are appended at once (one LDS atomic per
+    // block and list reserves the slots).
+    // 128-row tiles screen a passing block in the lane that holds it (the
+    // whole wave runs that path when one lane needs it); an entry that finds
+    // its buffer full is marked in the lane's lost mask, then the full
+    // buffers are compacted (lower thresholds) and only the lost entries are
+    // screened again, until none is left.  256-row tiles keep room for a
+    // whole tile in every buffer, and the lanes whose block passes push its
+    // 16 accumulators to a queue of the wave in LDS; the queue is then
+    // screened one block per lane, so a tile in which a few lanes of the
+    // wave pass costs one screening pass instead of one per passing block.
     {
       int lc0 = wc + 4 * half;
       asm volatile("" : "+v"(lc0));
       const uint32_t cbase = (uint32_t)(ct0 - a.c0);
       uint64_t lost[RBW][NL];
       bool near_full = false;  // room scheme: an admission of this lane passed C - BN
+      // smallest squared norm among the 16 columns of each of the lane's
+      // column blocks (padding and left-out columns carry +inf)
+      float n2min[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        float m = INFINITY;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 v = *(const f32x4*)&col_n2[lc0 + 32 * cb + 8 * g];
+          m = fminf(m, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+        }
+        n2min[cb] = m;
+      }
+      if constexpr (ROOM) {
+        static_assert(NL == 1 && PREC != GCR_PREC_FP8, "the queue scheme screens one list of float32/BF16 keys");
+        float* qv = reinterpret_cast<float*>(smem + T::SMEM) + wave * (64 * 16);
+        int* qm = reinterpret_cast<int*>(smem + T::SMEM + NT * 16 * 4) + wave * 64;
+        float thr[RBW];
+#pragma unroll
+        for (int rb2 = 0; rb2 < RBW; ++rb2) thr[rb2] = fminf(row_thr[0][wr + 32 * rb2 + l32], 3.40282347e38f);
+        // blocks still to be queued (wave-uniform): a block that does not
+        // fit in the 64 free slots of this pass waits for the next pass
+        uint32_t todo = (1u << (4 * RBW)) - 1u;
+        while (todo) {
+          int qn = 0;
+          uint32_t next = 0u;
+#pragma unroll
+          for (int rb2 = 0; rb2 < RBW; ++rb2) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              const int blk = 4 * rb2 + cb;
+              if (!(todo & (1u << blk))) continue;
+              asm volatile("" : "+a"(acc[cb][rb2]));
+              float smax = acc[cb][rb2][0];
+#pragma unroll
+              for (int i = 1; i < 16; ++i) smax = fmaxf(smax, acc[cb][rb2][i]);
+              const bool pass = fmaf(-2.0f, smax, n2min[cb]) <= thr[rb2];
+              const uint64_t b = __ballot(pass);
+              if (b == 0ull) continue;
+              const int nb = __popcll(b);
+              if (qn + nb > 64) {
+                next |= 1u << blk;
+                continue;
+              }
+              if (pass) {
+                const int slot =
+                    qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                f32x4* d = reinterpret_cast<f32x4*>(qv + slot * 16);
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                  d[g] = f32x4{acc[cb][rb2][4 * g], acc[cb][rb2][4 * g + 1], acc[cb][rb2][4 * g + 2],
+                               acc[cb][rb2][4 * g + 3]};
+                qm[slot] = rb2 | (cb << 2) | (lane << 4);
+              }
+              // (qn and todo are wave-uniform; readfirstlane keeps them in
+              // scalar registers, so the tests above are scalar branches)
+              qn = __builtin_amdgcn_readfirstlane(qn + nb);
+            }
+          }
+          todo = __builtin_amdgcn_readfirstlane(next);
+          // (LDS operations of one wave complete in order: the reads below
+          // see this pass's queue)
+          if (lane < qn) {
+            const int meta = qm[lane];
+            const int rb2 = meta & 3, cb = (meta >> 2) & 3, sl = meta >> 4;
+            const int lr = wr + 32 * rb2 + (sl & 31);
+            // entry 4 g + j of the block holds column lcb + 8 g + j of the tile
+            const int lcb = wc + 4 * (sl >> 5) + 32 * cb;
+            const float t = fminf(row_thr[0][lr], 3.40282347e38f);
+            const f32x4* src = reinterpret_cast<const f32x4*>(qv + lane * 16);
+            float keys[16];
+            uint32_t m = 0u;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              const f32x4 sv = src[g];
+              const f32x4 nv = *(const f32x4*)&col_n2[lcb + 8 * g];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                keys[4 * g + j] = fmaf(-2.0f, sv[j], nv[j]);
+                if (keys[4 * g + j] <= t) m |= 1u << (4 * g + j);
+              }
+            }
+            const int64_t ds = row0 + lr - ct0 - lcb;  // the row's own column, relative to the block
+            if (a.exclude_self && ds >= 0 && ds < 32 && (ds & 4) == 0)
+              m &= ~(1u << (4 * (int)(ds >> 3) + (int)(ds & 3)));
+            if (a.filt.row_mark) {
+#pragma unroll
+              for (int i = 0; i < 16; ++i)
+                if (row_out(row_mk[lr], row_stp[lr], ct0 + lcb + 8 * (i >> 2) + (i & 3))) m &= ~(1u << i);
+            }
+            if (m != 0u) {
+              dirty = true;
+              const int nm = __popc(m);
+              const int pos = atomicAdd(&row_cnt[0][lr], nm);
+              near_full |= pos + nm > a.C - BN;
+              uint64_t* buf = a.cand + ((rrel0 + lr) * NL * (int64_t)a.S + cs) * a.C;
+              const uint32_t cbv = cbase + (uint32_t)lcb;
+#pragma unroll
+              for (int i = 0; i < 16; ++i) {
+                if (m & (1u << i)) {
+                  const int q = pos + __popc(m & ((1u << i) - 1u));
+                  if (q < a.C) buf[q] = pack_cand(keys[i], cbv + (uint32_t)(8 * (i >> 2) + (i & 3)));
+                }
+              }
+            }
+          }
+        }
+      } else
 #pragma unroll
       for (int rb2 = 0; rb2 < RBW; ++rb2) {
         const int lr = wr + 32 * rb2 + l32;
@@ -532,6 +651,19 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         const float tmax = NL > 1 ? fmaxf(t0, t1) : t0;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
+          // the block's accumulators are read here and not earlier (an
+          // early copy of all of them would not fit in the registers)
+          asm volatile("" : "+a"(acc[cb][rb2]));
+          if constexpr (PREC != GCR_PREC_FP8) {
+            // n2_min - 2 s_max bounds every key of the block from below
+            // (fma with one rounding is monotone in both operands), so a
+            // block whose bound is above the threshold admits nothing: one
+            // max per entry instead of a key and a min
+            float smax = acc[cb][rb2][0];
+#pragma unroll
+            for (int i = 1; i < 16; ++i) smax = fmaxf(smax, acc[cb][rb2][i]);
+            if (!(fmaf(-2.0f, smax, n2min[cb]) <= tmax)) continue;
+          }
           f32x4 n2v[4], scv[4];
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
@@ -541,9 +673,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
           }
           float keys[16];
           float kmin = INFINITY;
-          // the block's accumulators are read here and not earlier (an
-          // early copy of all of them would not fit in the registers)
-          asm volatile("" : "+a"(acc[cb][rb2]));
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             float sv = acc[cb][rb2][i];
@@ -552,30 +681,55 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
             keys[i] = fmaf(-2.0f, sv, n2v[i >> 2][i & 3]);
             kmin = fminf(kmin, keys[i]);
           }
-          if (!(kmin <= tmax)) continue;
+          if (PREC == GCR_PREC_FP8 && !(kmin <= tmax)) continue;
           dirty = true;
           i32x4 camv[4];
           if (NL > 1) {
 #pragma unroll
             for (int g = 0; g < 4; ++g) camv[g] = *(const i32x4*)&col_cam[lc0 + 32 * cb + 8 * g];
           }
+          // the block's admissions to each list as a 16-bit mask; one LDS
+          // atomic per list reserves their slots, which they take in order
+          uint32_t m0 = 0, m1 = 0;
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            const float key = keys[i];
-            const int lc = lc0 + 32 * cb + 8 * (i >> 2) + (i & 3);
-            const uint64_t bit = 1ull << (cb * 16 + i);
-            if (key <= t0 && lc != selfc && !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
-              const int pos = atomicAdd(&row_cnt[0][lr], 1);
-              if (pos < a.C) buf0[pos] = pack_cand(key, cbase + (uint32_t)lc);
-              else if constexpr (!ROOM) lost[rb2][0] |= bit;
-              if constexpr (ROOM) near_full |= pos >= a.C - BN;
+            if (keys[i] <= t0) m0 |= 1u << i;
+            if (NL > 1 && camv[i >> 2][i & 3] != rc && keys[i] <= t1) m1 |= 1u << i;
+          }
+          // the row's own column (entry 4 g + j holds column lc0 + 32 cb + 8 g + j)
+          const int ds = selfc - (lc0 + 32 * cb);
+          if (ds >= 0 && ds < 32 && (ds & 4) == 0) {
+            const uint32_t keep = ~(1u << (4 * (ds >> 3) + (ds & 3)));
+            m0 &= keep;
+            m1 &= keep;
+          }
+          if (a.filt.row_mark) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              if (row_out(row_mk[lr], row_stp[lr], ct0 + lc0 + 32 * cb + 8 * (i >> 2) + (i & 3))) {
+                m0 &= ~(1u << i);
+                m1 &= ~(1u << i);
+              }
             }
-            if (NL > 1 && camv[i >> 2][i & 3] != rc && key <= t1 && lc != selfc &&
-                !(a.filt.row_mark && row_out(row_mk[lr], row_stp[lr], ct0 + lc))) {
-              const int pos = atomicAdd(&row_cnt[NL - 1][lr], 1);
-              if (pos < a.C) buf1[pos] = pack_cand(key, cbase + (uint32_t)lc);
-              else if constexpr (!ROOM) lost[rb2][NL - 1] |= bit;
-              if constexpr (ROOM) near_full |= pos >= a.C - BN;
+          }
+#pragma unroll
+          for (int L = 0; L < NL; ++L) {
+            const uint32_t m = L == 0 ? m0 : m1;
+            if (m == 0u) continue;
+            const int nm = __popc(m);
+            const int pos = atomicAdd(&row_cnt[L][lr], nm);
+            uint64_t* buf = L == 0 ? buf0 : buf1;
+            // (the entries are packed after the atomic returns, not before it
+            // with sixteen more registers live)
+            uint32_t cbv = cbase + (uint32_t)(lc0 + 32 * cb);
+            asm volatile("" : "+v"(cbv) : "v"(pos));
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              if (m & (1u << i)) {
+                const int q = pos + __popc(m & ((1u << i) - 1u));
+                if (q < a.C) buf[q] = pack_cand(keys[i], cbv + (uint32_t)(8 * (i >> 2) + (i & 3)));
+                else lost[rb2][L] |= 1ull << (cb * 16 + i);
+              }
             }
           }
         }
@@ -701,8 +855,8 @@ template <int PREC, int NL, int E, int BMT>
 static void launch_one(const SimArgs& a, hipStream_t st) {
   const dim3 grid(a.balanced ? a.grid : sim_topk_grid(a.RB, a.S)), block(NT);
   auto k = sim_topk_kernel<PREC, NL, E, BMT>;
-  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, Tile<BMT>::SMEM);
-  hipLaunchKernelGGL(k, grid, block, Tile<BMT>::SMEM, st, a);
+  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, Tile<BMT>::DSMEM);
+  hipLaunchKernelGGL(k, grid, block, Tile<BMT>::DSMEM, st, a);
 }
 
 template <int PREC, int NL, int BMT>
