@@ -41,6 +41,8 @@ constexpr int BN = 256, NT = 256;
 constexpr int waitcnt_vm(int n) { return 0xF70 | (n & 0xF) | (((n >> 4) & 3) << 14); }
 // ... and for lgkmcnt == 0 (this wave's LDS reads have returned)
 constexpr int waitcnt_vm_lgkm0(int n) { return 0x070 | (n & 0xF) | (((n >> 4) & 3) << 14); }
+// lgkmcnt == 0 only
+constexpr int waitcnt_lgkm0 = 0xC07F;
 
 // Workgroup tiles.  BMT = 128: 128 rows x 256 columns (waves of 64 x 128),
 // 128-byte chunks of the feature dimension in a 3-stage ring (144 KB).
@@ -62,7 +64,10 @@ struct Tile {
   // 256-row tiles: after the ring, each wave's admission queue (64 blocks of
   // 16 float32 accumulators, then 64 block tags)
   static constexpr int QBYTES = BMT == 256 ? NT * 16 * 4 + NT * 4 : 0;
-  static constexpr int DSMEM = SMEM + QBYTES;
+  // then the tile's column data (norms, FP8 scales, cameras, stamps) and the
+  // thresholds other splits published for the rows (up to two lists)
+  static constexpr int COLBYTES = 4 * BN * 4 + 2 * BM * 4;
+  static constexpr int DSMEM = SMEM + QBYTES + COLBYTES;
   static constexpr int RPL = 1024 / CHB;               // rows per 1 KB wave load
   static constexpr int DMA_PER_WAVE = (BM + BN) / RPL / 4;
   static constexpr int RBW = BM / 64;                  // 32-row blocks per wave
@@ -205,6 +210,17 @@ __device__ __forceinline__ void frag_mma(const Frag<PREC, RBW>& f, f32x16 (&acc)
   }
 }
 
+// LDS fetch-and-add with its wait in the same block.  (Written as a C++
+// atomic, it makes the compiler wait first for every load in flight, those
+// of the operand ring included, because direct-to-LDS loads count there.)
+typedef int __attribute__((address_space(3)))* lds_i32_ptr;
+__device__ __forceinline__ int lds_fetch_add(int* p, int v) {
+  const uint32_t a = (uint32_t)(uintptr_t)(lds_i32_ptr)p;
+  int r;
+  asm volatile("ds_add_rtn_u32 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(a), "v"(v) : "memory");
+  return r;
+}
+
 // A serving row's own mask: column c is left out when its stamp matches.
 __device__ __forceinline__ bool row_out(const uint32_t* mk, uint32_t stamp, int64_t c) {
   return mk && mk[c] == stamp;
@@ -287,9 +303,14 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
   // compaction: the accumulators are then read once, in the admission.
   constexpr bool ROOM = BMT == 256;
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ __align__(16) float col_n2[BN];
-  __shared__ __align__(16) float col_sc[BN];
-  __shared__ __align__(16) int col_cam[BN];
+  // column data of the tile and the row thresholds other splits published,
+  // copied straight into LDS (see the chunk loop)
+  float* const col_n2 = reinterpret_cast<float*>(smem + T::SMEM + T::QBYTES);
+  float* const col_sc = col_n2 + BN;
+  int* const col_cam = reinterpret_cast<int*>(col_n2 + 2 * BN);
+  uint32_t* const col_stamp = reinterpret_cast<uint32_t*>(col_n2 + 3 * BN);
+  uint32_t* const sh_thr = reinterpret_cast<uint32_t*>(col_n2 + 4 * BN);
+  static_assert(NL <= 2, "two lists at most");
   __shared__ float row_thr[NL][BM];
   __shared__ int row_cnt[NL][BM];
   __shared__ float row_twoE[BM], row_sc[BM];
@@ -350,6 +371,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     any_flag[tid] = 0;
     room_flag[tid] = 0;
   }
+  if (NL > 1 && !a.cam) col_cam[tid] = 0;  // (NT == BN; never loaded then)
   for (int t = tid; t < BM; t += NT) {
     const int64_t r = row0 + t;
     const bool rv = r < a.r1;
@@ -403,10 +425,11 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
 
   constexpr int NSTEP = steps_per_chunk<PREC, BMT>();
   Frag<PREC, RBW> f[2];
-  // The vector-memory counter also counts the epilogue's candidate stores,
-  // which may complete out of order with the loads: after a wave has stored
-  // (or compacted), its next ring wait drains everything.
-  bool dirty = false;
+  // The vector-memory counter also counts the epilogue's candidate stores
+  // and the column-data loads.  Loads return in the order they were issued,
+  // so once at most the (NSTAGE - 2) * DMA ops issued after chunk g + 1's
+  // loads are pending, chunk g + 1 has landed whatever else was issued in
+  // between (other ops only make the wait longer).
   if (total > 0) {
 #pragma unroll
     for (int i = 0; i < NSTAGE; ++i) issue();
@@ -424,12 +447,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       for (int rb2 = 0; rb2 < RBW; ++rb2)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[cb][rb2][i] = 0.f;
-    float pf_n2 = INFINITY, pf_sc = 1.0f;
-    int pf_cam = 0;
-    uint32_t pf_stamp = 0u;
-    uint32_t pf_sh[SH];  // shared thresholds of (row, list) tid + NT j (ordered bits)
-#pragma unroll
-    for (int j = 0; j < SH; ++j) pf_sh[j] = 0xffffffffu;
     for (int ch = 0; ch < kch; ++ch, ++g) {
       const uint8_t* S = smem + gs * STAGE;
       const int gn = gs + 1 == NSTAGE ? 0 : gs + 1;
@@ -440,32 +457,53 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         } else {
           // Every fragment of chunk g has reached the registers (lgkmcnt
           // 0), and chunk g + 1 has landed once at most the loads of the
-          // NSTAGE - 2 chunks issued after it are pending (all loads, after
-          // a store); the barrier then makes chunk g + 1 visible and frees
+          // NSTAGE - 2 chunks issued after it are pending; the barrier then
+          // makes chunk g + 1 visible and frees
           // stage gs, which receives chunk g + NSTAGE while the last step's
           // MFMAs run.
-          if (ch == 0 && __any(dirty)) __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-          else __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * DMA));
+          __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * DMA));
           asm volatile("s_barrier" ::: "memory");
-          issue();
           if (ch == 0) {
-            dirty = false;
-            // column data of this tile for the epilogue
-            const int64_t c = ct0 + tid;  // NT == BN
-            if (c < sc1) {
-              pf_n2 = a.n2[c];
-              if (a.cam) pf_cam = a.cam[c];
-              if (PREC == GCR_PREC_FP8) pf_sc = a.scale[c];
-              if (a.filt.stamp_of) pf_stamp = a.filt.stamp_of[c];
-            }
-            if (a.thr_shared) {
+            // Column data of this tile for the epilogue (every wave is past
+            // the previous epilogue), copied into LDS ahead of chunk
+            // g + NSTAGE: the ring wait that guarantees that chunk at step
+            // NSTAGE - 1 of the tile guarantees these too, and no register
+            // waits for them (a register load would make the epilogue wait
+            // for every load in flight).  One 1 KB load per array; the
+            // shared thresholds in 256-byte pieces.
+            // (reads past an array's end return zero; the byte offsets are
+            // in the per-lane offset, which the descriptor's range checks;
+            // the norms and scales have npad entries, a multiple of 128)
+            const int cv = (int)(ct0 * 4) + lane * 16;
+            if (wave == 0) {
+              gcr_buffer_load_lds(make_res(a.n2, (uint64_t)a.npad * 4), (lds_u32_ptr)col_n2, 16, cv, 0, 0, 0);
+            } else if (wave == 1) {
+              // (arrays that may end at column c1: 4-byte loads, so the range
+              // check drops exactly the columns past it)
+              const int cw = (int)(ct0 * 4) + lane * 4;
+              if (a.filt.stamp_of) {
+                const i32x4 rs = make_res(a.filt.stamp_of, (uint64_t)a.c1 * 4);
 #pragma unroll
-              for (int j = 0; j < SH; ++j) {
-                const int e = tid + NT * j;
-                if (e < BM * NL && row0 + (e % BM) < a.r1) pf_sh[j] = a.thr_shared[(rrel0 + e % BM) * NL + e / BM];
+                for (int i = 0; i < 4; ++i)
+                  gcr_buffer_load_lds(rs, (lds_u32_ptr)(col_stamp + 64 * i), 4, cw + 256 * i, 0, 0, 0);
               }
+              if (NL > 1 && a.cam) {
+                const i32x4 rc = make_res(a.cam, (uint64_t)a.c1 * 4);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  gcr_buffer_load_lds(rc, (lds_u32_ptr)(col_cam + 64 * i), 4, cw + 256 * i, 0, 0, 0);
+              }
+            } else if (wave == 2) {
+              if (PREC == GCR_PREC_FP8)
+                gcr_buffer_load_lds(make_res(a.scale, (uint64_t)a.npad * 4), (lds_u32_ptr)col_sc, 16, cv, 0, 0, 0);
+            } else if (a.thr_shared) {
+              const i32x4 rt = make_res(a.thr_shared, (uint64_t)(a.r1 - a.r0) * NL * 4);
+#pragma unroll
+              for (int i = 0; i < BM * NL / 64; ++i)
+                gcr_buffer_load_lds(rt, (lds_u32_ptr)(sh_thr + 64 * i), 4, (int)((rrel0 * NL + 64 * i + lane) * 4), 0, 0, 0);
             }
           }
+          issue();
           frag_load<PREC, BMT>(f[(q + 1) & 1], smem + gn * STAGE, 0, wr, wc, lane);
         }
         frag_mma<PREC>(f[q & 1], acc);
@@ -473,23 +511,32 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
       gs = gn;
     }
 
-    // ---------------- epilogue of one 128 x 256 tile ----------------
-    col_n2[tid] = (a.filt.stamp_of && pf_stamp == a.filt.stamp) ? INFINITY : pf_n2;
-    col_cam[tid] = pf_cam;
-    col_sc[tid] = pf_sc;
+    // ---------------- epilogue of one tile ----------------
+    // (with fewer than NSTAGE chunks per tile the column data may still be
+    // in flight)
+    if (kch < NSTAGE) {
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+      __syncthreads();
+    }
+    // padding columns and left-out columns get an infinite norm
+    if (ct0 + tid >= sc1 || (a.filt.stamp_of && col_stamp[tid] == a.filt.stamp)) col_n2[tid] = INFINITY;
     // adopt the row's threshold published by the other splits of the row
-    // (every split's k-th key + 2E bounds the row's k-th key + 2E from above)
+    // (every split's k-th key + 2E bounds the row's k-th key + 2E from above;
+    // all ones: none yet)
     if (a.thr_shared) {
 #pragma unroll
       for (int j = 0; j < SH; ++j) {
-        const int e = tid + NT * j;
-        if (e < BM * NL && pf_sh[j] != 0xffffffffu) {
-          float& t = row_thr[e / BM][e % BM];
-          t = fminf(t, unord_f32(pf_sh[j]));
+        const int e = tid + NT * j;  // (row, list) = (e / NL, e % NL)
+        if (e < BM * NL && row0 + e / NL < a.r1 && sh_thr[e] != 0xffffffffu) {
+          float& t = row_thr[e % NL][e / NL];
+          t = fminf(t, unord_f32(sh_thr[e]));
         }
       }
     }
-    __syncthreads();
+    // (a plain barrier after this wave's LDS writes: a full __syncthreads
+    // would also wait for the next chunks' loads, which write LDS)
+    __builtin_amdgcn_s_waitcnt(waitcnt_lgkm0);
+    asm volatile("s_barrier" ::: "memory");
     // every wave read the flag of tile - 1 before this barrier; it is the
     // flag the next tile sets
     if (ROOM && tid == 0) room_flag[(tile + 1) & 1] = 0;
@@ -607,9 +654,8 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
                 if (row_out(row_mk[lr], row_stp[lr], ct0 + lcb + 8 * (i >> 2) + (i & 3))) m &= ~(1u << i);
             }
             if (m != 0u) {
-              dirty = true;
-              const int nm = __popc(m);
-              const int pos = atomicAdd(&row_cnt[0][lr], nm);
+                const int nm = __popc(m);
+              const int pos = lds_fetch_add(&row_cnt[0][lr], nm);
               near_full |= pos + nm > a.C - BN;
               uint64_t* buf = a.cand + ((rrel0 + lr) * NL * (int64_t)a.S + cs) * a.C;
               const uint32_t cbv = cbase + (uint32_t)lcb;
@@ -682,7 +728,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
             kmin = fminf(kmin, keys[i]);
           }
           if (PREC == GCR_PREC_FP8 && !(kmin <= tmax)) continue;
-          dirty = true;
           i32x4 camv[4];
           if (NL > 1) {
 #pragma unroll
@@ -717,7 +762,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
             const uint32_t m = L == 0 ? m0 : m1;
             if (m == 0u) continue;
             const int nm = __popc(m);
-            const int pos = atomicAdd(&row_cnt[L][lr], nm);
+            const int pos = lds_fetch_add(&row_cnt[L][lr], nm);
             uint64_t* buf = L == 0 ? buf0 : buf1;
             // (the entries are packed after the atomic returns, not before it
             // with sixteen more registers live)
@@ -751,7 +796,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
           const int kk = L == 0 ? a.k0 : a.k1;
           const int n = row_cnt[L][lr];
           if (kk > 0 && (n > a.C - BN || (tile == 0 && n >= kk))) {
-            dirty = true;
             uint64_t* base = a.cand + (((rrel0 + lr) * NL + L) * (int64_t)a.S + cs) * a.C;
             compact_row<E>(base, &row_cnt[L][lr], &row_thr[L][lr], a.C, kk, row_twoE[lr], BN);
             if (a.thr_shared && lane == 0)
@@ -770,8 +814,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
         const int more = any_flag[it & 1];
         if (tid == 0) any_flag[(it + 1) & 1] = 0;
         if (!more) break;
-        dirty = true;
-        // compact the full buffers (a count past C counts lost entries too)
+          // compact the full buffers (a count past C counts lost entries too)
         for (int q = wave; q < NL * BM; q += NT / 64) {
           const int L = q / BM, lr = q - L * BM;
           if (row_cnt[L][lr] >= a.C) {
@@ -823,7 +866,6 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
     if (!ROOM && tile == 0) {
       // set every row's threshold from its first tile instead of waiting
       // for its buffer to fill
-      dirty = true;
       for (int q = wave; q < NL * BM; q += NT / 64) {
         const int L = q / BM, lr = q - L * BM;
         const int kk = L == 0 ? a.k0 : a.k1;
