@@ -654,7 +654,7 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
                 if (row_out(row_mk[lr], row_stp[lr], ct0 + lcb + 8 * (i >> 2) + (i & 3))) m &= ~(1u << i);
             }
             if (m != 0u) {
-                const int nm = __popc(m);
+              const int nm = __popc(m);
               const int pos = lds_fetch_add(&row_cnt[0][lr], nm);
               near_full |= pos + nm > a.C - BN;
               uint64_t* buf = a.cand + ((rrel0 + lr) * NL * (int64_t)a.S + cs) * a.C;
