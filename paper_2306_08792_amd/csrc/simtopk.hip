@@ -3,20 +3,24 @@
 // The k-nearest-neighbour sets of Eq. (4) (and the cross-camera sets of
 // Eq. (8)) need, for every row i, the k smallest ||x_i - x_j||^2.  For a
 // fixed row this ranks columns by the key n2_j - 2 <x_i, x_j>.  Each work-
-// group owns 128 rows and sweeps one column split in 256-column tiles; a tile
-// of similarities is an MFMA GEMM over the feature dimension (float32,
-// bfloat16 or FP8-E4M3 operands, float32 accumulation) and never leaves the
-// registers.  Its epilogue screens every score against the row's running
-// admission threshold and appends survivors to the row's candidate buffer
-// (global memory, one region per row/list/split).
+// group owns 128 rows (256 for sweeps of one list over many row blocks) and
+// sweeps a range of 256-column tiles; a tile of similarities is an MFMA GEMM
+// over the feature dimension (float32, bfloat16 or FP8-E4M3 operands,
+// float32 accumulation) and never leaves the registers.  Its epilogue
+// screens every score against the row's running admission threshold and
+// appends survivors to the row's candidate buffer (global memory, one region
+// per row/list/split).
 //
-// Data movement: the feature dimension is consumed in 128-byte chunks.  Each
-// chunk of the 128-row tile and of the 256-column tile is copied straight
-// from global memory into LDS by buffer loads with an LDS destination
-// (16 bytes per lane, no register staging), through a 3-stage ring so two
-// chunks are in flight while a third is multiplied.  Rows are XOR-swizzled in
-// 16-byte units inside LDS so that fragment reads are free of bank conflicts.
-// Out-of-range reads return zero through the buffer descriptor's range.
+// Data movement: the feature dimension is consumed in chunks (128 bytes per
+// row, in a 3-stage ring, for 128-row tiles; 64 bytes in a 4-stage ring for
+// 256-row tiles).  Each chunk of the row tile and of the column tile is
+// copied straight from global memory into LDS by buffer loads with an LDS
+// destination (16 bytes per lane, no register staging), so NSTAGE - 1
+// chunks are in flight while one is multiplied.  Rows are XOR-swizzled in
+// 16-byte units inside LDS so that fragment reads are free of bank
+// conflicts.  The column data the epilogue needs comes into LDS the same
+// way, so no step waits for more than the ring's own next chunk.  Out-of-
+// range reads return zero through the buffer descriptor's range.
 //
 // Admission rule.  Let E_i bound |screened key - exact key| (screen_margin)
 // and tau_i be the k-th smallest screened key the buffer has seen.  A column
