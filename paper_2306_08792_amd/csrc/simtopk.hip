@@ -663,12 +663,17 @@ __global__ __launch_bounds__(NT, 1) void sim_topk_kernel(SimArgs a) {
               near_full |= pos + nm > a.C - BN;
               uint64_t* buf = a.cand + ((rrel0 + lr) * NL * (int64_t)a.S + cs) * a.C;
               const uint32_t cbv = cbase + (uint32_t)lcb;
-#pragma unroll
-              for (int i = 0; i < 16; ++i) {
-                if (m & (1u << i)) {
-                  const int q = pos + __popc(m & ((1u << i) - 1u));
-                  if (q < a.C) buf[q] = pack_cand(keys[i], cbv + (uint32_t)(8 * (i >> 2) + (i & 3)));
-                }
+              // store step j writes each lane's j-th admitted entry (its key
+              // recomputed from the queued accumulator), so a pass issues as
+              // many store instructions as the most entries one lane admits
+              // rather than one per entry index that some lane admits
+              uint32_t mm = m;
+              for (int q = pos; mm != 0u; ++q) {
+                const int i = __builtin_ctz(mm);
+                mm &= mm - 1u;
+                const int lc = lcb + 8 * (i >> 2) + (i & 3);
+                const float key = fmaf(-2.0f, qv[lane * 16 + i], col_n2[lc]);
+                if (q < a.C) buf[q] = pack_cand(key, cbase + (uint32_t)lc);
               }
             }
           }
